@@ -1,0 +1,247 @@
+"""Benchmark of the multidirect-forcing IB step on one MI355X.
+
+One step is the whole forward hot path on the 1000-sphere 256^3 workload:
+marker build (a1), bucketing (a2), desired velocity and the N_s = 5
+multidirect iterations with finalization (a3-a9), and the per-particle
+reductions (a10), FP32 fields with FP64 positions and sums, inputs resident in
+HBM, no host synchronization inside the step.  Prints one JSON line.
+
+Beside the headline value it reports the loop alone, the plain FP64 path on
+the same inputs, a per-kernel breakdown from the library's event profiler, the
+dominant kernel's roofline, the adjoint (a11) on the 64-sphere 128^3 workload,
+and the FP64 oracle timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def support_cells(level, b, delta):
+    """Number of distinct cells in the union of all marker stencils."""
+    import torch
+    n = torch.tensor(level.n, device=b.base.device, dtype=torch.int64)
+    base = b.base.to(torch.int64)
+    o = torch.arange(delta, device=base.device)
+    cx = (base[:, 0, None] + o[None, :]) % n[0]
+    cy = (base[:, 1, None] + o[None, :]) % n[1]
+    cz = (base[:, 2, None] + o[None, :]) % n[2]
+    lin = (cx[:, None, None, :] + n[0] * (cy[:, None, :, None] + n[1] * cz[:, :, None, None]))
+    return int(torch.unique(lin.reshape(-1)).numel())
+
+
+def model_bytes(kind, s, P, N, S, A, C):
+    """Compulsory bytes of one launch of a batched-path kernel class.
+
+    N markers, S source-list entries, A active tiles (512 cells each), C
+    support cells, s field bytes.  Marker records: stencil base 12 B, weights
+    3P*s, dV/h^3 s, U^d / D / F 3s each."""
+    rec = 12 + 3 * P * s
+    if kind == "interp_u0":
+        return 3 * s * C + N * (rec + 3 * s + 6 * s)
+    if kind == "spread":
+        return N * (rec + s + 3 * s) + 4 * S + 3 * s * 512 * A
+    if kind == "interp_g":
+        return 3 * s * 512 * A + N * (rec + 3 * s + 3 * s + 3 * s)
+    if kind == "spread_final":
+        return N * (rec + s + 3 * s) + 4 * S + 3 * 3 * s * 512 * A
+    return None
+
+
+def main():
+    if "--gpus" in sys.argv:
+        i = sys.argv.index("--gpus")
+        if i + 1 < len(sys.argv) and sys.argv[i + 1] != "1":
+            print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+                  "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+            sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()          # default priority; graph capture needs a real stream
+    with torch.cuda.stream(stream):
+        run()
+
+
+def run():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--bucket-width", type=int, default=0)
+    ap.add_argument("--spread-wgs", type=int, default=0)
+    args = ap.parse_args()
+
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    wl = W.config(3, args.seed)
+    log(f"workload {wl.name}: {wl.npart} spheres, {wl.level.nbox} boxes, gen {time.time()-t0:.1f}s")
+    lev = wl.level
+    P, ns, dt = wl.delta, wl.ns, wl.dt
+    dl = ibx.device_level(lev, dev)
+    parts = ibx.particles(wl.xc, wl.d, wl.up, wl.om, dev)
+    m = ibx.build_markers(dl, parts)
+    b = ibx.bucket(dl, m, P)
+    torch.cuda.synchronize()
+    N = m.nl
+    assert int(b.flag[0].item()) == 0 and int(b.flag[1].item()) == 0
+    S = b.nsrc()
+    act = (b.src_offs[1:] > b.src_offs[:-1])
+    A = int(act.sum().item())
+    C = support_cells(dl, b, P)
+    log(f"markers {N}, source entries {S}, active tiles {A}, support cells {C}")
+
+    u_host = W.to_boxes(wl.u0, lev, fill=0.0)
+    u32 = torch.as_tensor(u_host, device=dev).to(torch.float32)
+    f32 = torch.zeros_like(u32)
+    F32 = torch.zeros((N, 3), dtype=torch.float32, device=dev)
+    plan = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, bucket_width=args.bucket_width,
+                    spread_wgs_per_cu=args.spread_wgs, use_graph=True)
+    red = torch.zeros((wl.npart, 12), dtype=torch.float64, device=dev)
+
+    def step():
+        ibx.build_markers_into(dl, parts, m)
+        ibx.bucket_into(dl, m, P, b)
+        plan.multidirect_force(dl, parts, m, b, ns, dt, u32, ustar=u32, f=f32, F=F32)
+        red.copy_(ibx.particle_reductions(dl, parts, m, F32, u32))
+
+    def loop_only():
+        plan.multidirect_force(dl, parts, m, b, ns, dt, u32, ustar=u32, f=f32, F=F32)
+
+    def timed(fn, k):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(k):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / k
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warm")
+    ms_step = timed(step, args.steps)
+    ms_loop = timed(loop_only, args.steps)
+    log(f"step {ms_step:.3f} ms, loop {ms_loop:.3f} ms")
+
+    # per-kernel breakdown over the same number of loops, events on the launch stream
+    plan.profile(True)
+    for _ in range(args.steps):
+        loop_only()
+    prof = plan.profile_read(reset=True)
+    plan.profile(False)
+    kern = {k: {"ms_total": v[0], "calls": v[1], "avg_us": 1e3 * v[0] / v[1]}
+            for k, v in prof.items() if v[1] > 0}
+    dom = max(kern, key=lambda k: kern[k]["ms_total"])
+    nb = model_bytes(dom, 4, P, N, S, A, C)
+    avg_s = kern[dom]["avg_us"] * 1e-6
+    achieved = nb / avg_s / 1e9 if nb else None
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": None, "bytes_per_launch": nb, "avg_launch_us": kern[dom]["avg_us"]}
+    log(f"kernels {json.dumps(kern)}")
+
+    # SURVEY-style loop byte model: per iteration u0 on C + 60 B per marker, plus final writes
+    bmodel = ns * (3 * 4 * C + N * 60) + 6 * 4 * C
+    out = {
+        "metric": "marker-iters/s of the multidirect IB step (FP32 batched)",
+        "value": N * ns / (ms_step * 1e-3),
+        "unit": "marker-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "spheres1000_256: 1000 polydisperse spheres (D/h lognormal, "
+                               "median 16, sigma 0.3, clipped [8,32]) in a periodic 256^3 grid "
+                               "of 32^3 boxes, 4-point delta, N_s=5, dt=h/2",
+                   "markers": N, "ns": ns, "seed": args.seed,
+                   "steps_cover": "a1 markers, a2 bucket, a3-a9 loop, a10 reductions"},
+        "loop_ms": ms_loop,
+        "loop_marker_iters_per_s": N * ns / (ms_loop * 1e-3),
+        "loop_model_gbs": bmodel / (ms_loop * 1e-3) / 1e9,
+        "loop_model_bytes": bmodel,
+        "roofline": roofline,
+        "kernels": kern,
+    }
+
+    if not args.no_plain:
+        u64 = torch.as_tensor(u_host, device=dev)
+        us64 = torch.zeros_like(u64)
+        f64 = torch.zeros_like(u64)
+        F64 = torch.zeros((N, 3), dtype=torch.float64, device=dev)
+        plan64 = ibx.Plan(P, torch.float64, ibx.IB_PATH_PLAIN)
+
+        def plain64():
+            plan64.multidirect_force(dl, parts, m, b, ns, dt, u64, ustar=us64, f=f64, F=F64)
+
+        plain64()
+        ms64 = timed(plain64, max(2, args.steps // 5))
+        out["fp64_plain_loop_ms"] = ms64
+        out["speedup_fp32_batched_vs_fp64_plain"] = ms64 / ms_loop
+        log(f"fp64 plain loop {ms64:.3f} ms")
+        del u64, us64, f64, F64
+
+    if not args.no_backward:
+        wl5 = W.config(5, args.seed)
+        dl5 = ibx.device_level(wl5.level, dev)
+        p5 = ibx.particles(wl5.xc, wl5.d, wl5.up, wl5.om, dev)
+        m5 = ibx.build_markers(dl5, p5)
+        b5 = ibx.bucket(dl5, m5, wl5.delta)
+        u5 = torch.as_tensor(W.to_boxes(wl5.u0, wl5.level, fill=0.0), device=dev).float()
+        pl5 = ibx.Plan(wl5.delta, torch.float32, ibx.IB_PATH_BATCHED)
+        Fh = torch.zeros((wl5.ns, m5.nl, 3), dtype=torch.float32, device=dev)
+        _, f5, F5 = pl5.multidirect_force(dl5, p5, m5, b5, wl5.ns, wl5.dt, u5, Fhist=Fh)
+        gF = torch.ones_like(F5)
+
+        def bwd():
+            pl5.backward(dl5, p5, m5, b5, wl5.ns, wl5.dt, u5, Fh, g_f=f5, g_F=gF)
+
+        bwd()
+        out["backward_spheres64_128_fp32_ms"] = timed(bwd, 3)
+        log(f"backward {out['backward_spheres64_128_fp32_ms']:.3f} ms")
+
+    if not args.no_cpu_baseline:
+        import oracle as O
+        mo = O.build_markers(wl.xc, wl.d, lev.h)
+        t = time.perf_counter()
+        O.multidirect(O.grid_of(lev), P, ns, dt, mo, wl.xc, wl.up, wl.om, wl.u0,
+                      residuals=False)
+        el = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": mo.nl * ns / el, "unit": "marker-iters/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"the full workload's loop (a3-a9, {mo.nl} markers, "
+                                         f"N_s={ns}) in the FP64 C oracle, one thread, "
+                                         f"{el:.1f} s"}
+        log(f"oracle loop {el:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

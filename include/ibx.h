@@ -1,0 +1,259 @@
+/*
+ * ibx.h -- C ABI of libibx, the multidirect-forcing immersed-boundary (IB)
+ * loop of arXiv 2408.14140 (IAMReX) on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Memory:  every buffer is allocated and owned by the caller.  "device"
+ *          pointers are HIP device allocations on the current device, "host"
+ *          pointers are ordinary host memory.  The library allocates device
+ *          memory only inside an ib_plan (graph cache), released by
+ *          ib_plan_destroy.  Scratch memory is passed as a workspace whose
+ *          size is queried first.
+ * Streams: every call is enqueued on the given stream (hipStream_t passed as
+ *          void*, NULL = the null stream) and returns without synchronizing;
+ *          outputs are valid once the stream reaches that point.
+ * Errors:  arguments are validated on the host before anything is enqueued;
+ *          a negative ib_status is returned synchronously and nothing runs.
+ *          A failed kernel launch returns IB_EHIP (hipGetLastError text via
+ *          ib_last_hip_error).  Conditions only the device can see (a marker
+ *          stencil outside the covered boxes) are reported through device
+ *          flag words that the caller reads after synchronizing.
+ * Grid:    the finest AMR level: n[0] x n[1] x n[2] cells of edge h whose low
+ *          corner is lo (Sec. 3.1: IB markers live on the finest level only).
+ *          It is tiled into cubic boxes of `box` cells; only covered boxes
+ *          hold data.  A cell-centred field is stored per covered box as
+ *          [nbox][3][E][E][E] with E = box + 2*ngrow, x fastest; the ghost
+ *          cells are neither read nor written.  FP32 fields are float, FP64
+ *          fields double.
+ * Markers: structure of arrays in FP64 positions, contiguous per particle;
+ *          per-marker vectors (U, U^d, F) are [nl][3] in the field
+ *          precision.
+ * Kernel:  delta_h(x) h^3 = prod_d phi((X_d - x_d)/h) with phi the 3-point
+ *          kernel of Roma, Peskin & Berger (1999) or the 4-point kernel of
+ *          Peskin (2002), the two the paper cites in Sec. 3.1.  Stencil of a
+ *          marker per axis: s = (X - lo)/h, base b = floor(s) - 1 (3-point)
+ *          or floor(s - 1/2) - 1 (4-point), cells b .. b+P-1 (wrapped on
+ *          periodic axes).
+ */
+#ifndef IBX_H
+#define IBX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IB_OK = 0,
+    IB_EINVAL = -1,       /* invalid argument (null pointer, bad size or enum) */
+    IB_EDOMAIN = -2,      /* input outside the covered grid (host-detectable) */
+    IB_EWORKSPACE = -3,   /* workspace missing or smaller than required */
+    IB_EHIP = -4,         /* a HIP runtime call or kernel launch failed */
+    IB_EUNSUPPORTED = -5  /* valid but unsupported combination */
+} ib_status;
+
+typedef enum { IB_DELTA3 = 3, IB_DELTA4 = 4 } ib_delta;
+typedef enum { IB_F64 = 0, IB_F32 = 1 } ib_prec;
+typedef enum { IB_PATH_AUTO = 0, IB_PATH_PLAIN = 1, IB_PATH_BATCHED = 2 } ib_path;
+
+/* Finest level (Sec. 3.1, Algorithm 2: markers exist on level l_max only). */
+typedef struct ib_level {
+    int32_t n[3];            /* cells per axis; each a multiple of box */
+    double h;                /* cell edge, equal on all axes */
+    double lo[3];            /* physical position of the low corner of cell (0,0,0) */
+    int32_t periodic[3];     /* 1 = periodic axis, 0 = bounded axis */
+    int32_t box;             /* box edge in cells, a multiple of 8 */
+    int32_t ngrow;           /* ghost width of caller field arrays (>= 0, never read) */
+    int32_t nbox;            /* number of covered boxes */
+    const int32_t* box_lo;   /* device [nbox][3] low cell of each covered box */
+    const int32_t* box_lut;  /* device [(n0/box)(n1/box)(n2/box)] x fastest: box id or -1 */
+} ib_level;
+
+/* Rigid particles (Sec. 3.2): centroid X_r, diameter, U_r and W_r of Eq. (pr1). */
+typedef struct ib_particles {
+    int32_t np;
+    const double* xc;        /* device [np][3] */
+    const double* d;         /* device [np] */
+    const double* up;        /* device [np][3] */
+    const double* om;        /* device [np][3] */
+} ib_particles;
+
+/* Lagrangian surface markers (Sec. 3.1, Fig. 4: on the surface only). */
+typedef struct ib_markers {
+    int64_t nl;              /* total number of markers */
+    const int64_t* offs;     /* device [np+1] first marker of each particle */
+    double* x;               /* device [nl] */
+    double* y;               /* device [nl] */
+    double* z;               /* device [nl] */
+    int32_t* pid;            /* device [nl] owning particle */
+    double* dv;              /* device [np] marker volume dV of each particle */
+} ib_markers;
+
+/* Markers bucketed by owning tile (tile = 8 cells per axis). */
+typedef struct ib_buckets {
+    int32_t* cell;           /* device [nl] owning cell (wrapped), x + n0 (y + n1 z) */
+    int32_t* tileid;         /* device [nl] tile of the owning cell, x fastest */
+    int32_t* base;           /* device [nl][3] stencil base b (unwrapped) */
+    int32_t* perm;           /* device [nl] marker at each sorted position (stable) */
+    int32_t* tile_offs;      /* device [T+1] first sorted position of each tile */
+    int32_t* src_offs;       /* device [T+1] start of each tile's source list */
+    int32_t* src_idx;        /* device [src_cap] sorted positions touching each tile */
+    int64_t src_cap;         /* capacity of src_idx (8*nl always suffices) */
+    int32_t* flag;           /* device [2]: [0] markers outside coverage, [1] src overflow */
+} ib_buckets;
+
+typedef struct ib_plan ib_plan;
+
+/* ---------------------------------------------------------------------- */
+/* a1  Markers.  N_p = round(pi (D_p/h)^2) markers on an equal-area        */
+/* Fibonacci spiral of radius D_p/2 around each centroid, with             */
+/* dV_p = (pi h / 3 N_p)(3 D_p^2 + h^2), the shell of thickness h divided   */
+/* evenly.  The paper states only that markers sit on the particle surface  */
+/* at the finest level (Sec. 3.1, Fig. 4); the counts are this library's.   */
+/* ---------------------------------------------------------------------- */
+
+/* Host: offs_host[np+1] receives the running marker counts.  Returns the
+ * total count, or IB_EINVAL for np < 0, h <= 0, a null pointer or d <= 0. */
+int64_t ib_count_markers(int32_t np, const double* d_host, double h, int64_t* offs_host);
+
+/* Device: fills m->x, y, z, pid, dv from p and m->offs (copied from
+ * ib_count_markers by the caller).  Returns IB_OK, IB_EINVAL, IB_EHIP. */
+int ib_build_markers(const ib_level* lv, const ib_particles* p, const ib_markers* m,
+                     void* stream);
+
+/* a3  Desired marker velocity, Eq. (pr1): U^d_l = U_r + W_r x (X_l - X_r).
+ * Ud: device [nl][3] in precision prec. */
+int ib_desired_velocity(const ib_particles* p, const ib_markers* m, ib_prec prec, void* Ud,
+                        void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* a2  Bucketing.  Owning cell c = floor(s) per axis, tile = c / 8;        */
+/* stable counting sort of markers by tile (histogram, scan, scatter); for */
+/* every tile the ascending list of sorted positions whose stencil cells   */
+/* touch it.  Not in the paper, which treats one particle at a time        */
+/* (Sec. 3.1); integer outputs are deterministic.  flag[0] counts markers   */
+/* whose stencil leaves the covered boxes or a bounded axis; such markers   */
+/* make every later call return garbage for them.                          */
+/* ---------------------------------------------------------------------- */
+
+size_t ib_bucket_workspace(const ib_level* lv, int64_t nl);
+int ib_bucket(const ib_level* lv, const ib_markers* m, ib_delta delta, const ib_buckets* b,
+              void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* a4  Velocity interpolation, Algorithm 1 first sub-step:                  */
+/*     U_l = sum_x u(x) delta_h(x - X_l) h^3.                               */
+/* u: field in the box layout; U: device [nl][3].  One thread per marker,   */
+/* FP64 or FP32 arithmetic as prec.                                         */
+/* ---------------------------------------------------------------------- */
+int ib_interp(const ib_level* lv, const ib_markers* m, ib_delta delta, ib_prec prec,
+              const void* u, void* U, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* a6  Force spreading, Algorithm 1 third sub-step:                          */
+/*     f(x) = sum_l F_l delta_h(x - X_l) dV_l.                              */
+/* Writes f on every valid cell of every covered box (zero where no marker  */
+/* reaches).  Deterministic: each cell sums its tile's source list in       */
+/* order.  Needs the buckets of the same markers.                           */
+/* ---------------------------------------------------------------------- */
+int ib_spread(const ib_level* lv, const ib_markers* m, const ib_buckets* b, ib_delta delta,
+              ib_prec prec, const void* F, void* f, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* a3-a9  Multidirect forcing, Algorithm 1 (Sec. 3.1): with F^0 = 0 and      */
+/* u^(0) = u0, for m = 1..ns: U = J u^(m-1); F^m = F^(m-1) + (U^d - U)/dt;  */
+/* f^m = S F^m; u^(m) = u0 + dt f^m.  All markers of all particles are      */
+/* iterated together.  Outputs ustar = u^(ns) and f = f^ns on every valid   */
+/* cell of the covered boxes, F = F^ns [nl][3] (marker order).              */
+/*   ustar may equal u0 (in place) on the batched path; f may be NULL.      */
+/*   resid (device double [ns+1] or NULL) receives                          */
+/*   sqrt(sum_l dV_l |U^d_l - (J u^(m))_l|^2), m = 0..ns.                     */
+/*   Fhist (device [ns][nl][3] or NULL) receives F^1..F^ns for the adjoint. */
+/* The plan fixes kernel width, precision and path (plain: one kernel per   */
+/* sub-step, straight from global memory; batched: tile-staged LDS kernels  */
+/* fed by the buckets, ustar may alias u0).  bucket_width: markers per      */
+/* interpolation work item (64, 128 or 256; 0 = 128).  spread_wgs_per_cu:   */
+/* resident spreading workgroups per compute unit (1..32; 0 = 16).          */
+/* use_graph: replay the launch sequence from a captured hipGraph when the  */
+/* arguments repeat (batched path, non-null stream).                        */
+/* ---------------------------------------------------------------------- */
+int ib_plan_create(ib_plan** plan, ib_delta delta, ib_prec prec, ib_path path,
+                   int32_t bucket_width, int32_t spread_wgs_per_cu, int32_t use_graph);
+void ib_plan_destroy(ib_plan* plan);
+/* Current tuning of a plan: out[0] = path, out[1] = bucket_width,
+ * out[2] = spread_wgs_per_cu, out[3] = use_graph. */
+int ib_plan_query(const ib_plan* plan, int32_t* out);
+size_t ib_workspace_bytes(const ib_plan* plan, const ib_level* lv, int64_t nl, int32_t ns);
+
+/* Per-kernel timing of the batched path.  ib_plan_profile(plan, 1) makes
+ * later ib_multidirect_force calls record a pair of HIP events around each
+ * kernel launch on the caller's stream (up to 1024 launches between reads;
+ * graph replay is suspended while enabled).  ib_plan_profile_read waits for
+ * the recorded events, adds their durations per kernel class and returns the
+ * totals (milliseconds) and launch counts in arrays of IB_PROF_CLASSES
+ * entries, in the order of ib_prof_class; reset != 0 clears the totals.     */
+typedef enum {
+    IB_PROF_PREP = 0,         /* sorted marker records: stencil, weights, U^d */
+    IB_PROF_LISTS = 1,        /* work lists: per-tile items, active tiles */
+    IB_PROF_INTERP_U0 = 2,    /* interpolation of u0 and F^1 */
+    IB_PROF_SPREAD = 3,       /* spreading of F^(m-1) into the per-tile buffer */
+    IB_PROF_INTERP_G = 4,     /* interpolation of that buffer and the F update */
+    IB_PROF_SPREAD_FINAL = 5, /* spreading of F^ns into f and ustar */
+    IB_PROF_FILL = 6,         /* f = 0, ustar = u0 where no marker reaches */
+    IB_PROF_UNSORT = 7,       /* F back to marker order */
+    IB_PROF_RESID = 8,        /* residual-only interpolation */
+    IB_PROF_CLASSES = 9
+} ib_prof_class;
+int ib_plan_profile(ib_plan* plan, int32_t enable);
+int ib_plan_profile_read(ib_plan* plan, double* total_ms, int64_t* calls, int32_t reset);
+int ib_multidirect_force(ib_plan* plan, const ib_level* lv, const ib_particles* p,
+                         const ib_markers* m, const ib_buckets* b, int32_t ns, double dt,
+                         const void* u0, void* ustar, void* f, void* F, double* resid,
+                         void* Fhist, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* a10 Per-particle sums for the rigid-body update, Eqs. (particle1),       */
+/* (particle2) and (FD): out[p] = [ sum_l F_l dV (3), sum_l R_l x F_l dV (3),*/
+/* sum_x alpha_p u h^3 (3), sum_x alpha_p (x - X_p) x u h^3 (3) ] in FP64,   */
+/* alpha_p the particle volume fraction of Eq. (level-set function) from     */
+/* the eight nodal values of phi_p = |x - X_p|/(D_p/2) - 1 (Sec. 4.1).       */
+/* Raw sums: the caller applies -rho_f and the time derivatives.  F and u   */
+/* in precision prec; out: device double [np][12].  flag (device int32 or   */
+/* NULL) is set to 1 when a particle's cells leave the covered boxes.       */
+/* Deterministic: fixed-order tree reductions in FP64.                      */
+/* ---------------------------------------------------------------------- */
+int ib_particle_reductions(const ib_level* lv, const ib_particles* p, const ib_markers* m,
+                           ib_prec prec, const void* F, const void* u, double* out,
+                           int32_t* flag, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* a11 Adjoint of ib_multidirect_force (reverse sweep; S and J adjoint,     */
+/* Sec. 2).  Given Fhist from the forward call and the upstream gradients   */
+/* g_ustar (field or NULL), g_f (field or NULL) and g_F ([nl][3] or NULL),  */
+/* all in precision prec, writes g_u0 (field, precision prec), and in FP64   */
+/* g_up and g_om ([np][3]) and g_X ([nl][3], gradient with respect to the   */
+/* marker positions through phi').  Intermediate fields u^(m-1) are         */
+/* recomputed from u0 and Fhist, never stored.  ws sized by                 */
+/* ib_backward_workspace_bytes.  Runs on the plain kernels for either plan  */
+/* path.                                                                    */
+/* ---------------------------------------------------------------------- */
+size_t ib_backward_workspace_bytes(const ib_plan* plan, const ib_level* lv, int64_t nl);
+int ib_multidirect_backward(ib_plan* plan, const ib_level* lv, const ib_particles* p,
+                            const ib_markers* m, const ib_buckets* b, int32_t ns, double dt,
+                            const void* u0, const void* Fhist, const void* g_ustar,
+                            const void* g_f, const void* g_F, void* g_u0, double* g_up,
+                            double* g_om, double* g_X, void* ws, size_t ws_bytes, void* stream);
+
+/* Helpers. */
+const char* ib_status_string(int status);
+const char* ib_last_hip_error(void);
+int ib_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBX_H */

@@ -197,7 +197,7 @@ def spread(g: Grid, P: int, m: Markers, F) -> np.ndarray:
 
 
 def multidirect(g: Grid, P: int, ns: int, dt: float, m: Markers, xc, up, om, u0,
-                order: str = "jacobi", history: bool = False) -> dict:
+                order: str = "jacobi", history: bool = False, residuals: bool = True) -> dict:
     lib = _load()
     xc, up, om, u0 = _f64(xc), _f64(up), _f64(om), _f64(u0)
     ustar = np.zeros_like(u0)
@@ -210,10 +210,11 @@ def multidirect(g: Grid, P: int, ns: int, dt: float, m: Markers, xc, up, om, u0,
                              _ptr(xc), _ptr(up), _ptr(om), m.nl, _ptr(m.x), _ptr(m.y),
                              _ptr(m.z), _ptr(m.pid), _ptr(m.dv), _ptr(u0), _ptr(ustar),
                              _ptr(f), _ptr(F), _ptr(Fh),
-                             _ptr(resid) if order == "jacobi" else None)
+                             _ptr(resid) if (order == "jacobi" and residuals) else None)
     if rc:
         raise ValueError("marker stencil leaves the grid")
-    out = dict(ustar=ustar, f=f, F=F, resid=resid if order == "jacobi" else None)
+    out = dict(ustar=ustar, f=f, F=F,
+               resid=resid if (order == "jacobi" and residuals) else None)
     if history:
         out["Fhist"] = Fh
     return out

@@ -1,0 +1,375 @@
+// api.hip -- plans, workspace sizing and the multidirect entry points.
+#include <new>
+#include <stdlib.h>
+#include <string.h>
+
+#include "paths.h"
+
+struct ib_plan {
+    int P;
+    ib_prec prec;
+    ib_path path;
+    int32_t bucket_width;
+    int32_t spread_wgs_per_cu;
+    int32_t use_graph;
+    int32_t ncu;
+    // launch sequence captured for one argument set
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t key[24];
+    int has_graph;
+    ibx::Profiler* prof;
+};
+
+namespace ibx {
+
+int Profiler::init()
+{
+    for (; created < 2 * MAXP; ++created) {
+        hipError_t e = hipEventCreate(&ev[created]);
+        if (e != hipSuccess) {
+            set_hip_error(e);
+            return IB_EHIP;
+        }
+    }
+    return IB_OK;
+}
+
+void Profiler::begin(int k, hipStream_t st)
+{
+    if (n >= MAXP) {
+        ++dropped;
+        open = -1;
+        return;
+    }
+    kind[n] = k;
+    open = n;
+    (void)hipEventRecord(ev[2 * n], st);
+}
+
+void Profiler::end(hipStream_t st)
+{
+    if (open < 0)
+        return;
+    (void)hipEventRecord(ev[2 * open + 1], st);
+    n = open + 1;
+    open = -1;
+}
+
+int Profiler::collect()
+{
+    for (int i = 0; i < n; ++i) {
+        hipError_t e = hipEventSynchronize(ev[2 * i + 1]);
+        float ms = 0.f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+        if (e != hipSuccess) {
+            set_hip_error(e);
+            n = 0;
+            return IB_EHIP;
+        }
+        total_ms[kind[i]] += ms;
+        calls[kind[i]] += 1;
+    }
+    n = 0;
+    return IB_OK;
+}
+
+void Profiler::release()
+{
+    for (int i = 0; i < created; ++i)
+        (void)hipEventDestroy(ev[i]);
+    created = 0;
+}
+
+static ib_path resolved_path(const ib_plan* pl)
+{
+    if (pl->path != IB_PATH_AUTO)
+        return pl->path;
+    return pl->prec == IB_F32 ? IB_PATH_BATCHED : IB_PATH_PLAIN;
+}
+
+static BatchedCfg cfg_of(const ib_plan* pl)
+{
+    BatchedCfg c;
+    c.bw = pl->bucket_width;
+    const int waves_per_wg = pl->bucket_width / 64;
+    int per_cu = 24 / (waves_per_wg > 0 ? waves_per_wg : 1);
+    if (per_cu < 1)
+        per_cu = 1;
+    c.grid_i = pl->ncu * per_cu;
+    c.grid_s = pl->ncu * pl->spread_wgs_per_cu;
+    c.prof = pl->prof;
+    return c;
+}
+
+static void drop_graph(ib_plan* pl)
+{
+    if (pl->has_graph) {
+        (void)hipGraphExecDestroy(pl->exec);
+        (void)hipGraphDestroy(pl->graph);
+        pl->has_graph = 0;
+    }
+}
+
+}  // namespace ibx
+
+using namespace ibx;
+
+extern "C" int ib_plan_create(ib_plan** plan, ib_delta delta, ib_prec prec, ib_path path,
+                              int32_t bucket_width, int32_t spread_wgs_per_cu,
+                              int32_t use_graph)
+{
+    if (!plan || (delta != IB_DELTA3 && delta != IB_DELTA4) ||
+        (prec != IB_F32 && prec != IB_F64) ||
+        (path != IB_PATH_AUTO && path != IB_PATH_PLAIN && path != IB_PATH_BATCHED))
+        return IB_EINVAL;
+    if (bucket_width == 0)
+        bucket_width = 128;
+    if (bucket_width != 64 && bucket_width != 128 && bucket_width != 256)
+        return IB_EINVAL;
+    if (spread_wgs_per_cu == 0)
+        spread_wgs_per_cu = 16;
+    if (spread_wgs_per_cu < 1 || spread_wgs_per_cu > 32)
+        return IB_EINVAL;
+    ib_plan* pl = new (std::nothrow) ib_plan;
+    if (!pl)
+        return IB_EINVAL;
+    memset(pl, 0, sizeof(*pl));
+    pl->P = (int)delta;
+    pl->prec = prec;
+    pl->path = path;
+    pl->bucket_width = bucket_width;
+    pl->spread_wgs_per_cu = spread_wgs_per_cu;
+    pl->use_graph = use_graph ? 1 : 0;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        ncu > 0)
+        pl->ncu = ncu;
+    else
+        pl->ncu = 256;
+    *plan = pl;
+    return IB_OK;
+}
+
+extern "C" void ib_plan_destroy(ib_plan* plan)
+{
+    if (!plan)
+        return;
+    drop_graph(plan);
+    if (plan->prof) {
+        plan->prof->release();
+        delete plan->prof;
+    }
+    delete plan;
+}
+
+extern "C" int ib_plan_profile(ib_plan* plan, int32_t enable)
+{
+    if (!plan)
+        return IB_EINVAL;
+    if (enable && !plan->prof) {
+        Profiler* p = new (std::nothrow) Profiler();
+        if (!p)
+            return IB_EINVAL;
+        int rc = p->init();
+        if (rc) {
+            p->release();
+            delete p;
+            return rc;
+        }
+        plan->prof = p;
+    } else if (!enable && plan->prof) {
+        plan->prof->release();
+        delete plan->prof;
+        plan->prof = nullptr;
+    }
+    return IB_OK;
+}
+
+extern "C" int ib_plan_profile_read(ib_plan* plan, double* total_ms, int64_t* calls,
+                                    int32_t reset)
+{
+    if (!plan || !plan->prof || !total_ms || !calls)
+        return IB_EINVAL;
+    int rc = plan->prof->collect();
+    for (int k = 0; k < PK_COUNT; ++k) {
+        total_ms[k] = plan->prof->total_ms[k];
+        calls[k] = plan->prof->calls[k];
+        if (reset) {
+            plan->prof->total_ms[k] = 0.0;
+            plan->prof->calls[k] = 0;
+        }
+    }
+    return rc;
+}
+
+extern "C" int ib_plan_query(const ib_plan* plan, int32_t* out)
+{
+    if (!plan || !out)
+        return IB_EINVAL;
+    out[0] = (int32_t)resolved_path(plan);
+    out[1] = plan->bucket_width;
+    out[2] = plan->spread_wgs_per_cu;
+    out[3] = plan->use_graph;
+    return IB_OK;
+}
+
+extern "C" size_t ib_workspace_bytes(const ib_plan* plan, const ib_level* lv, int64_t nl,
+                                     int32_t ns)
+{
+    (void)ns;
+    if (!plan || check_level(lv) || nl < 0)
+        return 0;
+    Grid g = make_grid(lv);
+    if (resolved_path(plan) == IB_PATH_PLAIN)
+        return plain_workspace(g, plan->prec, nl);
+    return batched_workspace(g, plan->prec, nl, cfg_of(plan));
+}
+
+static int check_common(const ib_plan* plan, const ib_level* lv, const ib_particles* p,
+                        const ib_markers* m, const ib_buckets* b, int32_t ns, double dt)
+{
+    if (!plan)
+        return IB_EINVAL;
+    int rc = check_level(lv);
+    if (rc)
+        return rc;
+    if (!p || !m || !b || ns < 0 || ns > 1000 || !(dt > 0.0) || m->nl < 0 || p->np < 0 ||
+        m->nl > (int64_t)INT32_MAX / 8)
+        return IB_EINVAL;
+    if (m->nl > 0 && (!m->x || !m->y || !m->z || !m->pid || !m->dv || !m->offs || !p->xc ||
+                      !p->up || !p->om || !b->perm || !b->tile_offs || !b->src_offs ||
+                      !b->src_idx))
+        return IB_EINVAL;
+    return IB_OK;
+}
+
+// Launch sequence key: every argument that shapes the enqueued work.
+static void make_key(uint64_t* k, const ib_level* lv, const ib_particles* p, const ib_markers* m,
+                     const ib_buckets* b, int32_t ns, double dt, const void* u0, void* ustar,
+                     void* f, void* F, double* resid, void* Fhist, void* ws, size_t ws_bytes,
+                     void* stream)
+{
+    memset(k, 0, sizeof(uint64_t) * 24);
+    uint64_t dtb;
+    memcpy(&dtb, &dt, 8);
+    k[0] = (uint64_t)lv->n[0] | ((uint64_t)lv->n[1] << 21) | ((uint64_t)lv->n[2] << 42);
+    k[1] = (uint64_t)(uintptr_t)lv->box_lut;
+    k[2] = (uint64_t)lv->nbox | ((uint64_t)lv->box << 32);
+    memcpy(&k[3], &lv->h, 8);
+    k[4] = (uint64_t)m->nl;
+    k[5] = (uint64_t)(uintptr_t)m->x ^ ((uint64_t)(uintptr_t)m->pid << 1);
+    k[6] = (uint64_t)(uintptr_t)p->xc ^ ((uint64_t)(uintptr_t)p->up << 1);
+    k[7] = (uint64_t)(uintptr_t)b->perm ^ ((uint64_t)(uintptr_t)b->src_idx << 1);
+    k[8] = (uint64_t)ns;
+    k[9] = dtb;
+    k[10] = (uint64_t)(uintptr_t)u0;
+    k[11] = (uint64_t)(uintptr_t)ustar;
+    k[12] = (uint64_t)(uintptr_t)f;
+    k[13] = (uint64_t)(uintptr_t)F;
+    k[14] = (uint64_t)(uintptr_t)resid;
+    k[15] = (uint64_t)(uintptr_t)Fhist;
+    k[16] = (uint64_t)(uintptr_t)ws;
+    k[17] = (uint64_t)ws_bytes;
+    k[18] = (uint64_t)(uintptr_t)stream;
+    k[19] = (uint64_t)(uintptr_t)m->y ^ ((uint64_t)(uintptr_t)m->z << 1);
+    k[20] = (uint64_t)(uintptr_t)m->dv ^ ((uint64_t)(uintptr_t)m->offs << 1);
+    k[21] = (uint64_t)(uintptr_t)p->om ^ ((uint64_t)(uintptr_t)p->d << 1);
+    k[22] = (uint64_t)(uintptr_t)b->tile_offs ^ ((uint64_t)(uintptr_t)b->src_offs << 1);
+    memcpy(&k[23], lv->lo, 8);
+}
+
+extern "C" int ib_multidirect_force(ib_plan* plan, const ib_level* lv, const ib_particles* p,
+                                    const ib_markers* m, const ib_buckets* b, int32_t ns,
+                                    double dt, const void* u0, void* ustar, void* f, void* F,
+                                    double* resid, void* Fhist, void* ws, size_t ws_bytes,
+                                    void* stream)
+{
+    int rc = check_common(plan, lv, p, m, b, ns, dt);
+    if (rc)
+        return rc;
+    if (!u0 || !ustar || (m->nl > 0 && !F))
+        return IB_EINVAL;
+    const ib_path path = resolved_path(plan);
+    if (path == IB_PATH_PLAIN && ustar == u0)
+        return IB_EINVAL;
+    if (ws_bytes < ib_workspace_bytes(plan, lv, m->nl, ns) || !ws)
+        return IB_EWORKSPACE;
+    Grid g = make_grid(lv);
+    hipStream_t st = (hipStream_t)stream;
+    if (path == IB_PATH_PLAIN)
+        return plain_multidirect(g, plan->P, plan->prec, p, m, b, ns, dt, u0, ustar, f, F, resid,
+                                 Fhist, ws, ws_bytes, st);
+    const BatchedCfg cfg = cfg_of(plan);
+    if (!plan->use_graph || !stream || plan->prof)
+        return batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0, ustar, f, F,
+                                   resid, Fhist, ws, ws_bytes, st);
+    uint64_t key[24];
+    make_key(key, lv, p, m, b, ns, dt, u0, ustar, f, F, resid, Fhist, ws, ws_bytes, stream);
+    if (!plan->has_graph || memcmp(key, plan->key, sizeof(key)) != 0) {
+        drop_graph(plan);
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            set_hip_error(e);
+            return IB_EHIP;
+        }
+        rc = batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0, ustar, f, F,
+                                 resid, Fhist, ws, ws_bytes, st);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(st, &graph);
+        if (rc != IB_OK || e != hipSuccess) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            if (e != hipSuccess)
+                set_hip_error(e);
+            return rc != IB_OK ? rc : IB_EHIP;
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            set_hip_error(e);
+            return IB_EHIP;
+        }
+        plan->graph = graph;
+        plan->exec = exec;
+        memcpy(plan->key, key, sizeof(key));
+        plan->has_graph = 1;
+    }
+    hipError_t e = hipGraphLaunch(plan->exec, st);
+    if (e != hipSuccess) {
+        set_hip_error(e);
+        return IB_EHIP;
+    }
+    return IB_OK;
+}
+
+extern "C" size_t ib_backward_workspace_bytes(const ib_plan* plan, const ib_level* lv,
+                                              int64_t nl)
+{
+    if (!plan || check_level(lv) || nl < 0)
+        return 0;
+    return backward_workspace(make_grid(lv), plan->prec, nl);
+}
+
+extern "C" int ib_multidirect_backward(ib_plan* plan, const ib_level* lv, const ib_particles* p,
+                                       const ib_markers* m, const ib_buckets* b, int32_t ns,
+                                       double dt, const void* u0, const void* Fhist,
+                                       const void* g_ustar, const void* g_f, const void* g_F,
+                                       void* g_u0, double* g_up, double* g_om, double* g_X,
+                                       void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = check_common(plan, lv, p, m, b, ns, dt);
+    if (rc)
+        return rc;
+    if (!u0 || !g_u0 || (ns > 0 && m->nl > 0 && !Fhist) || (m->nl > 0 && !g_X) ||
+        (p->np > 0 && (!g_up || !g_om)))
+        return IB_EINVAL;
+    if (!ws || ws_bytes < ib_backward_workspace_bytes(plan, lv, m->nl))
+        return IB_EWORKSPACE;
+    return multidirect_backward(make_grid(lv), plan->P, plan->prec, p, m, b, ns, dt, u0, Fhist,
+                                g_ustar, g_f, g_F, g_u0, g_up, g_om, g_X, ws, ws_bytes,
+                                (hipStream_t)stream);
+}

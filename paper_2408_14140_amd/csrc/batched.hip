@@ -1,0 +1,354 @@
+// batched.hip -- the batched path of Algorithm 1 for many particles at once.
+//
+// The interpolation operator is linear, so with G^m = S F^m (the force field
+// before the dt factor) the velocity at the markers in iteration m+1 is
+//     J u^(m) = J u0 + dt J G^m.
+// J u0 is formed once (first iteration); later iterations move only marker
+// data and G, never the velocity field:
+//     D     = (U^d - J u0)/dt,   F^1 = D,
+//     F^m   = F^(m-1) + D - J G^(m-1),          m = 2..ns,
+//     f     = G^ns,  ustar = u0 + dt G^ns.
+// This is the recurrence of Algorithm 1 with the correction substituted into
+// the next interpolation; results equal the literal loop up to rounding.
+//
+// Markers are processed in bucket order (sorted by owning 8^3 tile) from
+// structure-of-arrays copies: stencil base relative to the owning cell,
+// P weights per axis, dV/h^3, U^d, D and F.
+//
+// Kernels (persistent workgroups striding over device-side work lists):
+//   interp   work item = up to bw markers of one tile; the item's tile plus a
+//            ceil(P/2)-cell halo of the field (u0 or G) is staged in LDS, then
+//            one thread per marker sums its P^3 stencil from LDS.
+//   spread   work item = one tile with a non-empty source list; one wavefront
+//            accumulates every source's stencil cells that fall in the tile
+//            into an LDS tile with LDS atomics issued by that single wave (the
+//            order of additions is the fixed program and lane order, so the
+//            result is reproducible run to run), then stores the tile with
+//            coalesced writes: to the compact G slots, or in the last
+//            iteration to the caller's f and ustar.  No float atomics reach HBM.
+#include "paths.h"
+
+namespace ibx {
+
+template <int P>
+struct Halo {
+    static constexpr int g = P == 4 ? 2 : 1;
+    static constexpr int R = TILE + 2 * g;
+    static constexpr int R3 = R * R * R;
+};
+
+struct Item {
+    int32_t tile, start, count, pad;
+};
+
+template <typename T, int P>
+struct MarkerSoA {
+    int32_t* rb;   // [3][n] stencil base relative to the owning cell's tile frame
+    T* rw;         // [3P][n] weights
+    T* rs;         // [n] dV / h^3
+    T* ud;         // [3][n] U^d
+    T* d;          // [3][n] D = (U^d - J u0)/dt
+    T* fs;         // [3][n] F^m
+};
+
+__device__ inline void tile_coords(const Grid& g, int t, int* lo)
+{
+    lo[0] = (t % g.nt[0]) * TILE;
+    lo[1] = ((t / g.nt[0]) % g.nt[1]) * TILE;
+    lo[2] = (t / (g.nt[0] * g.nt[1])) * TILE;
+}
+
+// ------------------------------------------------------------------ prep
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+k_prep(Grid g, int64_t nl, const double* __restrict__ x, const double* __restrict__ y,
+       const double* __restrict__ z, const int32_t* __restrict__ pid,
+       const double* __restrict__ dv, const int32_t* __restrict__ perm,
+       const double* __restrict__ xc, const double* __restrict__ up,
+       const double* __restrict__ om, MarkerSoA<T, P> s)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl)
+        return;
+    const int64_t l = perm[i];
+    const double X[3] = {x[l], y[l], z[l]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double sa = grid_coord(g, a, X[a]);
+        T w[P];
+        const int b = axis_weights<T, P>(sa, w);
+        const int fl = (int)floor(sa);
+        const int c = g.periodic[a] ? wrapi(fl, g.n[a]) : fl;
+        s.rb[a * nl + i] = c + (b - fl);
+#pragma unroll
+        for (int o = 0; o < P; ++o)
+            s.rw[(a * P + o) * nl + i] = w[o];
+    }
+    const int p = pid[l];
+    s.rs[i] = (T)(dv[p] * g.inv_h3);
+    const double R0 = X[0] - xc[3 * p], R1 = X[1] - xc[3 * p + 1], R2 = X[2] - xc[3 * p + 2];
+    const double w0 = om[3 * p], w1 = om[3 * p + 1], w2 = om[3 * p + 2];
+    s.ud[0 * nl + i] = (T)(up[3 * p + 0] + (w1 * R2 - w2 * R1));
+    s.ud[1 * nl + i] = (T)(up[3 * p + 1] + (w2 * R0 - w0 * R2));
+    s.ud[2 * nl + i] = (T)(up[3 * p + 2] + (w0 * R1 - w1 * R0));
+}
+
+// ------------------------------------------------------------------ work lists
+
+__global__ void k_tile_counts(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
+                              const int32_t* __restrict__ src_offs, int32_t* item_cnt,
+                              int32_t* act)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T)
+        return;
+    const int cnt = tile_offs[t + 1] - tile_offs[t];
+    item_cnt[t] = (cnt + bw - 1) / bw;
+    act[t] = src_offs[t + 1] > src_offs[t] ? 1 : 0;
+}
+
+__global__ void k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
+                             const int32_t* __restrict__ src_offs,
+                             const int32_t* __restrict__ item_offs,
+                             const int32_t* __restrict__ act_offs, Item* items,
+                             int32_t* active, int32_t* slot)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T)
+        return;
+    const int start = tile_offs[t];
+    const int cnt = tile_offs[t + 1] - start;
+    const int io = item_offs[t];
+    for (int k = 0; k * bw < cnt; ++k) {
+        Item it;
+        it.tile = (int32_t)t;
+        it.start = start + k * bw;
+        it.count = min(bw, cnt - k * bw);
+        it.pad = 0;
+        items[io + k] = it;
+    }
+    if (src_offs[t + 1] > src_offs[t]) {
+        active[act_offs[t]] = (int32_t)t;
+        slot[t] = act_offs[t];
+    } else {
+        slot[t] = -1;
+    }
+}
+
+#include "tiles.h"
+
+// ------------------------------------------------------------------ fill
+
+// Tiles of covered boxes that no marker reaches: f = 0, ustar = u0.
+template <typename T>
+__global__ void k_fill_inactive(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ u0,
+                                T* __restrict__ ustar, T* __restrict__ f, int all)
+{
+    const int64_t total = g.ntiles * TILE_CELLS;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(q / TILE_CELLS);
+        if (!all && slot[t] >= 0)
+            continue;
+        const int r = (int)(q % TILE_CELLS);
+        int lo[3];
+        tile_coords(g, t, lo);
+        const int64_t off = cell_offset(g, lo[0] + (r & 7), lo[1] + ((r >> 3) & 7), lo[2] + (r >> 6));
+        if (off < 0)
+            continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t o = off + c * g.cstride;
+            if (f)
+                f[o] = T(0);
+            if (ustar != u0)
+                ustar[o] = u0[o];
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_unsort(int64_t nl, const int32_t* __restrict__ perm, const T* __restrict__ fs,
+                         T* __restrict__ F)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl)
+        return;
+    const int64_t l = perm[i];
+    F[3 * l + 0] = fs[i];
+    F[3 * l + 1] = fs[nl + i];
+    F[3 * l + 2] = fs[2 * nl + i];
+}
+
+template <typename T>
+__global__ void k_zero(int64_t n, T* a)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        a[q] = T(0);
+}
+
+// ------------------------------------------------------------------ host
+
+template <typename T, int P>
+struct BatchedWs {
+    MarkerSoA<T, P> s;
+    double* e2;
+    double* part;
+    Item* items;
+    int32_t *item_cnt, *item_offs, *act, *act_offs, *active, *slot, *nitems, *nactive;
+    T* G;
+    void* scan;
+};
+
+template <typename T, int P>
+static BatchedWs<T, P> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, size_t bytes,
+                                     size_t* need)
+{
+    Carver cv(ws, bytes);
+    BatchedWs<T, P> w;
+    const int64_t T_ = g.ntiles;
+    w.s.rb = cv.take<int32_t>(3 * nl);
+    w.s.rw = cv.take<T>(3 * P * nl);
+    w.s.rs = cv.take<T>(nl);
+    w.s.ud = cv.take<T>(3 * nl);
+    w.s.d = cv.take<T>(3 * nl);
+    w.s.fs = cv.take<T>(3 * nl);
+    w.e2 = cv.take<double>(nl);
+    w.part = cv.take<double>(sum_partials(nl));
+    w.items = cv.take<Item>(T_ + nl / bw + 1);
+    w.item_cnt = cv.take<int32_t>(T_);
+    w.item_offs = cv.take<int32_t>(T_);
+    w.act = cv.take<int32_t>(T_);
+    w.act_offs = cv.take<int32_t>(T_);
+    w.active = cv.take<int32_t>(T_);
+    w.slot = cv.take<int32_t>(T_);
+    w.nitems = cv.take<int32_t>(1);
+    w.nactive = cv.take<int32_t>(1);
+    const int64_t max_active = T_ < 8 * nl ? T_ : 8 * nl;
+    w.G = cv.take<T>((size_t)3 * TILE_CELLS * (max_active > 0 ? max_active : 1));
+    w.scan = cv.take<char>(scan_workspace(T_));
+    *need = cv.used;
+    return w;
+}
+
+template <typename T, int P>
+static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles* p,
+                       const ib_markers* m, const ib_buckets* b, int ns, double dt,
+                       const T* u0, T* ustar, T* f, T* F, double* resid, T* Fhist, void* ws,
+                       size_t ws_bytes, hipStream_t st)
+{
+    const int64_t nl = m->nl;
+    const int64_t T_ = g.ntiles;
+    size_t need = 0;
+    carve_batched<T, P>(g, nl, cfg.bw, nullptr, 0, &need);
+    if (!ws || ws_bytes < need)
+        return IB_EWORKSPACE;
+    BatchedWs<T, P> w = carve_batched<T, P>(g, nl, cfg.bw, ws, ws_bytes, &need);
+    const unsigned gm = (unsigned)((nl + 255) / 256 > 0 ? (nl + 255) / 256 : 1);
+    const unsigned gt = (unsigned)((T_ + 255) / 256);
+    const unsigned gfill = (unsigned)((T_ * TILE_CELLS + 255) / 256 < 65536
+                                          ? (T_ * TILE_CELLS + 255) / 256 : 65536);
+    if (nl == 0) {
+        k_fill_inactive<T><<<gfill, 256, 0, st>>>(g, w.slot, u0, ustar, f, 1);
+        if (resid)
+            k_zero<double><<<1, 64, 0, st>>>(ns + 1, resid);
+        return launch_status();
+    }
+    if (cfg.prof) cfg.prof->begin(PK_PREP, st);
+    k_prep<T, P><<<gm, 256, 0, st>>>(g, nl, m->x, m->y, m->z, m->pid, m->dv, b->perm, p->xc,
+                                     p->up, p->om, w.s);
+    if (cfg.prof) cfg.prof->end(st);
+    if (cfg.prof) cfg.prof->begin(PK_LISTS, st);
+    k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt, w.act);
+    scan_exclusive(w.item_cnt, w.item_offs, T_, w.nitems, w.scan, st);
+    scan_exclusive(w.act, w.act_offs, T_, w.nactive, w.scan, st);
+    k_fill_lists<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs,
+                                     w.act_offs, w.items, w.active, w.slot);
+    if (cfg.prof) cfg.prof->end(st);
+    double* e2 = resid ? w.e2 : nullptr;
+    if (cfg.prof) cfg.prof->begin(PK_INTERP_U0, st);
+    k_interp_tiles<T, P, 0><<<cfg.grid_i, cfg.bw, 0, st>>>(g, nl, dt, w.items, w.nitems, u0,
+                                                           w.G, w.slot, w.s, e2);
+    if (cfg.prof) cfg.prof->end(st);
+    if (resid)
+        sum_to(w.e2, nl, w.part, resid + 0, true, st);
+    if (ns == 0) {
+        // no iteration: ustar = u0, f = 0, F = 0
+        k_fill_inactive<T><<<gfill, 256, 0, st>>>(g, w.slot, u0, ustar, f, 1);
+        k_zero<T><<<gm, 256, 0, st>>>(3 * nl, F);
+        return launch_status();
+    }
+    if (Fhist)
+        k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.fs, Fhist);
+    for (int mi = 2; mi <= ns; ++mi) {
+        if (cfg.prof) cfg.prof->begin(PK_SPREAD, st);
+        k_spread_tiles<T, P, 0><<<cfg.grid_s, 64, 0, st>>>(g, nl, dt, w.active, w.nactive,
+                                                           b->src_offs, b->src_idx, w.s, w.G,
+                                                           u0, ustar, f, 0);
+        if (cfg.prof) cfg.prof->end(st);
+        if (cfg.prof) cfg.prof->begin(PK_INTERP_G, st);
+        k_interp_tiles<T, P, 1><<<cfg.grid_i, cfg.bw, 0, st>>>(g, nl, dt, w.items, w.nitems, u0,
+                                                               w.G, w.slot, w.s, e2);
+        if (cfg.prof) cfg.prof->end(st);
+        if (resid)
+            sum_to(w.e2, nl, w.part, resid + (mi - 1), true, st);
+        if (Fhist)
+            k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.fs,
+                                            Fhist + (int64_t)(mi - 1) * 3 * nl);
+    }
+    if (cfg.prof) cfg.prof->begin(PK_SPREAD_FINAL, st);
+    k_spread_tiles<T, P, 1><<<cfg.grid_s, 64, 0, st>>>(g, nl, dt, w.active, w.nactive,
+                                                       b->src_offs, b->src_idx, w.s, w.G, u0,
+                                                       ustar, f, resid ? 1 : 0);
+    if (cfg.prof) cfg.prof->end(st);
+    if (f || ustar != u0) {
+        if (cfg.prof) cfg.prof->begin(PK_FILL, st);
+        k_fill_inactive<T><<<gfill, 256, 0, st>>>(g, w.slot, u0, ustar, f, 0);
+        if (cfg.prof) cfg.prof->end(st);
+    }
+    if (resid) {
+        k_interp_tiles<T, P, 2><<<cfg.grid_i, cfg.bw, 0, st>>>(g, nl, dt, w.items, w.nitems, u0,
+                                                               w.G, w.slot, w.s, w.e2);
+        sum_to(w.e2, nl, w.part, resid + ns, true, st);
+    }
+    if (cfg.prof) cfg.prof->begin(PK_UNSORT, st);
+    k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.fs, F);
+    if (cfg.prof) cfg.prof->end(st);
+    return launch_status();
+}
+
+size_t batched_workspace(const Grid& g, ib_prec prec, int64_t nl, const BatchedCfg& cfg)
+{
+    size_t need = 0;
+    if (prec == IB_F64)
+        carve_batched<double, 4>(g, nl, cfg.bw, nullptr, 0, &need);
+    else
+        carve_batched<float, 4>(g, nl, cfg.bw, nullptr, 0, &need);
+    return need;
+}
+
+int batched_multidirect(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg,
+                        const ib_particles* p, const ib_markers* m, const ib_buckets* b, int ns,
+                        double dt, const void* u0, void* ustar, void* f, void* F, double* resid,
+                        void* Fhist, void* ws, size_t ws_bytes, hipStream_t st)
+{
+    if (prec == IB_F64) {
+        if (P == 3)
+            return run_batched<double, 3>(g, cfg, p, m, b, ns, dt, (const double*)u0,
+                                          (double*)ustar, (double*)f, (double*)F, resid,
+                                          (double*)Fhist, ws, ws_bytes, st);
+        return run_batched<double, 4>(g, cfg, p, m, b, ns, dt, (const double*)u0,
+                                      (double*)ustar, (double*)f, (double*)F, resid,
+                                      (double*)Fhist, ws, ws_bytes, st);
+    }
+    if (P == 3)
+        return run_batched<float, 3>(g, cfg, p, m, b, ns, dt, (const float*)u0, (float*)ustar,
+                                     (float*)f, (float*)F, resid, (float*)Fhist, ws, ws_bytes,
+                                     st);
+    return run_batched<float, 4>(g, cfg, p, m, b, ns, dt, (const float*)u0, (float*)ustar,
+                                 (float*)f, (float*)F, resid, (float*)Fhist, ws, ws_bytes, st);
+}
+
+}  // namespace ibx

@@ -1,0 +1,494 @@
+// bucket.hip -- a2: markers bucketed by owning 8^3 tile, and per-tile source
+// lists.  Integer work only; every output is deterministic.
+//
+// Pipeline (all on one stream, no host synchronization):
+//   keys    per marker: owning cell, tile, stencil base, coverage check
+//   sort    stable LSD radix sort of (tile, marker) -> perm
+//   offs    tile_offs[t] = lower bound of t in the sorted tiles
+//   pairs   per sorted position i, the (tile, i) pairs of every tile its
+//           stencil touches, emitted in i order, then stably sorted by tile
+//           -> src_idx / src_offs (each list ascending in i)
+#include "ibx_internal.h"
+
+namespace ibx {
+
+// ------------------------------------------------------------------ scan
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_scan_tile(const int32_t* in, int32_t* out, int64_t n, int32_t* sums)
+{
+    __shared__ int32_t ts[SCAN_THREADS];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)t * SCAN_ITEMS;
+    int32_t v[SCAN_ITEMS];
+    int32_t tsum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        tsum += v[k];
+    }
+    ts[t] = tsum;
+    __syncthreads();
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+        int32_t x = (t >= off) ? ts[t - off] : 0;
+        __syncthreads();
+        ts[t] += x;
+        __syncthreads();
+    }
+    int32_t run = ts[t] - tsum;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n)
+            out[base + k] = run;
+        run += v[k];
+    }
+    if (t == SCAN_THREADS - 1)
+        sums[blockIdx.x] = ts[t];
+}
+
+__global__ void k_scan_add(int32_t* out, int64_t n, const int32_t* sums)
+{
+    const int32_t add = sums[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    for (int k = threadIdx.x; k < SCAN_TILE; k += blockDim.x)
+        if (base + k < n)
+            out[base + k] += add;
+}
+
+__global__ void k_copy1(int32_t* dst, const int32_t* src) { *dst = *src; }
+__global__ void k_set1(int32_t* dst, int32_t v) { *dst = v; }
+
+size_t scan_workspace(int64_t n)
+{
+    size_t bytes = 0;
+    while (n > 0) {
+        int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+        bytes += align_up(sizeof(int32_t) * nb);
+        if (nb == 1)
+            break;
+        n = nb;
+    }
+    return bytes + 256;
+}
+
+void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* total, void* ws,
+                    hipStream_t st)
+{
+    if (n <= 0) {
+        if (total)
+            k_set1<<<1, 1, 0, st>>>(total, 0);
+        return;
+    }
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    int32_t* sums = (int32_t*)ws;
+    k_scan_tile<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, out, n, sums);
+    if (nb == 1) {
+        if (total)
+            k_copy1<<<1, 1, 0, st>>>(total, sums);
+        return;
+    }
+    scan_exclusive(sums, sums, nb, total, (char*)ws + align_up(sizeof(int32_t) * nb), st);
+    k_scan_add<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(out, n, sums);
+}
+
+// ------------------------------------------------------------------ radix sort
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_ROUNDS = 8;
+constexpr int RS_TILE = RS_THREADS * RS_ROUNDS;
+constexpr int RS_WAVES = RS_THREADS / 64;
+
+__device__ inline int64_t live_count(int64_t n_max, const int32_t* n_dev)
+{
+    if (!n_dev)
+        return n_max;
+    int64_t v = *n_dev;
+    return v < n_max ? v : n_max;
+}
+
+__global__ void __launch_bounds__(RS_THREADS)
+k_radix_hist(const int32_t* keys, int64_t n_max, const int32_t* n_dev, int shift,
+             int32_t* hist, int nblocks)
+{
+    __shared__ int32_t h[256];
+    const int t = threadIdx.x;
+    const int64_t n = live_count(n_max, n_dev);
+    h[t] = 0;
+    __syncthreads();
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        int64_t j = (int64_t)blockIdx.x * RS_TILE + r * RS_THREADS + t;
+        if (j < n)
+            atomicAdd(&h[(keys[j] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)t * nblocks + blockIdx.x] = h[t];
+}
+
+// Stable scatter: elements keep their input order within each digit.  Ranks
+// inside a wave come from ballot matching on the 8 digit bits; ranks across
+// the block's waves and rounds from per-digit counters in LDS.
+__global__ void __launch_bounds__(RS_THREADS)
+k_radix_scatter(const int32_t* kin, const int32_t* vin, int32_t* kout, int32_t* vout,
+                int64_t n_max, const int32_t* n_dev, int shift, const int32_t* hist_scan,
+                int nblocks)
+{
+    __shared__ int32_t run[256];
+    __shared__ int32_t wc[RS_WAVES][256];
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    const int64_t n = live_count(n_max, n_dev);
+    run[t] = hist_scan[(int64_t)t * nblocks + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w)
+        wc[w][t] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int r = 0; r < RS_ROUNDS; ++r) {
+        const int64_t j = (int64_t)blockIdx.x * RS_TILE + r * RS_THREADS + t;
+        const bool valid = j < n;
+        const int32_t k = valid ? kin[j] : 0;
+        const int32_t v = valid ? vin[j] : 0;
+        const int d = (k >> shift) & 255;
+        uint64_t mask = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t m = __ballot(valid && bit);
+            mask &= bit ? m : ~m;
+        }
+        const int rank = __popcll(mask & lt);
+        if (valid && rank == 0)
+            wc[wave][d] = __popcll(mask);
+        __syncthreads();
+        if (valid) {
+            int pos = run[d] + rank;
+            for (int w = 0; w < wave; ++w)
+                pos += wc[w][d];
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __syncthreads();
+        int add = 0;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; ++w) {
+            add += wc[w][t];
+            wc[w][t] = 0;
+        }
+        run[t] += add;
+        __syncthreads();
+    }
+}
+
+__global__ void k_copy_pairs(const int32_t* ks, const int32_t* vs, int32_t* kd, int32_t* vd,
+                             int64_t n_max, const int32_t* n_dev)
+{
+    const int64_t n = live_count(n_max, n_dev);
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        kd[j] = ks[j];
+        vd[j] = vs[j];
+    }
+}
+
+static int64_t rs_blocks(int64_t n_max) { return (n_max + RS_TILE - 1) / RS_TILE; }
+
+size_t radix_workspace(int64_t n_max)
+{
+    int64_t nb = rs_blocks(n_max > 0 ? n_max : 1);
+    return align_up(sizeof(int32_t) * 256 * nb) + scan_workspace(256 * nb);
+}
+
+void radix_sort_pairs(int32_t* keys, int32_t* vals, int32_t* tk, int32_t* tv, int64_t n_max,
+                      const int32_t* n_dev, int bits, void* ws, hipStream_t st)
+{
+    if (n_max <= 0 || bits <= 0)
+        return;
+    const int64_t nb = rs_blocks(n_max);
+    int32_t* hist = (int32_t*)ws;
+    void* sws = (char*)ws + align_up(sizeof(int32_t) * 256 * nb);
+    int32_t *ka = keys, *va = vals, *kb = tk, *vb = tv;
+    const int passes = (bits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        k_radix_hist<<<(unsigned)nb, RS_THREADS, 0, st>>>(ka, n_max, n_dev, shift, hist, (int)nb);
+        scan_exclusive(hist, hist, 256 * nb, nullptr, sws, st);
+        k_radix_scatter<<<(unsigned)nb, RS_THREADS, 0, st>>>(ka, va, kb, vb, n_max, n_dev, shift,
+                                                             hist, (int)nb);
+        int32_t* t0 = ka; ka = kb; kb = t0;
+        t0 = va; va = vb; vb = t0;
+    }
+    if (ka != keys) {
+        int64_t g = (n_max + 255) / 256;
+        if (g > 65536)
+            g = 65536;
+        k_copy_pairs<<<(unsigned)g, 256, 0, st>>>(ka, va, keys, vals, n_max, n_dev);
+    }
+}
+
+__global__ void k_lower_bounds(const int32_t* keys, int64_t n_max, const int32_t* n_dev,
+                               int32_t* offs, int64_t T)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > T)
+        return;
+    int64_t lo = 0, hi = live_count(n_max, n_dev);
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < t)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    offs[t] = (int32_t)lo;
+}
+
+void lower_bounds(const int32_t* keys, int64_t n_max, const int32_t* n_dev, int32_t* offs,
+                  int64_t T, hipStream_t st)
+{
+    k_lower_bounds<<<(unsigned)((T + 1 + 255) / 256), 256, 0, st>>>(keys, n_max, n_dev, offs, T);
+}
+
+// ------------------------------------------------------------------ bucket keys
+
+__global__ void k_init_flags(int32_t* flag)
+{
+    if (threadIdx.x < 2)
+        flag[threadIdx.x] = 0;
+}
+
+// Per marker: owning cell c = floor(s) (wrapped on periodic axes), its tile,
+// the unwrapped stencil base, and whether all stencil cells are covered.
+template <int P>
+__global__ void k_bucket_keys(Grid g, int64_t nl, const double* __restrict__ x,
+                              const double* __restrict__ y, const double* __restrict__ z,
+                              int32_t* cell, int32_t* tileid, int32_t* base, int32_t* keys,
+                              int32_t* vals, int32_t* flag)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nl)
+        return;
+    const double X[3] = {x[l], y[l], z[l]};
+    int c[3], b[3];
+    int bad = 0;
+    int bx[3][2], nbx[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double s = grid_coord(g, a, X[a]);
+        const int fl = (int)floor(s);
+        b[a] = stencil_base<P>(s);
+        if (g.periodic[a]) {
+            c[a] = wrapi(fl, g.n[a]);
+        } else {
+            c[a] = fl;
+            if (fl < 0 || fl >= g.n[a]) {
+                bad = 1;
+                c[a] = fl < 0 ? 0 : g.n[a] - 1;
+            }
+        }
+        // boxes touched by the stencil cells b .. b+P-1 on this axis (at most 2)
+        nbx[a] = 0;
+        for (int o = 0; o < P; ++o) {
+            int q = b[a] + o;
+            if (g.periodic[a])
+                q = wrapi(q, g.n[a]);
+            else if (q < 0 || q >= g.n[a]) {
+                bad = 1;
+                continue;
+            }
+            const int bq = q / g.box;
+            if (nbx[a] == 0 || (bx[a][nbx[a] - 1] != bq && (nbx[a] < 2)))
+                bx[a][nbx[a]++] = bq;
+        }
+    }
+    for (int k = 0; k < nbx[2] && !bad; ++k)
+        for (int j = 0; j < nbx[1] && !bad; ++j)
+            for (int i = 0; i < nbx[0] && !bad; ++i)
+                if (g.lut[bx[0][i] + g.nb[0] * (bx[1][j] + g.nb[1] * bx[2][k])] < 0)
+                    bad = 1;
+    cell[l] = c[0] + g.n[0] * (c[1] + g.n[1] * c[2]);
+    const int t = c[0] / TILE + g.nt[0] * (c[1] / TILE + g.nt[1] * (c[2] / TILE));
+    tileid[l] = t;
+    keys[l] = t;
+    vals[l] = (int32_t)l;
+    base[3 * l + 0] = b[0];
+    base[3 * l + 1] = b[1];
+    base[3 * l + 2] = b[2];
+    if (bad)
+        atomicAdd(&flag[0], 1);
+}
+
+// Tiles touched on one axis by the stencil cells b .. b+P-1 (1 or 2 tiles).
+template <int P>
+__device__ inline int axis_tiles(const Grid& g, int a, int b, int* tl)
+{
+    int nt = 0;
+    for (int o = 0; o < P; ++o) {
+        int q = b + o;
+        if (g.periodic[a])
+            q = wrapi(q, g.n[a]);
+        else if (q < 0 || q >= g.n[a])
+            continue;
+        const int tq = q / TILE;
+        if (nt == 0 || (tl[nt - 1] != tq && nt < 2 && tl[0] != tq))
+            tl[nt++] = tq;
+    }
+    return nt;
+}
+
+template <int P>
+__global__ void k_src_count(Grid g, int64_t nl, const int32_t* perm, const int32_t* base,
+                            int32_t* cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl)
+        return;
+    const int64_t l = perm[i];
+    int tl[2], c = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        c *= axis_tiles<P>(g, a, base[3 * l + a], tl);
+    cnt[i] = c;
+}
+
+template <int P>
+__global__ void k_src_emit(Grid g, int64_t nl, const int32_t* perm, const int32_t* base,
+                           const int32_t* offs, int32_t* keys2, int32_t* vals2, int64_t cap,
+                           int32_t* flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl)
+        return;
+    const int64_t l = perm[i];
+    int tl[3][2], nt[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        nt[a] = axis_tiles<P>(g, a, base[3 * l + a], tl[a]);
+    int64_t pos = offs[i];
+    for (int k = 0; k < nt[2]; ++k)
+        for (int j = 0; j < nt[1]; ++j)
+            for (int q = 0; q < nt[0]; ++q) {
+                if (pos < cap) {
+                    keys2[pos] = tl[0][q] + g.nt[0] * (tl[1][j] + g.nt[1] * tl[2][k]);
+                    vals2[pos] = (int32_t)i;
+                } else {
+                    flag[1] = 1;
+                }
+                ++pos;
+            }
+}
+
+__global__ void k_clamp_count(int32_t* npairs, const int32_t* total, int64_t cap)
+{
+    int64_t v = *total;
+    *npairs = (int32_t)(v < cap ? v : cap);
+}
+
+static int key_bits(int64_t T)
+{
+    int bits = 0;
+    while (((int64_t)1 << bits) < T)
+        ++bits;
+    return bits;
+}
+
+struct BucketWs {
+    int32_t *keys, *tk, *tv, *cnt, *total, *npairs, *keys2, *tk2, *tv2;
+    void *rs, *scan;
+};
+
+static BucketWs carve_bucket_ws(void* ws, size_t bytes, int64_t nl, int64_t cap, size_t* need)
+{
+    Carver cv(ws, bytes);
+    BucketWs w;
+    w.keys = cv.take<int32_t>(nl);
+    w.tk = cv.take<int32_t>(nl);
+    w.tv = cv.take<int32_t>(nl);
+    w.cnt = cv.take<int32_t>(nl);
+    w.total = cv.take<int32_t>(1);
+    w.npairs = cv.take<int32_t>(1);
+    w.keys2 = cv.take<int32_t>(cap);
+    w.tk2 = cv.take<int32_t>(cap);
+    w.tv2 = cv.take<int32_t>(cap);
+    size_t rsb = radix_workspace(cap > nl ? cap : nl);
+    w.rs = cv.take<char>(rsb);
+    w.scan = cv.take<char>(scan_workspace(nl));
+    *need = cv.used;
+    return w;
+}
+
+}  // namespace ibx
+
+using namespace ibx;
+
+extern "C" size_t ib_bucket_workspace(const ib_level* lv, int64_t nl)
+{
+    (void)lv;
+    size_t need = 0;
+    if (nl < 0)
+        return 0;
+    carve_bucket_ws(nullptr, 0, nl, 8 * (nl > 0 ? nl : 1), &need);
+    return need;
+}
+
+extern "C" int ib_bucket(const ib_level* lv, const ib_markers* m, ib_delta delta,
+                         const ib_buckets* b, void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = check_level(lv);
+    if (rc)
+        return rc;
+    if (!m || !b || (delta != IB_DELTA3 && delta != IB_DELTA4) || m->nl < 0 ||
+        m->nl > (int64_t)INT32_MAX / 8)
+        return IB_EINVAL;
+    if (!b->tile_offs || !b->src_offs || !b->flag)
+        return IB_EINVAL;
+    const int64_t nl = m->nl;
+    if (nl > 0 && (!m->x || !m->y || !m->z || !b->cell || !b->tileid || !b->base || !b->perm ||
+                   !b->src_idx || b->src_cap < 0))
+        return IB_EINVAL;
+    Grid g = make_grid(lv);
+    const int64_t T = g.ntiles;
+    hipStream_t st = (hipStream_t)stream;
+    size_t need = 0;
+    const int64_t cap = b->src_cap < 8 * nl ? b->src_cap : 8 * nl;
+    BucketWs w = carve_bucket_ws(nullptr, 0, nl, cap, &need);
+    if (!ws || ws_bytes < need)
+        return IB_EWORKSPACE;
+    w = carve_bucket_ws(ws, ws_bytes, nl, cap, &need);
+
+    k_init_flags<<<1, 64, 0, st>>>(b->flag);
+    if (nl == 0) {
+        lower_bounds(w.keys, 0, nullptr, b->tile_offs, T, st);
+        lower_bounds(w.keys, 0, nullptr, b->src_offs, T, st);
+        return launch_status();
+    }
+    const unsigned gb = (unsigned)((nl + 255) / 256);
+    if (delta == IB_DELTA3)
+        k_bucket_keys<3><<<gb, 256, 0, st>>>(g, nl, m->x, m->y, m->z, b->cell, b->tileid,
+                                             b->base, w.keys, b->perm, b->flag);
+    else
+        k_bucket_keys<4><<<gb, 256, 0, st>>>(g, nl, m->x, m->y, m->z, b->cell, b->tileid,
+                                             b->base, w.keys, b->perm, b->flag);
+    const int bits = key_bits(T);
+    radix_sort_pairs(w.keys, b->perm, w.tk, w.tv, nl, nullptr, bits, w.rs, st);
+    lower_bounds(w.keys, nl, nullptr, b->tile_offs, T, st);
+
+    if (delta == IB_DELTA3)
+        k_src_count<3><<<gb, 256, 0, st>>>(g, nl, b->perm, b->base, w.cnt);
+    else
+        k_src_count<4><<<gb, 256, 0, st>>>(g, nl, b->perm, b->base, w.cnt);
+    scan_exclusive(w.cnt, w.cnt, nl, w.total, w.scan, st);
+    if (delta == IB_DELTA3)
+        k_src_emit<3><<<gb, 256, 0, st>>>(g, nl, b->perm, b->base, w.cnt, w.keys2, b->src_idx,
+                                          cap, b->flag);
+    else
+        k_src_emit<4><<<gb, 256, 0, st>>>(g, nl, b->perm, b->base, w.cnt, w.keys2, b->src_idx,
+                                          cap, b->flag);
+    k_clamp_count<<<1, 1, 0, st>>>(w.npairs, w.total, cap);
+    radix_sort_pairs(w.keys2, b->src_idx, w.tk2, w.tv2, cap, w.npairs, bits, w.rs, st);
+    lower_bounds(w.keys2, cap, w.npairs, b->src_offs, T, st);
+    return launch_status();
+}

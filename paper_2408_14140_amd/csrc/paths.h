@@ -1,0 +1,49 @@
+// paths.h -- host-side entry points of the plain and batched loops.
+#pragma once
+
+#include "ibx_internal.h"
+
+namespace ibx {
+
+void desired_velocity(const ib_particles* p, const ib_markers* m, ib_prec prec, void* Ud,
+                      hipStream_t st);
+
+// Deterministic sum (fixed chunking and tree) of v[0..n) into *out (sqrt if asked).
+void sum_to(const double* v, int64_t n, double* part, double* out, bool do_sqrt, hipStream_t st);
+size_t sum_partials(int64_t n);
+size_t field_elems(const Grid& g);
+
+void plain_interp(const Grid& g, int P, ib_prec prec, const ib_markers* m, const void* u,
+                  void* U, hipStream_t st);
+void plain_spread(const Grid& g, int P, ib_prec prec, const ib_markers* m, const ib_buckets* b,
+                  const void* F, void* f, double scale, int use_dv, hipStream_t st);
+
+size_t plain_workspace(const Grid& g, ib_prec prec, int64_t nl);
+int plain_multidirect(const Grid& g, int P, ib_prec prec, const ib_particles* p,
+                      const ib_markers* m, const ib_buckets* b, int ns, double dt,
+                      const void* u0, void* ustar, void* f, void* F, double* resid, void* Fhist,
+                      void* ws, size_t ws_bytes, hipStream_t st);
+
+struct BatchedCfg {
+    int bw;        // markers per interpolation work item (= threads per workgroup)
+    int grid_i;    // persistent workgroups of the interpolation kernels
+    int grid_s;    // persistent workgroups of the spreading kernel
+    Profiler* prof;  // nullable: per-kernel event timing
+};
+
+size_t batched_workspace(const Grid& g, ib_prec prec, int64_t nl, const BatchedCfg& cfg);
+int batched_multidirect(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg,
+                        const ib_particles* p, const ib_markers* m, const ib_buckets* b, int ns,
+                        double dt, const void* u0, void* ustar, void* f, void* F, double* resid,
+                        void* Fhist, void* ws, size_t ws_bytes, hipStream_t st);
+
+}  // namespace ibx
+
+namespace ibx {
+size_t backward_workspace(const Grid& g, ib_prec prec, int64_t nl);
+int multidirect_backward(const Grid& g, int P, ib_prec prec, const ib_particles* p,
+                         const ib_markers* m, const ib_buckets* b, int ns, double dt,
+                         const void* u0, const void* Fhist, const void* gus, const void* gf,
+                         const void* gF, void* gu0, double* gup, double* gom, double* gX,
+                         void* ws, size_t ws_bytes, hipStream_t st);
+}  // namespace ibx

@@ -1,0 +1,474 @@
+"""ctypes binding of libibx (the C ABI in ``include/ibx.h``).
+
+Argument marshalling only: every step of the IB loop runs in the library's
+HIP kernels.  Tensors are torch tensors on the current HIP device; calls are
+enqueued on torch's current stream.  Importing this module fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibx.so")
+
+IB_OK, IB_EINVAL, IB_EDOMAIN, IB_EWORKSPACE, IB_EHIP, IB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+IB_F64, IB_F32 = 0, 1
+IB_PATH_AUTO, IB_PATH_PLAIN, IB_PATH_BATCHED = 0, 1, 2
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libibx.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+_lib = C.CDLL(LIB_PATH)
+
+_p = C.c_void_p
+_i32 = C.c_int32
+_i64 = C.c_int64
+_d = C.c_double
+_sz = C.c_size_t
+
+
+class IbLevel(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("h", C.c_double), ("lo", C.c_double * 3),
+                ("periodic", C.c_int32 * 3), ("box", C.c_int32), ("ngrow", C.c_int32),
+                ("nbox", C.c_int32), ("box_lo", _p), ("box_lut", _p)]
+
+
+class IbParticles(C.Structure):
+    _fields_ = [("np", C.c_int32), ("xc", _p), ("d", _p), ("up", _p), ("om", _p)]
+
+
+class IbMarkers(C.Structure):
+    _fields_ = [("nl", C.c_int64), ("offs", _p), ("x", _p), ("y", _p), ("z", _p),
+                ("pid", _p), ("dv", _p)]
+
+
+class IbBuckets(C.Structure):
+    _fields_ = [("cell", _p), ("tileid", _p), ("base", _p), ("perm", _p), ("tile_offs", _p),
+                ("src_offs", _p), ("src_idx", _p), ("src_cap", C.c_int64), ("flag", _p)]
+
+
+_PL = C.POINTER(IbLevel)
+_PP = C.POINTER(IbParticles)
+_PM = C.POINTER(IbMarkers)
+_PB = C.POINTER(IbBuckets)
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_count_markers = _sig("ib_count_markers", _i64, [_i32, _p, _d, _p])
+_build_markers = _sig("ib_build_markers", C.c_int, [_PL, _PP, _PM, _p])
+_desired_velocity = _sig("ib_desired_velocity", C.c_int, [_PP, _PM, C.c_int, _p, _p])
+_bucket_ws = _sig("ib_bucket_workspace", _sz, [_PL, _i64])
+_bucket = _sig("ib_bucket", C.c_int, [_PL, _PM, C.c_int, _PB, _p, _sz, _p])
+_interp = _sig("ib_interp", C.c_int, [_PL, _PM, C.c_int, C.c_int, _p, _p, _p])
+_spread = _sig("ib_spread", C.c_int, [_PL, _PM, _PB, C.c_int, C.c_int, _p, _p, _p])
+_plan_create = _sig("ib_plan_create", C.c_int,
+                    [C.POINTER(_p), C.c_int, C.c_int, C.c_int, _i32, _i32, _i32])
+_plan_destroy = _sig("ib_plan_destroy", None, [_p])
+_plan_query = _sig("ib_plan_query", C.c_int, [_p, _p])
+_ws_bytes = _sig("ib_workspace_bytes", _sz, [_p, _PL, _i64, _i32])
+_plan_profile = _sig("ib_plan_profile", C.c_int, [_p, _i32])
+_plan_profile_read = _sig("ib_plan_profile_read", C.c_int, [_p, _p, _p, _i32])
+PROF_CLASSES = ("prep", "lists", "interp_u0", "spread", "interp_g", "spread_final", "fill",
+                "unsort", "resid")
+_multidirect = _sig("ib_multidirect_force", C.c_int,
+                    [_p, _PL, _PP, _PM, _PB, _i32, _d, _p, _p, _p, _p, _p, _p, _p, _sz, _p])
+_reductions = _sig("ib_particle_reductions", C.c_int, [_PL, _PP, _PM, C.c_int, _p, _p, _p, _p, _p])
+_bwd_ws = _sig("ib_backward_workspace_bytes", _sz, [_p, _PL, _i64])
+_backward = _sig("ib_multidirect_backward", C.c_int,
+                 [_p, _PL, _PP, _PM, _PB, _i32, _d, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
+                  _sz, _p])
+_status_string = _sig("ib_status_string", C.c_char_p, [C.c_int])
+_last_hip_error = _sig("ib_last_hip_error", C.c_char_p, [])
+_version = _sig("ib_version", C.c_int, [])
+
+EXPORTED = ("ib_count_markers", "ib_build_markers", "ib_desired_velocity", "ib_bucket_workspace",
+            "ib_bucket", "ib_interp", "ib_spread", "ib_plan_create", "ib_plan_destroy",
+            "ib_plan_query", "ib_workspace_bytes", "ib_plan_profile", "ib_plan_profile_read",
+            "ib_multidirect_force",
+            "ib_particle_reductions", "ib_backward_workspace_bytes", "ib_multidirect_backward",
+            "ib_status_string", "ib_last_hip_error", "ib_version")
+
+
+class IbxError(RuntimeError):
+    def __init__(self, status, where):
+        msg = _status_string(status).decode()
+        if status == IB_EHIP:
+            msg += ": " + _last_hip_error().decode()
+        super().__init__(f"{where}: {msg} ({status})")
+        self.status = status
+
+
+def _check(rc, where):
+    if rc < 0:
+        raise IbxError(rc, where)
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _prec_of(dtype):
+    if dtype == torch.float64:
+        return IB_F64
+    if dtype == torch.float32:
+        return IB_F32
+    raise TypeError(f"unsupported field dtype {dtype}")
+
+
+def _dev(device):
+    return torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+
+
+# ---------------------------------------------------------------- containers
+
+@dataclasses.dataclass
+class DeviceLevel:
+    n: tuple
+    h: float
+    lo: tuple
+    periodic: tuple
+    box: int
+    ngrow: int
+    box_lo: torch.Tensor
+    lut: torch.Tensor
+
+    @property
+    def nbox(self):
+        return int(self.box_lo.shape[0])
+
+    @property
+    def ext(self):
+        return self.box + 2 * self.ngrow
+
+    @property
+    def ntiles(self):
+        return int(np.prod([v // 8 for v in self.n]))
+
+    def field_shape(self):
+        e = self.ext
+        return (self.nbox, 3, e, e, e)
+
+    @property
+    def c(self):
+        s = IbLevel()
+        s.n[:] = list(self.n)
+        s.h = self.h
+        s.lo[:] = list(self.lo)
+        s.periodic[:] = list(self.periodic)
+        s.box, s.ngrow, s.nbox = self.box, self.ngrow, self.nbox
+        s.box_lo = _ptr(self.box_lo) if self.nbox else None
+        s.box_lut = _ptr(self.lut)
+        return s
+
+
+def device_level(level, device=None) -> DeviceLevel:
+    """From a host level description (``workloads.Level`` or anything alike)."""
+    dev = _dev(device)
+    box_lo = torch.as_tensor(np.ascontiguousarray(level.box_lo, dtype=np.int32).reshape(-1, 3),
+                             device=dev)
+    lut = torch.as_tensor(np.ascontiguousarray(level.lut, dtype=np.int32), device=dev)
+    return DeviceLevel(tuple(int(v) for v in level.n), float(level.h),
+                       tuple(float(v) for v in level.lo), tuple(int(v) for v in level.periodic),
+                       int(level.box), int(level.ngrow), box_lo, lut)
+
+
+@dataclasses.dataclass
+class Particles:
+    xc: torch.Tensor   # (np, 3) float64
+    d: torch.Tensor    # (np,)
+    up: torch.Tensor   # (np, 3)
+    om: torch.Tensor   # (np, 3)
+
+    @property
+    def np(self):
+        return int(self.d.shape[0])
+
+    @property
+    def c(self):
+        s = IbParticles()
+        s.np = self.np
+        s.xc, s.d, s.up, s.om = _ptr(self.xc), _ptr(self.d), _ptr(self.up), _ptr(self.om)
+        return s
+
+
+def particles(xc, d, up, om, device=None) -> Particles:
+    dev = _dev(device)
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev) \
+        if not isinstance(a, torch.Tensor) else a.to(dev, torch.float64).contiguous()
+    return Particles(f(xc).reshape(-1, 3), f(d).reshape(-1), f(up).reshape(-1, 3),
+                     f(om).reshape(-1, 3))
+
+
+@dataclasses.dataclass
+class Markers:
+    offs: torch.Tensor  # (np+1,) int64
+    x: torch.Tensor
+    y: torch.Tensor
+    z: torch.Tensor
+    pid: torch.Tensor   # int32
+    dv: torch.Tensor    # (np,)
+
+    @property
+    def nl(self):
+        return int(self.x.shape[0])
+
+    def xyz(self):
+        return torch.stack([self.x, self.y, self.z], dim=1)
+
+    @property
+    def c(self):
+        s = IbMarkers()
+        s.nl = self.nl
+        s.offs = _ptr(self.offs)
+        s.x, s.y, s.z = _ptr(self.x), _ptr(self.y), _ptr(self.z)
+        s.pid, s.dv = _ptr(self.pid), _ptr(self.dv)
+        return s
+
+
+def markers_from(x, y, z, pid, dv, offs, device=None) -> Markers:
+    """Wrap existing marker arrays (host or device) as device tensors."""
+    dev = _dev(device)
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt).contiguous()
+    return Markers(t(offs, torch.int64), t(x, torch.float64), t(y, torch.float64),
+                   t(z, torch.float64), t(pid, torch.int32), t(dv, torch.float64))
+
+
+@dataclasses.dataclass
+class Buckets:
+    cell: torch.Tensor
+    tileid: torch.Tensor
+    base: torch.Tensor
+    perm: torch.Tensor
+    tile_offs: torch.Tensor
+    src_offs: torch.Tensor
+    src_idx: torch.Tensor
+    flag: torch.Tensor
+
+    @property
+    def c(self):
+        s = IbBuckets()
+        s.cell, s.tileid, s.base, s.perm = (_ptr(self.cell), _ptr(self.tileid),
+                                            _ptr(self.base), _ptr(self.perm))
+        s.tile_offs, s.src_offs, s.src_idx = (_ptr(self.tile_offs), _ptr(self.src_offs),
+                                              _ptr(self.src_idx))
+        s.src_cap = int(self.src_idx.numel())
+        s.flag = _ptr(self.flag)
+        return s
+
+    def nsrc(self):
+        return int(self.src_offs[-1].item())
+
+
+# ---------------------------------------------------------------- a1 / a3
+
+def count_markers(d, h) -> np.ndarray:
+    d = np.ascontiguousarray(np.asarray(d, dtype=np.float64))
+    offs = np.zeros(d.shape[0] + 1, dtype=np.int64)
+    _check(_count_markers(d.shape[0], d.ctypes.data, float(h), offs.ctypes.data),
+           "ib_count_markers")
+    return offs
+
+
+def build_markers_into(level: DeviceLevel, parts: Particles, m: Markers) -> Markers:
+    """Rebuild the markers of ``parts`` into existing arrays (counts unchanged)."""
+    lc, pc, mc = level.c, parts.c, m.c
+    _check(_build_markers(C.byref(lc), C.byref(pc), C.byref(mc), _stream()), "ib_build_markers")
+    return m
+
+
+def build_markers(level: DeviceLevel, parts: Particles) -> Markers:
+    offs_h = count_markers(parts.d.cpu().numpy(), level.h)
+    dev = parts.d.device
+    nl = int(offs_h[-1])
+    m = Markers(torch.as_tensor(offs_h, device=dev),
+                torch.empty(nl, dtype=torch.float64, device=dev),
+                torch.empty(nl, dtype=torch.float64, device=dev),
+                torch.empty(nl, dtype=torch.float64, device=dev),
+                torch.empty(nl, dtype=torch.int32, device=dev),
+                torch.empty(parts.np, dtype=torch.float64, device=dev))
+    lc, pc, mc = level.c, parts.c, m.c
+    _check(_build_markers(C.byref(lc), C.byref(pc), C.byref(mc), _stream()), "ib_build_markers")
+    return m
+
+
+def desired_velocity(parts: Particles, m: Markers, dtype=torch.float64) -> torch.Tensor:
+    Ud = torch.empty((m.nl, 3), dtype=dtype, device=m.x.device)
+    pc, mc = parts.c, m.c
+    _check(_desired_velocity(C.byref(pc), C.byref(mc), _prec_of(dtype), _ptr(Ud), _stream()),
+           "ib_desired_velocity")
+    return Ud
+
+
+# ---------------------------------------------------------------- a2
+
+def bucket_into(level: DeviceLevel, m: Markers, delta: int, b: Buckets) -> Buckets:
+    """Re-bucket into existing arrays and workspace (no allocation)."""
+    lc, mc, bc = level.c, m.c, b.c
+    _check(_bucket(C.byref(lc), C.byref(mc), int(delta), C.byref(bc), _ptr(b._ws),
+                   int(b._ws.numel()), _stream()), "ib_bucket")
+    return b
+
+
+def bucket(level: DeviceLevel, m: Markers, delta: int, src_cap=None) -> Buckets:
+    dev = m.x.device
+    nl = m.nl
+    T = level.ntiles
+    cap = 8 * nl if src_cap is None else int(src_cap)
+    i32 = dict(dtype=torch.int32, device=dev)
+    b = Buckets(torch.empty(nl, **i32), torch.empty(nl, **i32), torch.empty((nl, 3), **i32),
+                torch.empty(nl, **i32), torch.empty(T + 1, **i32), torch.empty(T + 1, **i32),
+                torch.empty(max(cap, 1), **i32), torch.zeros(2, **i32))
+    if cap == 0:
+        b.src_idx = b.src_idx[:0]
+    lc, mc = level.c, m.c
+    nbytes = _bucket_ws(C.byref(lc), nl)
+    ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
+    bc = b.c
+    _check(_bucket(C.byref(lc), C.byref(mc), int(delta), C.byref(bc), _ptr(ws), int(nbytes),
+                   _stream()), "ib_bucket")
+    b._ws = ws  # keep alive until the stream has run
+    return b
+
+
+# ---------------------------------------------------------------- a4 / a6
+
+def interp(level: DeviceLevel, m: Markers, delta: int, u: torch.Tensor) -> torch.Tensor:
+    U = torch.empty((m.nl, 3), dtype=u.dtype, device=u.device)
+    lc, mc = level.c, m.c
+    _check(_interp(C.byref(lc), C.byref(mc), int(delta), _prec_of(u.dtype), _ptr(u), _ptr(U),
+                   _stream()), "ib_interp")
+    return U
+
+
+def spread(level: DeviceLevel, m: Markers, b: Buckets, delta: int, F: torch.Tensor,
+           out: torch.Tensor = None) -> torch.Tensor:
+    f = out if out is not None else torch.zeros(level.field_shape(), dtype=F.dtype,
+                                                device=F.device)
+    lc, mc, bc = level.c, m.c, b.c
+    _check(_spread(C.byref(lc), C.byref(mc), C.byref(bc), int(delta), _prec_of(F.dtype),
+                   _ptr(F), _ptr(f), _stream()), "ib_spread")
+    return f
+
+
+# ---------------------------------------------------------------- a3-a9
+
+class Plan:
+    """Kernel width, precision and path of the multidirect loop."""
+
+    def __init__(self, delta: int, dtype=torch.float32, path: int = IB_PATH_AUTO,
+                 bucket_width: int = 0, spread_wgs_per_cu: int = 0, use_graph: bool = False):
+        self.delta = int(delta)
+        self.dtype = dtype
+        h = _p()
+        _check(_plan_create(C.byref(h), self.delta, _prec_of(dtype), int(path),
+                            int(bucket_width), int(spread_wgs_per_cu), int(bool(use_graph))),
+               "ib_plan_create")
+        self._h = h
+        self._ws = None
+
+    def query(self):
+        out = np.zeros(4, dtype=np.int32)
+        _check(_plan_query(self._h, out.ctypes.data), "ib_plan_query")
+        return dict(path=int(out[0]), bucket_width=int(out[1]), spread_wgs_per_cu=int(out[2]),
+                    use_graph=int(out[3]))
+
+    def profile(self, enable: bool = True):
+        _check(_plan_profile(self._h, int(bool(enable))), "ib_plan_profile")
+
+    def profile_read(self, reset: bool = True) -> dict:
+        ms = np.zeros(len(PROF_CLASSES), dtype=np.float64)
+        calls = np.zeros(len(PROF_CLASSES), dtype=np.int64)
+        _check(_plan_profile_read(self._h, ms.ctypes.data, calls.ctypes.data, int(bool(reset))),
+               "ib_plan_profile_read")
+        return {k: (float(ms[i]), int(calls[i])) for i, k in enumerate(PROF_CLASSES)}
+
+    def workspace_bytes(self, level: DeviceLevel, nl: int, ns: int) -> int:
+        lc = level.c
+        return int(_ws_bytes(self._h, C.byref(lc), int(nl), int(ns)))
+
+    def workspace(self, level, nl, ns, device):
+        nb = self.workspace_bytes(level, nl, ns)
+        if self._ws is None or self._ws.numel() < nb or self._ws.device != device:
+            self._ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+        return self._ws
+
+    def multidirect_force(self, level: DeviceLevel, parts: Particles, m: Markers, b: Buckets,
+                          ns: int, dt: float, u0: torch.Tensor, ustar: torch.Tensor = None,
+                          f: torch.Tensor = None, F: torch.Tensor = None, resid=None,
+                          Fhist=None, want_f: bool = True):
+        dev = u0.device
+        if u0.dtype != self.dtype:
+            raise TypeError("u0 dtype differs from the plan precision")
+        if ustar is None:
+            ustar = torch.empty_like(u0)
+        if f is None and want_f:
+            f = torch.empty_like(u0)
+        if F is None:
+            F = torch.empty((m.nl, 3), dtype=u0.dtype, device=dev)
+        ws = self.workspace(level, m.nl, ns, dev)
+        lc, pc, mc, bc = level.c, parts.c, m.c, b.c
+        _check(_multidirect(self._h, C.byref(lc), C.byref(pc), C.byref(mc), C.byref(bc),
+                            int(ns), float(dt), _ptr(u0), _ptr(ustar), _ptr(f), _ptr(F),
+                            _ptr(resid), _ptr(Fhist), _ptr(ws), int(ws.numel()), _stream()),
+               "ib_multidirect_force")
+        return ustar, f, F
+
+    def backward(self, level, parts, m, b, ns, dt, u0, Fhist, g_ustar=None, g_f=None,
+                 g_F=None):
+        dev = u0.device
+        lc = level.c
+        nb = int(_bwd_ws(self._h, C.byref(lc), m.nl))
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+        g_u0 = torch.zeros_like(u0)
+        g_up = torch.zeros((parts.np, 3), dtype=torch.float64, device=dev)
+        g_om = torch.zeros((parts.np, 3), dtype=torch.float64, device=dev)
+        g_X = torch.zeros((m.nl, 3), dtype=torch.float64, device=dev)
+        pc, mc, bc = parts.c, m.c, b.c
+        _check(_backward(self._h, C.byref(lc), C.byref(pc), C.byref(mc), C.byref(bc), int(ns),
+                         float(dt), _ptr(u0), _ptr(Fhist), _ptr(g_ustar), _ptr(g_f), _ptr(g_F),
+                         _ptr(g_u0), _ptr(g_up), _ptr(g_om), _ptr(g_X), _ptr(ws), nb,
+                         _stream()), "ib_multidirect_backward")
+        return g_u0, g_up, g_om, g_X
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                _plan_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- a10
+
+def particle_reductions(level: DeviceLevel, parts: Particles, m: Markers, F: torch.Tensor,
+                        u: torch.Tensor, flag: torch.Tensor = None) -> torch.Tensor:
+    out = torch.empty((parts.np, 12), dtype=torch.float64, device=u.device)
+    lc, pc, mc = level.c, parts.c, m.c
+    _check(_reductions(C.byref(lc), C.byref(pc), C.byref(mc), _prec_of(u.dtype), _ptr(F), _ptr(u),
+                       _ptr(out), _ptr(flag), _stream()), "ib_particle_reductions")
+    return out
+
+
+def version() -> int:
+    return int(_version())

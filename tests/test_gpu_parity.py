@@ -1,0 +1,273 @@
+"""GPU parity of every hot-path step against the FP64 oracle (through the C ABI).
+
+Tolerances: integer outputs bit-exact; FP64 results within 1e-12 relative
+(normwise over the covered cells or markers); FP32 results within 1e-5
+relative of the oracle run on the same FP64 inputs; per-particle sums within
+tol * sum |summands| (they cancel around a sphere).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import Case, announce, gpu_device, rel, small_workload
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return gpu_device()
+
+
+def _cases():
+    return [
+        ("small32_P4", lambda: small_workload(32, 16, 4, 3, 1)),
+        ("small32_P3", lambda: small_workload(32, 16, 3, 2, 2)),
+        ("small64_partial_P4", lambda: small_workload(64, 16, 4, 3, 3, cover_all=False, k=5)),
+        ("sphere1_64", lambda: W.config(1, 0)),
+    ]
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def test_build_markers(dev, name, mk):
+    import torch
+
+    import oracle as O
+    import paper_2408_14140_amd as ibx
+    announce(f"build_markers {name}")
+    wl = mk()
+    c = Case(wl, dev)
+    m = ibx.build_markers(c.dl, c.parts)
+    torch.cuda.synchronize()
+    assert np.array_equal(m.offs.cpu().numpy(), c.m.offs)
+    assert np.array_equal(m.pid.cpu().numpy(), c.m.pid)
+    assert rel(m.dv.cpu().numpy(), c.m.dv) <= 1e-15
+    X = m.xyz().cpu().numpy()
+    assert np.max(np.abs(X - c.m.xyz())) <= 4e-16 * 4
+    assert ibx.count_markers(wl.d, wl.level.h).tolist() == O.count_markers(wl.d, wl.level.h).tolist()
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def test_bucket_bit_exact(dev, name, mk):
+    import torch
+
+    import oracle as O
+    import paper_2408_14140_amd as ibx
+    announce(f"bucket {name}")
+    wl = mk()
+    c = Case(wl, dev)
+    ref = O.bucket(c.lev, wl.delta, c.m)
+    b = ibx.bucket(c.dl, c.dm, wl.delta)
+    torch.cuda.synchronize()
+    assert ref["flagged"] == 0 and int(b.flag[0].item()) == 0 and int(b.flag[1].item()) == 0
+    for k in ("cell", "base", "perm", "tile_offs", "src_offs"):
+        got = getattr(b, k if k != "tile" else "tileid").cpu().numpy()
+        assert np.array_equal(got, ref[k]), k
+    assert np.array_equal(b.tileid.cpu().numpy(), ref["tile"])
+    ns = int(ref["src_offs"][-1])
+    assert np.array_equal(b.src_idx[:ns].cpu().numpy(), ref["src_idx"])
+
+
+def test_bucket_flags_uncovered_support(dev):
+    import torch
+
+    import oracle as O
+    import paper_2408_14140_amd as ibx
+    announce("bucket flag")
+    n, box = 32, 16
+    cov = np.ones((2, 2, 2), bool)
+    cov[0, 0, 1] = False
+    lev = W.make_level((n, n, n), 1.0 / n, box=box, ngrow=2, covered=cov)
+    m = O.build_markers([[0.45, 0.25, 0.25], [0.25, 0.25, 0.75]], [6 / n, 5 / n], 1 / n)
+    ref = O.bucket(lev, 4, m)
+    dl = ibx.device_level(lev, dev)
+    dm = ibx.markers_from(m.x, m.y, m.z, m.pid, m.dv, m.offs, dev)
+    b = ibx.bucket(dl, dm, 4)
+    torch.cuda.synchronize()
+    assert ref["flagged"] > 0
+    assert int(b.flag[0].item()) == ref["flagged"]
+    assert np.array_equal(b.perm.cpu().numpy(), ref["perm"])
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_interp_and_spread(dev, name, mk, dtype):
+    import torch
+
+    import oracle as O
+    import paper_2408_14140_amd as ibx
+    announce(f"interp/spread {name} {dtype}")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    tol = TOL64 if dtype == "f64" else TOL32
+    wl = mk()
+    c = Case(wl, dev)
+    rng = np.random.default_rng(7)
+    F = rng.normal(size=(c.m.nl, 3))
+    Uref = O.interp(c.g, wl.delta, c.m, wl.u0)
+    fref = O.spread(c.g, wl.delta, c.m, F)
+    b = ibx.bucket(c.dl, c.dm, wl.delta)
+    U = ibx.interp(c.dl, c.dm, wl.delta, c.u0_boxes(tdt))
+    f = ibx.spread(c.dl, c.dm, b, wl.delta, torch.as_tensor(F, device=dev).to(tdt))
+    torch.cuda.synchronize()
+    assert rel(U.cpu().numpy(), Uref) <= tol
+    assert c.field_rel(f, fref) <= tol
+
+
+def _run(c, dtype, path, resid=True, inplace=False, ns=None, fhist=False, **kw):
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    wl = c.wl
+    ns = wl.ns if ns is None else ns
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    b = ibx.bucket(c.dl, c.dm, wl.delta)
+    plan = ibx.Plan(wl.delta, tdt, path, **kw)
+    u0 = c.u0_boxes(tdt)
+    r = torch.zeros(ns + 1, dtype=torch.float64, device=c.dev) if resid else None
+    Fh = torch.zeros((max(ns, 1), c.m.nl, 3), dtype=tdt, device=c.dev) if fhist else None
+    ustar, f, F = plan.multidirect_force(c.dl, c.parts, c.dm, b, ns, wl.dt, u0,
+                                         ustar=u0 if inplace else None, resid=r, Fhist=Fh)
+    torch.cuda.synchronize()
+    return ustar, f, F, r, Fh, b
+
+
+PATHS = [("f64", 1), ("f64", 2), ("f32", 2), ("f32", 1)]
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("dtype,path", PATHS, ids=[f"{d}-{'plain' if p == 1 else 'batched'}" for d, p in PATHS])
+def test_multidirect_matches_oracle(dev, name, mk, dtype, path):
+    import oracle as O
+    announce(f"multidirect {name} {dtype} path={path}")
+    wl = mk()
+    c = Case(wl, dev)
+    ref = O.multidirect(c.g, wl.delta, wl.ns, wl.dt, c.m, wl.xc, wl.up, wl.om, wl.u0,
+                        history=True)
+    ustar, f, F, r, Fh, _ = _run(c, dtype, path, fhist=True)
+    tol = TOL64 if dtype == "f64" else TOL32
+    assert rel(F.cpu().numpy(), ref["F"]) <= tol
+    assert c.field_rel(f, ref["f"]) <= tol
+    assert c.field_rel(ustar, ref["ustar"]) <= tol
+    assert rel(Fh.cpu().numpy(), ref["Fhist"]) <= tol
+    assert np.max(np.abs(r.cpu().numpy() - ref["resid"])) <= tol * ref["resid"][0] * 10
+
+
+def test_batched_in_place_and_deterministic(dev):
+    import torch
+    announce("in-place + determinism")
+    wl = small_workload(64, 16, 4, 3, 3, cover_all=False, k=5)
+    c = Case(wl, dev)
+    a = _run(c, "f32", 2)
+    b = _run(c, "f32", 2)
+    # fields: valid cells of covered boxes only (ghost cells are never written)
+    m = np.broadcast_to(c.mask, (3,) + c.mask.shape)
+    for x, y in zip(a[:2], b[:2]):
+        assert np.array_equal(c.to_global(x)[m], c.to_global(y)[m])
+    for x, y in zip(a[2:4], b[2:4]):
+        assert torch.equal(x, y)
+    ip = _run(c, "f32", 2, inplace=True)
+    assert np.array_equal(c.to_global(ip[0])[m], c.to_global(a[0])[m])
+    assert torch.equal(ip[2], a[2])
+
+
+@pytest.mark.parametrize("ns", [0, 1])
+@pytest.mark.parametrize("dtype,path", PATHS, ids=[f"{d}-{p}" for d, p in PATHS])
+def test_short_loops(dev, ns, dtype, path):
+    import oracle as O
+    announce(f"short loop ns={ns} {dtype} {path}")
+    wl = small_workload(32, 16, 4, 3, 1)
+    c = Case(wl, dev)
+    ref = O.multidirect(c.g, wl.delta, ns, wl.dt, c.m, wl.xc, wl.up, wl.om, wl.u0)
+    ustar, f, F, r, _, _ = _run(c, dtype, path, ns=ns)
+    tol = TOL64 if dtype == "f64" else TOL32
+    assert rel(F.cpu().numpy(), ref["F"]) <= tol
+    assert c.field_rel(ustar, ref["ustar"]) <= tol
+    got_f = c.to_global(f)
+    m = np.broadcast_to(c.mask, got_f.shape)
+    assert np.max(np.abs(got_f[m] - ref["f"][m])) <= tol * max(1.0, np.abs(ref["f"]).max())
+    assert abs(r.cpu().numpy()[0] - ref["resid"][0]) <= tol * ref["resid"][0] * 10
+
+
+def test_no_markers(dev):
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    announce("no particles")
+    wl = small_workload(32, 16, 4, 3, 1)
+    lev = wl.level
+    dl = ibx.device_level(lev, dev)
+    parts = ibx.particles(np.zeros((0, 3)), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)), dev)
+    dm = ibx.markers_from(np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0, np.int32),
+                          np.zeros(0), np.zeros(1, np.int64), dev)
+    b = ibx.bucket(dl, dm, 4)
+    for dtype, path in PATHS:
+        tdt = torch.float64 if dtype == "f64" else torch.float32
+        plan = ibx.Plan(4, tdt, path)
+        u0 = torch.as_tensor(W.to_boxes(wl.u0, lev, fill=np.nan), device=dev).to(tdt)
+        r = torch.full((4,), -1.0, dtype=torch.float64, device=dev)
+        ustar, f, F = plan.multidirect_force(dl, parts, dm, b, 3, wl.dt, u0, resid=r)
+        torch.cuda.synchronize()
+        us = W.from_boxes(ustar.double().cpu().numpy(), lev)
+        assert np.array_equal(us, W.from_boxes(u0.double().cpu().numpy(), lev))
+        assert float(np.nanmax(np.abs(W.from_boxes(f.double().cpu().numpy(), lev)))) == 0.0
+        assert torch.all(r == 0)
+
+
+def test_box_tiling_invariance(dev):
+    """32^3 boxes and one 64^3 box hold the same grid: results agree."""
+    import torch
+    announce("box tiling invariance")
+    wl = small_workload(64, 16, 4, 3, 5, cover_all=True, k=4)
+    outs = []
+    for box in (64, 32, 16):
+        lev = W.make_level(wl.level.n, wl.level.h, box=box, ngrow=2 if box < 64 else 0)
+        w2 = W.Workload(wl.name, lev, wl.delta, wl.ns, wl.dt, wl.xc, wl.d, wl.up, wl.om, wl.u0)
+        c = Case(w2, dev)
+        ustar, f, F, _, _, _ = _run(c, "f64", 2, resid=False)
+        outs.append((c.to_global(ustar), F.cpu().numpy()))
+    for u, F in outs[1:]:
+        assert rel(u, outs[0][0]) <= 1e-14
+        assert rel(F, outs[0][1]) <= 1e-14
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_particle_reductions(dev, name, mk, dtype):
+    import torch
+
+    import oracle as O
+    import paper_2408_14140_amd as ibx
+    announce(f"reductions {name} {dtype}")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    wl = mk()
+    c = Case(wl, dev)
+    rng = np.random.default_rng(9)
+    F = rng.normal(size=(c.m.nl, 3))
+    if dtype == "f32":
+        F = F.astype(np.float32).astype(np.float64)
+        u_in = wl.u0.astype(np.float32).astype(np.float64)
+    else:
+        u_in = wl.u0
+    ref = O.particle_reductions(c.g, c.m, wl.xc, wl.d, F, u_in)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    u = torch.as_tensor(W.to_boxes(u_in, c.lev, fill=np.nan), device=dev).to(tdt)
+    out = ibx.particle_reductions(c.dl, c.parts, c.dm, torch.as_tensor(F, device=dev).to(tdt),
+                                  u, flag)
+    torch.cuda.synchronize()
+    assert int(flag.item()) == 0
+    got = out.cpu().numpy()
+    # scale: a bound on sum |summands| per particle and quantity
+    absref = O.particle_reductions(c.g, c.m, wl.xc, wl.d, np.abs(F), np.abs(u_in))
+    Rmax = 0.5 * wl.d.max() + 3 * c.lev.h
+    scale = np.empty_like(absref)
+    scale[:, 0:3] = absref[:, 0:3]
+    scale[:, 3:6] = absref[:, 0:3].sum(axis=1, keepdims=True) * Rmax
+    scale[:, 6:9] = absref[:, 6:9]
+    scale[:, 9:12] = absref[:, 6:9].sum(axis=1, keepdims=True) * Rmax
+    assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-300)

@@ -139,11 +139,14 @@ def test_reverse_sweep_matches_central_differences(oracle_mod, P, with_ustar):
     def mk(X):
         return oracle_mod.Markers(X[:, 0], X[:, 1], X[:, 2], m0.pid, m0.dv, m0.offs)
 
+    # markers within 10 steps of a kernel join (jump of phi'') are held fixed
+    keep = (np.abs(s - np.round(s)).min(axis=1) > 10 * 4 * eps / h).astype(float)
     for _ in range(20):
         v = {k: rng.normal(size=s) for k, s in
              (("u0", u0.shape), ("up", up.shape), ("om", om.shape), ("X", X0.shape))}
         for k in v:
             v[k] /= np.sqrt((v[k] ** 2).mean())
+        v["X"] = np.clip(v["X"], -4, 4) * keep[:, None]
         Lp, _ = _loss_and_grads(oracle_mod, g, P, ns, dt, mk(X0 + eps * v["X"]), xc,
                                 up + eps * v["up"], om + eps * v["om"], u0 + eps * v["u0"],
                                 wts, gus)
