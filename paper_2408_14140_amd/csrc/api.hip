@@ -97,8 +97,9 @@ static BatchedCfg cfg_of(const ib_plan* pl)
     int per_cu = 24 / (waves_per_wg > 0 ? waves_per_wg : 1);
     if (per_cu < 1)
         per_cu = 1;
-    c.grid_i = pl->ncu * per_cu;
-    c.grid_s = pl->ncu * pl->spread_wgs_per_cu;
+    // multiples of 8: the tile kernels split their work lists over the 8 XCDs
+    c.grid_i = (pl->ncu * per_cu + 7) / 8 * 8;
+    c.grid_s = (pl->ncu * pl->spread_wgs_per_cu + 7) / 8 * 8;
     c.prof = pl->prof;
     return c;
 }
@@ -125,7 +126,7 @@ extern "C" int ib_plan_create(ib_plan** plan, ib_delta delta, ib_prec prec, ib_p
         (path != IB_PATH_AUTO && path != IB_PATH_PLAIN && path != IB_PATH_BATCHED))
         return IB_EINVAL;
     if (bucket_width == 0)
-        bucket_width = 128;
+        bucket_width = 256;
     if (bucket_width != 64 && bucket_width != 128 && bucket_width != 256)
         return IB_EINVAL;
     if (spread_wgs_per_cu == 0)

@@ -11,21 +11,21 @@
 // This is the recurrence of Algorithm 1 with the correction substituted into
 // the next interpolation; results equal the literal loop up to rounding.
 //
-// Markers are processed in bucket order (sorted by owning 8^3 tile) from
-// structure-of-arrays copies: stencil base relative to the owning cell,
-// P weights per axis, dV/h^3, U^d, D and F.
+// Markers are processed in bucket order (sorted by owning 8^3 tile).  Each
+// marker's stencil is precomputed once per call into a 64-byte (FP32) record
+// -- stencil base relative to its owning tile's frame, P weights per axis,
+// dV/h^3 -- and its force is kept as one 4-vector, so the spreading kernel's
+// gathers of a source touch one or two cache lines.  U^d and D stay as
+// structure-of-arrays (read only by the marker's own interpolation item).
 //
-// Kernels (persistent workgroups striding over device-side work lists):
-//   interp   work item = up to bw markers of one tile; the item's tile plus a
-//            ceil(P/2)-cell halo of the field (u0 or G) is staged in LDS, then
-//            one thread per marker sums its P^3 stencil from LDS.
-//   spread   work item = one tile with a non-empty source list; one wavefront
-//            accumulates every source's stencil cells that fall in the tile
-//            into an LDS tile with LDS atomics issued by that single wave (the
-//            order of additions is the fixed program and lane order, so the
-//            result is reproducible run to run), then stores the tile with
-//            coalesced writes: to the compact G slots, or in the last
-//            iteration to the caller's f and ustar.  No float atomics reach HBM.
+// Kernels (persistent workgroups striding over device-side work lists; see
+// tiles.h for the two hot ones):
+//   interp   work item = up to bw markers of one tile; tile + halo of u0 or G
+//            staged in LDS, one thread per marker.
+//   spread   work item = one tile with a non-empty source list; one wavefront,
+//            lane = (y, z) row of the tile accumulated in registers.  Result
+//            to the compact per-tile G slots, or in the last iteration to the
+//            caller's f and ustar.  No float atomics anywhere.
 #include "paths.h"
 
 namespace ibx {
@@ -41,14 +41,31 @@ struct Item {
     int32_t tile, start, count, pad;
 };
 
-template <typename T, int P>
-struct MarkerSoA {
-    int32_t* rb;   // [3][n] stencil base relative to the owning cell's tile frame
-    T* rw;         // [3P][n] weights
-    T* rs;         // [n] dV / h^3
-    T* ud;         // [3][n] U^d
-    T* d;          // [3][n] D = (U^d - J u0)/dt
-    T* fs;         // [3][n] F^m
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using type = float4;
+};
+template <>
+struct Vec4<double> {
+    using type = double4;
+};
+
+// Stencil record of one marker (sorted order).
+template <typename T>
+struct alignas(sizeof(T) == 4 ? 64 : 128) Geo {
+    T w[3][4];        // kernel weights per axis (first P used)
+    T rs;             // dV / h^3
+    int32_t rb[3];    // stencil base, owning-tile frame: wrapped owning cell + (b - floor(s))
+};
+
+template <typename T>
+struct MarkerData {
+    Geo<T>* geo;                      // [n]
+    typename Vec4<T>::type* f4;       // [n] F^m (x, y, z, 0)
+    T* ud;                            // [3][n] U^d
+    T* d;                             // [3][n] D = (U^d - J u0)/dt
 };
 
 __device__ inline void tile_coords(const Grid& g, int t, int* lo)
@@ -66,13 +83,14 @@ k_prep(Grid g, int64_t nl, const double* __restrict__ x, const double* __restric
        const double* __restrict__ z, const int32_t* __restrict__ pid,
        const double* __restrict__ dv, const int32_t* __restrict__ perm,
        const double* __restrict__ xc, const double* __restrict__ up,
-       const double* __restrict__ om, MarkerSoA<T, P> s)
+       const double* __restrict__ om, MarkerData<T> s)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nl)
         return;
     const int64_t l = perm[i];
     const double X[3] = {x[l], y[l], z[l]};
+    Geo<T> r;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double sa = grid_coord(g, a, X[a]);
@@ -80,13 +98,14 @@ k_prep(Grid g, int64_t nl, const double* __restrict__ x, const double* __restric
         const int b = axis_weights<T, P>(sa, w);
         const int fl = (int)floor(sa);
         const int c = g.periodic[a] ? wrapi(fl, g.n[a]) : fl;
-        s.rb[a * nl + i] = c + (b - fl);
+        r.rb[a] = c + (b - fl);
 #pragma unroll
-        for (int o = 0; o < P; ++o)
-            s.rw[(a * P + o) * nl + i] = w[o];
+        for (int o = 0; o < 4; ++o)
+            r.w[a][o] = o < P ? w[o] : T(0);
     }
     const int p = pid[l];
-    s.rs[i] = (T)(dv[p] * g.inv_h3);
+    r.rs = (T)(dv[p] * g.inv_h3);
+    s.geo[i] = r;
     const double R0 = X[0] - xc[3 * p], R1 = X[1] - xc[3 * p + 1], R2 = X[2] - xc[3 * p + 2];
     const double w0 = om[3 * p], w1 = om[3 * p + 1], w2 = om[3 * p + 2];
     s.ud[0 * nl + i] = (T)(up[3 * p + 0] + (w1 * R2 - w2 * R1));
@@ -169,16 +188,17 @@ __global__ void k_fill_inactive(Grid g, const int32_t* __restrict__ slot, const 
 }
 
 template <typename T>
-__global__ void k_unsort(int64_t nl, const int32_t* __restrict__ perm, const T* __restrict__ fs,
-                         T* __restrict__ F)
+__global__ void k_unsort(int64_t nl, const int32_t* __restrict__ perm,
+                         const typename Vec4<T>::type* __restrict__ f4, T* __restrict__ F)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nl)
         return;
     const int64_t l = perm[i];
-    F[3 * l + 0] = fs[i];
-    F[3 * l + 1] = fs[nl + i];
-    F[3 * l + 2] = fs[2 * nl + i];
+    const typename Vec4<T>::type v = f4[i];
+    F[3 * l + 0] = v.x;
+    F[3 * l + 1] = v.y;
+    F[3 * l + 2] = v.z;
 }
 
 template <typename T>
@@ -191,33 +211,34 @@ __global__ void k_zero(int64_t n, T* a)
 
 // ------------------------------------------------------------------ host
 
-template <typename T, int P>
+template <typename T>
 struct BatchedWs {
-    MarkerSoA<T, P> s;
+    MarkerData<T> s;
     double* e2;
     double* part;
     Item* items;
     int32_t *item_cnt, *item_offs, *act, *act_offs, *active, *slot, *nitems, *nactive;
     T* G;
     void* scan;
+    int64_t max_items;
+    int64_t *nb_u, *nb_g;   // [item][27] element offsets of the neighbouring tiles
 };
 
-template <typename T, int P>
-static BatchedWs<T, P> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, size_t bytes,
-                                     size_t* need)
+template <typename T>
+static BatchedWs<T> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, size_t bytes,
+                                  size_t* need)
 {
     Carver cv(ws, bytes);
-    BatchedWs<T, P> w;
+    BatchedWs<T> w;
     const int64_t T_ = g.ntiles;
-    w.s.rb = cv.take<int32_t>(3 * nl);
-    w.s.rw = cv.take<T>(3 * P * nl);
-    w.s.rs = cv.take<T>(nl);
+    w.s.geo = cv.take<Geo<T>>(nl);
+    w.s.f4 = cv.take<typename Vec4<T>::type>(nl);
     w.s.ud = cv.take<T>(3 * nl);
     w.s.d = cv.take<T>(3 * nl);
-    w.s.fs = cv.take<T>(3 * nl);
     w.e2 = cv.take<double>(nl);
     w.part = cv.take<double>(sum_partials(nl));
-    w.items = cv.take<Item>(T_ + nl / bw + 1);
+    w.max_items = T_ + nl / bw + 1;
+    w.items = cv.take<Item>(w.max_items);
     w.item_cnt = cv.take<int32_t>(T_);
     w.item_offs = cv.take<int32_t>(T_);
     w.act = cv.take<int32_t>(T_);
@@ -228,10 +249,33 @@ static BatchedWs<T, P> carve_batched(const Grid& g, int64_t nl, int bw, void* ws
     w.nactive = cv.take<int32_t>(1);
     const int64_t max_active = T_ < 8 * nl ? T_ : 8 * nl;
     w.G = cv.take<T>((size_t)3 * TILE_CELLS * (max_active > 0 ? max_active : 1));
+    w.nb_u = cv.take<int64_t>(27 * w.max_items);
+    w.nb_g = cv.take<int64_t>(27 * w.max_items);
     w.scan = cv.take<char>(scan_workspace(T_));
     *need = cv.used;
     return w;
 }
+
+template <typename T, int P, int MODE>
+static void launch_interp(const BatchedCfg& cfg, hipStream_t st, const Grid& g, int64_t nl,
+                          double dt, const Item* items, const int32_t* nitems, const T* u0,
+                          const T* G, const int64_t* nbase, const MarkerData<T>& s, double* e2)
+{
+    if (cfg.bw == 64)
+        k_interp_tiles<T, P, MODE, 64><<<cfg.grid_i, 64, 0, st>>>(g, nl, dt, items, nitems, u0,
+                                                                 G, nbase, s, e2);
+    else if (cfg.bw == 128)
+        k_interp_tiles<T, P, MODE, 128><<<cfg.grid_i, 128, 0, st>>>(g, nl, dt, items, nitems,
+                                                                   u0, G, nbase, s, e2);
+    else
+        k_interp_tiles<T, P, MODE, 256><<<cfg.grid_i, 256, 0, st>>>(g, nl, dt, items, nitems,
+                                                                   u0, G, nbase, s, e2);
+}
+
+#define IBX_PROF_BEGIN(k) \
+    if (cfg.prof) cfg.prof->begin(k, st)
+#define IBX_PROF_END() \
+    if (cfg.prof) cfg.prof->end(st)
 
 template <typename T, int P>
 static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles* p,
@@ -242,10 +286,10 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     const int64_t nl = m->nl;
     const int64_t T_ = g.ntiles;
     size_t need = 0;
-    carve_batched<T, P>(g, nl, cfg.bw, nullptr, 0, &need);
+    carve_batched<T>(g, nl, cfg.bw, nullptr, 0, &need);
     if (!ws || ws_bytes < need)
         return IB_EWORKSPACE;
-    BatchedWs<T, P> w = carve_batched<T, P>(g, nl, cfg.bw, ws, ws_bytes, &need);
+    BatchedWs<T> w = carve_batched<T>(g, nl, cfg.bw, ws, ws_bytes, &need);
     const unsigned gm = (unsigned)((nl + 255) / 256 > 0 ? (nl + 255) / 256 : 1);
     const unsigned gt = (unsigned)((T_ + 255) / 256);
     const unsigned gfill = (unsigned)((T_ * TILE_CELLS + 255) / 256 < 65536
@@ -256,22 +300,26 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
             k_zero<double><<<1, 64, 0, st>>>(ns + 1, resid);
         return launch_status();
     }
-    if (cfg.prof) cfg.prof->begin(PK_PREP, st);
+    IBX_PROF_BEGIN(PK_PREP);
     k_prep<T, P><<<gm, 256, 0, st>>>(g, nl, m->x, m->y, m->z, m->pid, m->dv, b->perm, p->xc,
                                      p->up, p->om, w.s);
-    if (cfg.prof) cfg.prof->end(st);
-    if (cfg.prof) cfg.prof->begin(PK_LISTS, st);
+    IBX_PROF_END();
+    IBX_PROF_BEGIN(PK_LISTS);
     k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt, w.act);
     scan_exclusive(w.item_cnt, w.item_offs, T_, w.nitems, w.scan, st);
     scan_exclusive(w.act, w.act_offs, T_, w.nactive, w.scan, st);
     k_fill_lists<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs,
                                      w.act_offs, w.items, w.active, w.slot);
-    if (cfg.prof) cfg.prof->end(st);
+    {
+        const int64_t nth = 27 * w.max_items;
+        k_item_bases<<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(g, w.items, w.nitems, w.slot,
+                                                                    w.nb_u, w.nb_g);
+    }
+    IBX_PROF_END();
     double* e2 = resid ? w.e2 : nullptr;
-    if (cfg.prof) cfg.prof->begin(PK_INTERP_U0, st);
-    k_interp_tiles<T, P, 0><<<cfg.grid_i, cfg.bw, 0, st>>>(g, nl, dt, w.items, w.nitems, u0,
-                                                           w.G, w.slot, w.s, e2);
-    if (cfg.prof) cfg.prof->end(st);
+    IBX_PROF_BEGIN(PK_INTERP_U0);
+    launch_interp<T, P, 0>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_u, w.s, e2);
+    IBX_PROF_END();
     if (resid)
         sum_to(w.e2, nl, w.part, resid + 0, true, st);
     if (ns == 0) {
@@ -281,41 +329,42 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         return launch_status();
     }
     if (Fhist)
-        k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.fs, Fhist);
+        k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.f4, Fhist);
     for (int mi = 2; mi <= ns; ++mi) {
-        if (cfg.prof) cfg.prof->begin(PK_SPREAD, st);
+        IBX_PROF_BEGIN(PK_SPREAD);
         k_spread_tiles<T, P, 0><<<cfg.grid_s, 64, 0, st>>>(g, nl, dt, w.active, w.nactive,
                                                            b->src_offs, b->src_idx, w.s, w.G,
                                                            u0, ustar, f, 0);
-        if (cfg.prof) cfg.prof->end(st);
-        if (cfg.prof) cfg.prof->begin(PK_INTERP_G, st);
-        k_interp_tiles<T, P, 1><<<cfg.grid_i, cfg.bw, 0, st>>>(g, nl, dt, w.items, w.nitems, u0,
-                                                               w.G, w.slot, w.s, e2);
-        if (cfg.prof) cfg.prof->end(st);
+        IBX_PROF_END();
+        IBX_PROF_BEGIN(PK_INTERP_G);
+        launch_interp<T, P, 1>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_g, w.s, e2);
+        IBX_PROF_END();
         if (resid)
             sum_to(w.e2, nl, w.part, resid + (mi - 1), true, st);
         if (Fhist)
-            k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.fs,
+            k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.f4,
                                             Fhist + (int64_t)(mi - 1) * 3 * nl);
     }
-    if (cfg.prof) cfg.prof->begin(PK_SPREAD_FINAL, st);
+    IBX_PROF_BEGIN(PK_SPREAD_FINAL);
     k_spread_tiles<T, P, 1><<<cfg.grid_s, 64, 0, st>>>(g, nl, dt, w.active, w.nactive,
                                                        b->src_offs, b->src_idx, w.s, w.G, u0,
                                                        ustar, f, resid ? 1 : 0);
-    if (cfg.prof) cfg.prof->end(st);
+    IBX_PROF_END();
     if (f || ustar != u0) {
-        if (cfg.prof) cfg.prof->begin(PK_FILL, st);
+        IBX_PROF_BEGIN(PK_FILL);
         k_fill_inactive<T><<<gfill, 256, 0, st>>>(g, w.slot, u0, ustar, f, 0);
-        if (cfg.prof) cfg.prof->end(st);
+        IBX_PROF_END();
     }
     if (resid) {
-        k_interp_tiles<T, P, 2><<<cfg.grid_i, cfg.bw, 0, st>>>(g, nl, dt, w.items, w.nitems, u0,
-                                                               w.G, w.slot, w.s, w.e2);
+        IBX_PROF_BEGIN(PK_RESID);
+        launch_interp<T, P, 2>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_g, w.s,
+                               w.e2);
+        IBX_PROF_END();
         sum_to(w.e2, nl, w.part, resid + ns, true, st);
     }
-    if (cfg.prof) cfg.prof->begin(PK_UNSORT, st);
-    k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.fs, F);
-    if (cfg.prof) cfg.prof->end(st);
+    IBX_PROF_BEGIN(PK_UNSORT);
+    k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.f4, F);
+    IBX_PROF_END();
     return launch_status();
 }
 
@@ -323,9 +372,9 @@ size_t batched_workspace(const Grid& g, ib_prec prec, int64_t nl, const BatchedC
 {
     size_t need = 0;
     if (prec == IB_F64)
-        carve_batched<double, 4>(g, nl, cfg.bw, nullptr, 0, &need);
+        carve_batched<double>(g, nl, cfg.bw, nullptr, 0, &need);
     else
-        carve_batched<float, 4>(g, nl, cfg.bw, nullptr, 0, &need);
+        carve_batched<float>(g, nl, cfg.bw, nullptr, 0, &need);
     return need;
 }
 
@@ -334,6 +383,9 @@ int batched_multidirect(const Grid& g, int P, ib_prec prec, const BatchedCfg& cf
                         double dt, const void* u0, void* ustar, void* f, void* F, double* resid,
                         void* Fhist, void* ws, size_t ws_bytes, hipStream_t st)
 {
+    // a stencil must never reach the same tile from both sides of a periodic axis
+    if (g.n[0] < 2 * TILE || g.n[1] < 2 * TILE || g.n[2] < 2 * TILE)
+        return IB_EUNSUPPORTED;
     if (prec == IB_F64) {
         if (P == 3)
             return run_batched<double, 3>(g, cfg, p, m, b, ns, dt, (const double*)u0,

@@ -1,163 +1,182 @@
 // tiles.h -- the tile-staged interpolation and spreading kernels of the
-// batched path (included by batched.hip only).
+// batched path (included by batched.hip only).  Every axis of the grid has
+// at least 16 cells here, so a stencil never wraps onto its own tile.
 //
-// Interpolation (one work item = up to bw markers of one 8^3 tile): the
-// tile plus a ceil(P/2)-cell halo of the field is staged into LDS as one
-// 4-vector per cell.  Addresses come from small per-item tables (per-axis
-// wrapped coordinates and the ids of the <= 3 boxes or tiles the halo spans
-// along each axis), so staging issues independent loads with no division or
-// dependent lookups per cell.  One thread per marker then sums its P^3
-// stencil from LDS.
+// Interpolation (one work item = up to BW markers of one 8^3 tile, BW
+// threads): the tile plus a ceil(P/2)-cell halo of the field is staged into
+// three LDS planes.  For every item the element offsets of the 27 tiles
+// around it are precomputed once per loop (k_item_bases), so a halo cell's
+// address is base[(j-g+8)>>3 per axis] + its position in that tile: no
+// division, no dependent lookup.  Marker data is fetched before the staging
+// barrier so both streams of loads are in flight together.
 //
 // Spreading (one work item = one tile with a non-empty source list, one
-// wavefront): lane = source marker.  For every stencil offset each lane does
-// a plain LDS read-modify-write of its cell.  In one instruction two lanes
-// touch the same cell only if their markers share the stencil base cell, so
-// lanes are ranked among equal bases (ballot matching on the base key) and
-// rank classes are processed one after another.  No atomics; every cell's
-// sum is formed in a fixed order (source chunk, rank, offset), so results are
-// reproducible bit for bit.
+// wavefront): lane = one (y, z) row of the tile, holding its 8 cells x 3
+// components in registers.  Source records (tile-frame base, F dV/h^3, the
+// four x-weights and the sixteen y-z weight products) are staged 64 at a time
+// in LDS; every lane walks them in list order and, when its row lies in the
+// source's stencil, adds F w_yz w_x to its cells, the x-weight of each cell
+// selected on the scalar unit (zero outside the stencil).  No atomics and no
+// shared accumulator: each cell's sum is formed by one lane in a fixed order,
+// so the result is reproducible bit for bit.  The tile is then transposed
+// through LDS so the global stores are coalesced.
 #pragma once
 
-template <typename T>
-struct Vec4;
-template <>
-struct Vec4<float> {
-    using type = float4;
+// XCD-aware static work split.  Workgroups are dispatched to the 8 XCDs of
+// the device round-robin by id, and each XCD has its own L2.  The work list
+// (ordered by tile, so consecutive items are spatial neighbours) is cut into
+// 8 contiguous slabs and the workgroups of XCD x stride over slab x, so the
+// halo cells shared by neighbouring items are fetched into one L2, not eight.
+// The grid is a multiple of 8 workgroups.  Which workgroup computes an item
+// never changes the item's result.
+constexpr int NXCD = 8;
+
+struct Slab {
+    int begin, end, stride;
 };
-template <>
-struct Vec4<double> {
-    using type = double4;
-};
+
+__device__ inline Slab xcd_slab(int n)
+{
+    const int per = (n + NXCD - 1) / NXCD;
+    const int x = blockIdx.x % NXCD;
+    Slab r;
+    r.begin = x * per + (int)(blockIdx.x / NXCD);
+    r.end = min(n, (x + 1) * per);
+    r.stride = gridDim.x / NXCD;
+    return r;
+}
+
+// Element offsets of the 27 tiles around every interpolation item: [it][27]
+// for the velocity field (box layout) and for the per-tile force buffer.
+// -1 where the tile lies outside a bounded axis, in an uncovered box, or has
+// no force slot.
+__global__ void k_item_bases(Grid g, const Item* __restrict__ items,
+                             const int32_t* __restrict__ nitems, const int32_t* __restrict__ slot,
+                             int64_t* __restrict__ nb_u, int64_t* __restrict__ nb_g)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t it = q / 27;
+    if (it >= *nitems)
+        return;
+    const int k = (int)(q - it * 27);
+    int lo[3];
+    const int t = items[it].tile;
+    lo[0] = (t % g.nt[0]) * TILE;
+    lo[1] = ((t / g.nt[0]) % g.nt[1]) * TILE;
+    lo[2] = (t / (g.nt[0] * g.nt[1])) * TILE;
+    const int sel[3] = {k % 3, (k / 3) % 3, k / 9};
+    int c[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        int v = lo[a] + (sel[a] - 1) * TILE;
+        if (v < 0) {
+            if (g.periodic[a]) v += g.n[a]; else ok = false;
+        } else if (v >= g.n[a]) {
+            if (g.periodic[a]) v -= g.n[a]; else ok = false;
+        }
+        c[a] = v;
+    }
+    int64_t bu = -1, bg = -1;
+    if (ok) {
+        bu = cell_offset(g, c[0], c[1], c[2]);
+        const int sl = slot[(c[0] >> 3) + g.nt[0] * ((c[1] >> 3) + g.nt[1] * (c[2] >> 3))];
+        bg = sl >= 0 ? (int64_t)sl * 3 * TILE_CELLS : -1;
+    }
+    nb_u[q] = bu;
+    nb_g[q] = bg;
+}
 
 // mode 0: field = u0 (box layout): D = (U^d - J u0)/dt, F = D.
 // mode 1: field = G (slots): F += D - J G.
 // mode 2: field = G (slots): residual only.
 // e2 (nullable) receives dV |U^d - J u^(m)|^2 per marker.
-template <typename T, int P, int MODE>
-__global__ void __launch_bounds__(256)
+template <typename T, int P, int MODE, int BW>
+__global__ void __launch_bounds__(BW)
 k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                const int32_t* __restrict__ nitems, const T* __restrict__ u0,
-               const T* __restrict__ G, const int32_t* __restrict__ slot, MarkerSoA<T, P> s,
+               const T* __restrict__ G, const int64_t* __restrict__ nbase, MarkerData<T> s,
                double* __restrict__ e2)
 {
-    using V4 = typename Vec4<T>::type;
     constexpr int gh = Halo<P>::g, R = Halo<P>::R, R3 = Halo<P>::R3;
-    __shared__ V4 fld[R3];
-    __shared__ int32_t ax_off[3][R];   // per-axis part of the element offset
-    __shared__ int32_t ax_sel[3][R];   // which box / tile along the axis (-1: outside)
-    __shared__ int64_t nb_base[27];    // element offset of each (box or tile) or -1
+    constexpr int NPT = (R3 + BW - 1) / BW;
+    __shared__ T fld[3][R3];
+    __shared__ int64_t nb[27];
     const int n_items = *nitems;
     const double h3 = g.h * g.h * g.h;
     const int tid = threadIdx.x;
     const int64_t comp = MODE == 0 ? g.cstride : (int64_t)TILE_CELLS;
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int sy = MODE == 0 ? g.ext : TILE;
+    const int sz = MODE == 0 ? g.ext * g.ext : TILE * TILE;
+    const T* src = MODE == 0 ? u0 : G;
+    const Slab sl = xcd_slab(n_items);
+    for (int it = sl.begin; it < sl.end; it += sl.stride) {
         const Item item = items[it];
         int lo[3];
         tile_coords(g, item.tile, lo);
-        // per-axis tables
-        const int unit = MODE == 0 ? g.box : TILE;
-        if (tid < 3 * R) {
-            const int a = tid / R, j = tid - a * R;
-            // selector = number of unit changes along the axis up to cell j
-            int sel = 0, prev = 0, c = 0, ok = 1;
-            for (int q = 0; q <= j; ++q) {
-                c = lo[a] - gh + q;
-                ok = 1;
-                if (c < 0) {
-                    if (g.periodic[a]) c += g.n[a]; else ok = 0;
-                } else if (c >= g.n[a]) {
-                    if (g.periodic[a]) c -= g.n[a]; else ok = 0;
-                }
-                const int u = ok ? c / unit : -1;
-                if (q > 0 && u != prev)
-                    ++sel;
-                prev = u;
-            }
-            const int l = ok ? c - (c / unit) * unit : 0;
-            int off;
-            if (MODE == 0) {
-                const int e = l + g.ngrow;
-                off = a == 0 ? e : (a == 1 ? e * g.ext : e * g.ext * g.ext);
-            } else {
-                off = a == 0 ? l : (a == 1 ? l * TILE : l * TILE * TILE);
-            }
-            ax_off[a][j] = off;
-            ax_sel[a][j] = ok ? sel : -1;
-        }
-        __syncthreads();
-        if (tid < 27) {
-            const int sv[3] = {tid % 3, (tid / 3) % 3, tid / 9};
-            int u[3];
-            bool have = true;
-            for (int a = 0; a < 3; ++a) {
-                int j0 = -1;
-                for (int j = 0; j < R; ++j)
-                    if (ax_sel[a][j] == sv[a]) {
-                        j0 = j;
-                        break;
-                    }
-                if (j0 < 0) {
-                    have = false;
-                    u[a] = 0;
-                } else {
-                    int c = lo[a] - gh + j0;
-                    if (c < 0) c += g.n[a];
-                    else if (c >= g.n[a]) c -= g.n[a];
-                    u[a] = c / unit;
-                }
-            }
-            int64_t base = -1;
-            if (have) {
-                const int ux = u[0], uy = u[1], uz = u[2];
-                if (MODE == 0) {
-                    const int id = g.lut[ux + g.nb[0] * (uy + g.nb[1] * uz)];
-                    base = id >= 0 ? (int64_t)id * g.bstride : -1;
-                } else {
-                    const int sl = slot[ux + g.nt[0] * (uy + g.nt[1] * uz)];
-                    base = sl >= 0 ? (int64_t)sl * 3 * TILE_CELLS : -1;
-                }
-            }
-            nb_base[tid] = base;
-        }
-        __syncthreads();
-        // stage the tile and its halo
-        for (int q = tid; q < R3; q += blockDim.x) {
-            const int jx = q % R, jy = (q / R) % R, jz = q / (R * R);
-            const int sx = ax_sel[0][jx], sy = ax_sel[1][jy], sz = ax_sel[2][jz];
-            V4 v;
-            v.x = T(0);
-            v.y = T(0);
-            v.z = T(0);
-            v.w = T(0);
-            if ((sx | sy | sz) >= 0) {
-                const int64_t b = nb_base[sx + 3 * (sy + 3 * sz)];
-                if (b >= 0) {
-                    const int64_t off = b + ax_off[0][jx] + ax_off[1][jy] + ax_off[2][jz];
-                    const T* src = MODE == 0 ? u0 : G;
-                    v.x = src[off];
-                    v.y = src[off + comp];
-                    v.z = src[off + 2 * comp];
-                }
-            }
-            fld[q] = v;
-        }
-        __syncthreads();
-        if (tid < item.count) {
-            const int64_t i = item.start + tid;
-            int lb[3];
-            bool ok = true;
+        if (tid < 27)
+            nb[tid] = nbase[(int64_t)it * 27 + tid];
+        // this thread's marker: fetch its records while the halo is staged
+        const bool mine = tid < item.count;
+        const int64_t i = item.start + (mine ? tid : 0);
+        int lb[3];
+        T w[3][P];
+        T dd[3] = {T(0), T(0), T(0)};
+        T rs = T(0);
+        typename Vec4<T>::type fv;
+        fv.x = fv.y = fv.z = fv.w = T(0);
+        if (mine) {
+            const Geo<T> gm = s.geo[i];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                lb[a] = s.rb[a * nl + i] - lo[a] + gh;
-                ok &= (lb[a] >= 0 && lb[a] <= R - P);
-            }
-            T w[3][P];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
+                lb[a] = gm.rb[a] - lo[a] + gh;
 #pragma unroll
                 for (int o = 0; o < P; ++o)
-                    w[a][o] = s.rw[(a * P + o) * nl + i];
+                    w[a][o] = gm.w[a][o];
+            }
+            rs = gm.rs;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                dd[c] = MODE == 0 ? s.ud[c * nl + i] : s.d[c * nl + i];
+            if (MODE == 1)
+                fv = s.f4[i];
+        }
+        __syncthreads();
+        T v0[NPT], v1[NPT], v2[NPT];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int q = tid + k * BW;
+            v0[k] = T(0);
+            v1[k] = T(0);
+            v2[k] = T(0);
+            if (q < R3) {
+                const int jx = q % R, jy = (q / R) % R, jz = q / (R * R);
+                const int sel = ((jx - gh + TILE) >> 3) + 3 * (((jy - gh + TILE) >> 3) +
+                                                              3 * ((jz - gh + TILE) >> 3));
+                const int64_t b = nb[sel];
+                if (b >= 0) {
+                    const int64_t off = b + ((jx - gh) & 7) + sy * ((jy - gh) & 7) +
+                                        sz * ((jz - gh) & 7);
+                    v0[k] = src[off];
+                    v1[k] = src[off + comp];
+                    v2[k] = src[off + 2 * comp];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int q = tid + k * BW;
+            if (q < R3) {
+                fld[0][q] = v0[k];
+                fld[1][q] = v1[k];
+                fld[2][q] = v2[k];
+            }
+        }
+        __syncthreads();
+        if (mine) {
+            bool ok = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                ok &= (lb[a] >= 0 && lb[a] <= R - P);
             T acc0 = 0, acc1 = 0, acc2 = 0;
             if (ok) {
 #pragma unroll
@@ -169,38 +188,59 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
 #pragma unroll
                         for (int q = 0; q < P; ++q) {
                             const T wt = w[0][q] * wyz;
-                            const V4 v = fld[row + q];
-                            acc0 += v.x * wt;
-                            acc1 += v.y * wt;
-                            acc2 += v.z * wt;
+                            acc0 += fld[0][row + q] * wt;
+                            acc1 += fld[1][row + q] * wt;
+                            acc2 += fld[2][row + q] * wt;
                         }
                     }
             }
             const T acc[3] = {acc0, acc1, acc2};
             double err = 0.0;
             const T idt = (T)(1.0 / dt);
+            T nf[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (MODE == 0) {
-                    const T e = s.ud[c * nl + i] - acc[c];
-                    const T dd = e * idt;
-                    s.d[c * nl + i] = dd;
-                    s.fs[c * nl + i] = dd;
+                    const T e = dd[c] - acc[c];             // U^d - J u0
+                    const T dv = e * idt;
+                    s.d[c * nl + i] = dv;
+                    nf[c] = dv;
                     err += (double)e * (double)e;
                 } else {
-                    const T r = s.d[c * nl + i] - acc[c];   // = (U^d - J u^(m))/dt
-                    if (MODE == 1)
-                        s.fs[c * nl + i] = s.fs[c * nl + i] + r;
+                    const T r = dd[c] - acc[c];             // (U^d - J u^(m))/dt
+                    nf[c] = r;
                     const double e = (double)r * dt;
                     err += e * e;
                 }
             }
+            if (MODE == 0) {
+                typename Vec4<T>::type o;
+                o.x = nf[0];
+                o.y = nf[1];
+                o.z = nf[2];
+                o.w = T(0);
+                s.f4[i] = o;
+            } else if (MODE == 1) {
+                fv.x += nf[0];
+                fv.y += nf[1];
+                fv.z += nf[2];
+                s.f4[i] = fv;
+            }
             if (e2)
-                e2[i] = (double)s.rs[i] * h3 * err;
+                e2[i] = (double)rs * h3 * err;
         }
         __syncthreads();
     }
 }
+
+// Source record staged in LDS for the spreading kernel.
+template <typename T, int P>
+struct SrcRec {
+    T wxs[TILE];       // x weight of each x cell of the tile (0 outside the stencil)
+    T f[3];            // F dV / h^3
+    T wyz[P * P];      // wy[b] * wz[c] at [c * P + b]
+    int32_t base;      // (bx+4) | (by+4) << 8 | (bz+4) << 16, tile frame
+};
 
 // One wavefront per workgroup.  FINAL = 0: store the tile to its G slot.
 // FINAL = 1: store f (if any) and ustar = u0 + dt G on the tile; also the G
@@ -209,121 +249,116 @@ template <typename T, int P, int FINAL>
 __global__ void __launch_bounds__(64)
 k_spread_tiles(Grid g, int64_t nl, double dt, const int32_t* __restrict__ active,
                const int32_t* __restrict__ nactive, const int32_t* __restrict__ src_offs,
-               const int32_t* __restrict__ src_idx, MarkerSoA<T, P> s, T* __restrict__ G,
+               const int32_t* __restrict__ src_idx, MarkerData<T> s, T* __restrict__ G,
                const T* __restrict__ u0, T* __restrict__ ustar, T* __restrict__ f, int keep_g)
 {
-    using V4 = typename Vec4<T>::type;
-    __shared__ V4 acc[TILE_CELLS];
+    __shared__ SrcRec<T, P> rec[64];
+    __shared__ T tr[3][TILE_CELLS];
     const int lane = threadIdx.x;
-    const uint64_t lt = lane ? ((~0ull) >> (64 - lane)) : 0ull;
+    const int ly = lane & 7, lz = lane >> 3;
     const int n_act = *nactive;
-    for (int a = blockIdx.x; a < n_act; a += gridDim.x) {
+    const Slab sl = xcd_slab(n_act);
+    for (int a = sl.begin; a < sl.end; a += sl.stride) {
         const int t = active[a];
         int lo[3];
         tile_coords(g, t, lo);
-        for (int q = lane; q < TILE_CELLS; q += 64) {
-            V4 z;
-            z.x = T(0);
-            z.y = T(0);
-            z.z = T(0);
-            z.w = T(0);
-            acc[q] = z;
-        }
-        __syncthreads();
+        T acc[TILE][3];
+#pragma unroll
+        for (int x = 0; x < TILE; ++x)
+            acc[x][0] = acc[x][1] = acc[x][2] = T(0);
         const int s0 = src_offs[t], s1 = src_offs[t + 1];
         for (int sb = s0; sb < s1; sb += 64) {
             const int sidx = sb + lane;
-            const bool valid = sidx < s1;
-            const int64_t i = valid ? src_idx[sidx] : 0;
-            // tile-frame coordinates of the stencil cells and their in-tile masks
-            int cx[P], cy[P], cz[P];
-            int mx = 0, my = 0, mz = 0, key = 0;
-            T w[3][P];
-            T F0 = 0, F1 = 0, F2 = 0;
-            if (valid) {
-                int d[3];
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax)
-                    d[ax] = wrapi(s.rb[ax * nl + i] - lo[ax], g.n[ax]);
-#pragma unroll
-                for (int o = 0; o < P; ++o) {
-                    int x = d[0] + o, y = d[1] + o, zc = d[2] + o;
-                    if (x >= g.n[0]) x -= g.n[0];
-                    if (y >= g.n[1]) y -= g.n[1];
-                    if (zc >= g.n[2]) zc -= g.n[2];
-                    cx[o] = x;
-                    cy[o] = y * TILE;
-                    cz[o] = zc * TILE * TILE;
-                    mx |= (x < TILE) << o;
-                    my |= (y < TILE) << o;
-                    mz |= (zc < TILE) << o;
-                }
-                // base key: tile-frame base in [-3, 7] per axis, shifted to [0, 10]
+            if (sidx < s1) {
+                const int64_t i = src_idx[sidx];
+                const Geo<T> gm = s.geo[i];
+                const typename Vec4<T>::type Fv = s.f4[i];
+                int packed = 0, bx = 0;
 #pragma unroll
                 for (int ax = 0; ax < 3; ++ax) {
-                    const int b = d[ax] > g.n[ax] - P ? d[ax] - g.n[ax] : d[ax];
-                    key |= (b + 3) << (4 * ax);
+                    int b = gm.rb[ax] - lo[ax];
+                    if (b < -3) b += g.n[ax];
+                    else if (b > 7) b -= g.n[ax];
+                    packed |= (b + 4) << (8 * ax);
+                    if (ax == 0)
+                        bx = b;
                 }
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax)
-#pragma unroll
-                    for (int o = 0; o < P; ++o)
-                        w[ax][o] = s.rw[(ax * P + o) * nl + i];
-                const T sc = s.rs[i];
-                F0 = s.fs[0 * nl + i] * sc;
-                F1 = s.fs[1 * nl + i] * sc;
-                F2 = s.fs[2 * nl + i] * sc;
-            } else {
+                SrcRec<T, P> r;
+                r.base = packed;
+                r.f[0] = Fv.x * gm.rs;
+                r.f[1] = Fv.y * gm.rs;
+                r.f[2] = Fv.z * gm.rs;
+                T wx[P], wy[P], wz[P];
 #pragma unroll
                 for (int o = 0; o < P; ++o) {
-                    cx[o] = cy[o] = cz[o] = 0;
-                    w[0][o] = w[1][o] = w[2][o] = T(0);
+                    wx[o] = gm.w[0][o];
+                    wy[o] = gm.w[1][o];
+                    wz[o] = gm.w[2][o];
                 }
+#pragma unroll
+                for (int x = 0; x < TILE; ++x) {
+                    T wv = T(0);
+#pragma unroll
+                    for (int o = 0; o < P; ++o)
+                        wv = (x - bx == o) ? wx[o] : wv;
+                    r.wxs[x] = wv;
+                }
+#pragma unroll
+                for (int c = 0; c < P; ++c)
+#pragma unroll
+                    for (int b = 0; b < P; ++b)
+                        r.wyz[c * P + b] = wy[b] * wz[c];
+                rec[lane] = r;
             }
-            // rank among lanes with the same base key
-            uint64_t mask = __ballot(valid);
+            __syncthreads();
+            const int cnt = min(64, s1 - sb);
+            for (int k = 0; k < cnt; ++k) {
+                const int packed = __builtin_amdgcn_readfirstlane(rec[k].base);
+                const int bx = (packed & 255) - 4, by = ((packed >> 8) & 255) - 4,
+                          bz = ((packed >> 16) & 255) - 4;
+                const int dy = ly - by, dz = lz - bz;
+                if ((unsigned)dy < (unsigned)P && (unsigned)dz < (unsigned)P) {
+                    const T wyz = rec[k].wyz[dz * P + dy];
+                    const T c0 = rec[k].f[0] * wyz, c1 = rec[k].f[1] * wyz,
+                            c2 = rec[k].f[2] * wyz;
+                    // the stencil covers x = bx .. bx+P-1: update the halves it meets
+                    if (bx <= TILE / 2 - 1) {
 #pragma unroll
-            for (int bit = 0; bit < 12; ++bit) {
-                const bool on = (key >> bit) & 1;
-                const uint64_t m = __ballot(valid && on);
-                mask &= on ? m : ~m;
-            }
-            const int rank = __popcll(mask & lt);
-            int rmax = 0;
-            while (__ballot(valid && rank > rmax))
-                ++rmax;
+                        for (int x = 0; x < TILE / 2; ++x) {
+                            const T wv = rec[k].wxs[x];
+                            acc[x][0] += c0 * wv;
+                            acc[x][1] += c1 * wv;
+                            acc[x][2] += c2 * wv;
+                        }
+                    }
+                    if (bx >= TILE / 2 - P + 1) {
 #pragma unroll
-            for (int k = 0; k < P; ++k)
-#pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    const T wyz = w[1][j] * w[2][k];
-                    const bool inyz = valid && ((my >> j) & 1) && ((mz >> k) & 1);
-#pragma unroll
-                    for (int q = 0; q < P; ++q) {
-                        const bool in = inyz && ((mx >> q) & 1);
-                        const T wt = w[0][q] * wyz;
-                        const int cell = cx[q] + cy[j] + cz[k];
-                        // rank classes in turn: no two active lanes share a cell
-                        for (int r = 0; r <= rmax; ++r) {
-                            if (in && rank == r) {
-                                V4 v = acc[cell];
-                                v.x += F0 * wt;
-                                v.y += F1 * wt;
-                                v.z += F2 * wt;
-                                acc[cell] = v;
-                            }
+                        for (int x = TILE / 2; x < TILE; ++x) {
+                            const T wv = rec[k].wxs[x];
+                            acc[x][0] += c0 * wv;
+                            acc[x][1] += c1 * wv;
+                            acc[x][2] += c2 * wv;
                         }
                     }
                 }
+            }
+            __syncthreads();
+        }
+        // transpose the tile through LDS, then coalesced stores
+        const int cell0 = TILE * ly + TILE * TILE * lz;
+#pragma unroll
+        for (int x = 0; x < TILE; ++x) {
+            tr[0][cell0 + x] = acc[x][0];
+            tr[1][cell0 + x] = acc[x][1];
+            tr[2][cell0 + x] = acc[x][2];
         }
         __syncthreads();
         if (!FINAL || keep_g) {
             T* gs = G + (int64_t)a * 3 * TILE_CELLS;
             for (int q = lane; q < TILE_CELLS; q += 64) {
-                const V4 v = acc[q];
-                gs[q] = v.x;
-                gs[q + TILE_CELLS] = v.y;
-                gs[q + 2 * TILE_CELLS] = v.z;
+                gs[q] = tr[0][q];
+                gs[q + TILE_CELLS] = tr[1][q];
+                gs[q + 2 * TILE_CELLS] = tr[2][q];
             }
         }
         if (FINAL) {
@@ -333,14 +368,13 @@ k_spread_tiles(Grid g, int64_t nl, double dt, const int32_t* __restrict__ active
                                                 lo[2] + (q >> 6));
                 if (off < 0)
                     continue;
-                const V4 v = acc[q];
-                const T vc[3] = {v.x, v.y, v.z};
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int64_t o = off + c * g.cstride;
+                    const T v = tr[c][q];
                     if (f)
-                        f[o] = vc[c];
-                    ustar[o] = u0[o] + tdt * vc[c];
+                        f[o] = v;
+                    ustar[o] = u0[o] + tdt * v;
                 }
             }
         }
