@@ -12,14 +12,12 @@
 //
 // Spreading (one work item = one tile with a non-empty source list, one
 // wavefront): lane = one (y, z) row of the tile, holding its 8 cells x 3
-// components in registers.  Source records (tile-frame base, F dV/h^3, the
-// four x-weights and the sixteen y-z weight products) are staged 64 at a time
-// in LDS; every lane walks them in list order and, when its row lies in the
-// source's stencil, adds F w_yz w_x to its cells, the x-weight of each cell
-// selected on the scalar unit (zero outside the stencil).  No atomics and no
-// shared accumulator: each cell's sum is formed by one lane in a fixed order,
-// so the result is reproducible bit for bit.  The tile is then transposed
-// through LDS so the global stores are coalesced.
+// components in registers.  Sources are staged 64 at a time in LDS; ballots
+// give each lane the set of staged sources whose stencil covers its row, and
+// the lane adds F w_x w_y w_z of exactly those, in list order.  No atomics and
+// no shared accumulator: each cell's sum is formed by one lane in a fixed
+// order, so the result is reproducible bit for bit.  The tile is then
+// transposed through LDS so the global stores are coalesced.
 #pragma once
 
 // XCD-aware static work split.  Workgroups are dispatched to the 8 XCDs of
@@ -233,18 +231,16 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     }
 }
 
-// Source record staged in LDS for the spreading kernel.
-template <typename T, int P>
-struct SrcRec {
-    T wxs[TILE];       // x weight of each x cell of the tile (0 outside the stencil)
-    T f[3];            // F dV / h^3
-    T wyz[P * P];      // wy[b] * wz[c] at [c * P + b]
-    int32_t base;      // (bx+4) | (by+4) << 8 | (bz+4) << 16, tile frame
-};
-
 // One wavefront per workgroup.  FINAL = 0: store the tile to its G slot.
 // FINAL = 1: store f (if any) and ustar = u0 + dt G on the tile; also the G
 // slot when keep_g is set (final residual).
+//
+// Sources are staged 64 at a time as structure-of-arrays in LDS: the weight
+// of every tile x cell, y row and z row (zero outside the stencil) and
+// F dV/h^3.  Sixteen ballots give, per tile row y and per tile row z, the
+// 64-bit set of staged sources whose stencil covers it; a lane's own set is
+// the AND of its two, and the lane visits exactly those sources in list
+// order.  The staging arrays share LDS with the transpose buffer.
 template <typename T, int P, int FINAL>
 __global__ void __launch_bounds__(64)
 k_spread_tiles(Grid g, int64_t nl, double dt, const int32_t* __restrict__ active,
@@ -252,8 +248,13 @@ k_spread_tiles(Grid g, int64_t nl, double dt, const int32_t* __restrict__ active
                const int32_t* __restrict__ src_idx, MarkerData<T> s, T* __restrict__ G,
                const T* __restrict__ u0, T* __restrict__ ustar, T* __restrict__ f, int keep_g)
 {
-    __shared__ SrcRec<T, P> rec[64];
-    __shared__ T tr[3][TILE_CELLS];
+    constexpr int NW = 3 * TILE + 3;                       // staged values per source
+    constexpr int NBUF = NW * 64 > 3 * TILE_CELLS ? NW * 64 : 3 * TILE_CELLS;
+    __shared__ T buf[NBUF];
+    T* const sx = buf;                  // [TILE][64] x weight of tile cell x
+    T* const sy = buf + TILE * 64;      // [TILE][64] y weight of tile row y
+    T* const sz = buf + 2 * TILE * 64;  // [TILE][64] z weight of tile row z
+    T* const sf = buf + 3 * TILE * 64;  // [3][64]    F dV / h^3
     const int lane = threadIdx.x;
     const int ly = lane & 7, lz = lane >> 3;
     const int n_act = *nactive;
@@ -269,96 +270,76 @@ k_spread_tiles(Grid g, int64_t nl, double dt, const int32_t* __restrict__ active
         const int s0 = src_offs[t], s1 = src_offs[t + 1];
         for (int sb = s0; sb < s1; sb += 64) {
             const int sidx = sb + lane;
+            int by = 64, bz = 64;       // no row for lanes past the list
             if (sidx < s1) {
                 const int64_t i = src_idx[sidx];
                 const Geo<T> gm = s.geo[i];
                 const typename Vec4<T>::type Fv = s.f4[i];
-                int packed = 0, bx = 0;
+                int b[3];
 #pragma unroll
                 for (int ax = 0; ax < 3; ++ax) {
-                    int b = gm.rb[ax] - lo[ax];
-                    if (b < -3) b += g.n[ax];
-                    else if (b > 7) b -= g.n[ax];
-                    packed |= (b + 4) << (8 * ax);
-                    if (ax == 0)
-                        bx = b;
+                    int v = gm.rb[ax] - lo[ax];
+                    if (v < -(P - 1)) v += g.n[ax];
+                    else if (v > TILE - 1) v -= g.n[ax];
+                    b[ax] = v;
                 }
-                SrcRec<T, P> r;
-                r.base = packed;
-                r.f[0] = Fv.x * gm.rs;
-                r.f[1] = Fv.y * gm.rs;
-                r.f[2] = Fv.z * gm.rs;
-                T wx[P], wy[P], wz[P];
+                by = b[1];
+                bz = b[2];
 #pragma unroll
-                for (int o = 0; o < P; ++o) {
-                    wx[o] = gm.w[0][o];
-                    wy[o] = gm.w[1][o];
-                    wz[o] = gm.w[2][o];
-                }
+                for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-                for (int x = 0; x < TILE; ++x) {
-                    T wv = T(0);
+                    for (int x = 0; x < TILE; ++x) {
+                        T wv = T(0);
 #pragma unroll
-                    for (int o = 0; o < P; ++o)
-                        wv = (x - bx == o) ? wx[o] : wv;
-                    r.wxs[x] = wv;
-                }
+                        for (int o = 0; o < P; ++o)
+                            wv = (x - b[ax] == o) ? gm.w[ax][o] : wv;
+                        buf[(ax * TILE + x) * 64 + lane] = wv;
+                    }
+                sf[0 * 64 + lane] = Fv.x * gm.rs;
+                sf[1 * 64 + lane] = Fv.y * gm.rs;
+                sf[2 * 64 + lane] = Fv.z * gm.rs;
+            }
+            uint64_t my = 0, mz = 0;
 #pragma unroll
-                for (int c = 0; c < P; ++c)
-#pragma unroll
-                    for (int b = 0; b < P; ++b)
-                        r.wyz[c * P + b] = wy[b] * wz[c];
-                rec[lane] = r;
+            for (int k = 0; k < TILE; ++k) {
+                const uint64_t yk = __ballot((unsigned)(k - by) < (unsigned)P);
+                const uint64_t zk = __ballot((unsigned)(k - bz) < (unsigned)P);
+                my = ly == k ? yk : my;
+                mz = lz == k ? zk : mz;
             }
             __syncthreads();
-            const int cnt = min(64, s1 - sb);
-            for (int k = 0; k < cnt; ++k) {
-                const int packed = __builtin_amdgcn_readfirstlane(rec[k].base);
-                const int bx = (packed & 255) - 4, by = ((packed >> 8) & 255) - 4,
-                          bz = ((packed >> 16) & 255) - 4;
-                const int dy = ly - by, dz = lz - bz;
-                if ((unsigned)dy < (unsigned)P && (unsigned)dz < (unsigned)P) {
-                    const T wyz = rec[k].wyz[dz * P + dy];
-                    const T c0 = rec[k].f[0] * wyz, c1 = rec[k].f[1] * wyz,
-                            c2 = rec[k].f[2] * wyz;
-                    // the stencil covers x = bx .. bx+P-1: update the halves it meets
-                    if (bx <= TILE / 2 - 1) {
+            uint64_t M = my & mz;
+            while (M) {
+                const int k = __builtin_ctzll(M);
+                M &= M - 1;
+                const T wyz = sy[ly * 64 + k] * sz[lz * 64 + k];
+                const T c0 = sf[k] * wyz, c1 = sf[64 + k] * wyz, c2 = sf[128 + k] * wyz;
 #pragma unroll
-                        for (int x = 0; x < TILE / 2; ++x) {
-                            const T wv = rec[k].wxs[x];
-                            acc[x][0] += c0 * wv;
-                            acc[x][1] += c1 * wv;
-                            acc[x][2] += c2 * wv;
-                        }
-                    }
-                    if (bx >= TILE / 2 - P + 1) {
-#pragma unroll
-                        for (int x = TILE / 2; x < TILE; ++x) {
-                            const T wv = rec[k].wxs[x];
-                            acc[x][0] += c0 * wv;
-                            acc[x][1] += c1 * wv;
-                            acc[x][2] += c2 * wv;
-                        }
-                    }
+                for (int x = 0; x < TILE; ++x) {
+                    const T wv = sx[x * 64 + k];
+                    acc[x][0] += c0 * wv;
+                    acc[x][1] += c1 * wv;
+                    acc[x][2] += c2 * wv;
                 }
             }
             __syncthreads();
         }
         // transpose the tile through LDS, then coalesced stores
+        T* const tr = buf;              // [3][TILE_CELLS]
         const int cell0 = TILE * ly + TILE * TILE * lz;
 #pragma unroll
         for (int x = 0; x < TILE; ++x) {
-            tr[0][cell0 + x] = acc[x][0];
-            tr[1][cell0 + x] = acc[x][1];
-            tr[2][cell0 + x] = acc[x][2];
+            tr[0 * TILE_CELLS + cell0 + x] = acc[x][0];
+            tr[1 * TILE_CELLS + cell0 + x] = acc[x][1];
+            tr[2 * TILE_CELLS + cell0 + x] = acc[x][2];
         }
         __syncthreads();
         if (!FINAL || keep_g) {
             T* gs = G + (int64_t)a * 3 * TILE_CELLS;
             for (int q = lane; q < TILE_CELLS; q += 64) {
-                gs[q] = tr[0][q];
-                gs[q + TILE_CELLS] = tr[1][q];
-                gs[q + 2 * TILE_CELLS] = tr[2][q];
+                gs[q] = tr[q];
+                gs[q + TILE_CELLS] = tr[TILE_CELLS + q];
+                gs[q + 2 * TILE_CELLS] = tr[2 * TILE_CELLS + q];
             }
         }
         if (FINAL) {
@@ -371,7 +352,7 @@ k_spread_tiles(Grid g, int64_t nl, double dt, const int32_t* __restrict__ active
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int64_t o = off + c * g.cstride;
-                    const T v = tr[c][q];
+                    const T v = tr[c * TILE_CELLS + q];
                     if (f)
                         f[o] = v;
                     ustar[o] = u0[o] + tdt * v;
