@@ -176,7 +176,8 @@ int ib_spread(const ib_level* lv, const ib_markers* m, const ib_buckets* b, ib_d
 /* sub-step, straight from global memory; batched: tile-staged LDS kernels  */
 /* fed by the buckets, ustar may alias u0).  bucket_width: markers per      */
 /* interpolation work item (64, 128 or 256; 0 = 256).  spread_wgs_per_cu:   */
-/* resident spreading workgroups per compute unit (1..32; 0 = 16).          */
+/* cap on resident spreading workgroups per compute unit (1..32; 0 = 16),  */
+/* lowered to what fits.  Interpolation runs as many workgroups as fit.     */
 /* use_graph: replay the launch sequence from a captured hipGraph when the  */
 /* arguments repeat (batched path, non-null stream).                        */
 /* ---------------------------------------------------------------------- */

@@ -93,13 +93,8 @@ static BatchedCfg cfg_of(const ib_plan* pl)
 {
     BatchedCfg c;
     c.bw = pl->bucket_width;
-    const int waves_per_wg = pl->bucket_width / 64;
-    int per_cu = 24 / (waves_per_wg > 0 ? waves_per_wg : 1);
-    if (per_cu < 1)
-        per_cu = 1;
-    // multiples of 8: the tile kernels split their work lists over the 8 XCDs
-    c.grid_i = (pl->ncu * per_cu + 7) / 8 * 8;
-    c.grid_s = (pl->ncu * pl->spread_wgs_per_cu + 7) / 8 * 8;
+    c.ncu = pl->ncu;
+    c.wgs_s = pl->spread_wgs_per_cu;
     c.prof = pl->prof;
     return c;
 }

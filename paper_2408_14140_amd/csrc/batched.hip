@@ -157,6 +157,22 @@ __global__ void k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile
 
 #include "tiles.h"
 
+// Persistent grid of a tile kernel: the workgroups that can be resident at
+// once (optionally capped per CU), a multiple of 8 for the XCD split.
+template <auto K, int BLOCK>
+int resident_grid(int ncu, int cap)
+{
+    static const int fit = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, K, BLOCK, 0) != hipSuccess || n < 1)
+            n = 1;
+        return n;
+    }();
+    const int per_cu = cap > 0 && cap < fit ? cap : fit;
+    const int grid = ncu * per_cu / NXCD * NXCD;
+    return grid > NXCD ? grid : NXCD;
+}
+
 // ------------------------------------------------------------------ fill
 
 // Tiles of covered boxes that no marker reaches: f = 0, ustar = u0.
@@ -262,14 +278,17 @@ static void launch_interp(const BatchedCfg& cfg, hipStream_t st, const Grid& g, 
                           const T* G, const int64_t* nbase, const MarkerData<T>& s, double* e2)
 {
     if (cfg.bw == 64)
-        k_interp_tiles<T, P, MODE, 64><<<cfg.grid_i, 64, 0, st>>>(g, nl, dt, items, nitems, u0,
-                                                                 G, nbase, s, e2);
+        k_interp_tiles<T, P, MODE, 64>
+            <<<resident_grid<k_interp_tiles<T, P, MODE, 64>, 64>(cfg.ncu, 0), 64, 0, st>>>(
+                g, nl, dt, items, nitems, u0, G, nbase, s, e2);
     else if (cfg.bw == 128)
-        k_interp_tiles<T, P, MODE, 128><<<cfg.grid_i, 128, 0, st>>>(g, nl, dt, items, nitems,
-                                                                   u0, G, nbase, s, e2);
+        k_interp_tiles<T, P, MODE, 128>
+            <<<resident_grid<k_interp_tiles<T, P, MODE, 128>, 128>(cfg.ncu, 0), 128, 0, st>>>(
+                g, nl, dt, items, nitems, u0, G, nbase, s, e2);
     else
-        k_interp_tiles<T, P, MODE, 256><<<cfg.grid_i, 256, 0, st>>>(g, nl, dt, items, nitems,
-                                                                   u0, G, nbase, s, e2);
+        k_interp_tiles<T, P, MODE, 256>
+            <<<resident_grid<k_interp_tiles<T, P, MODE, 256>, 256>(cfg.ncu, 0), 256, 0, st>>>(
+                g, nl, dt, items, nitems, u0, G, nbase, s, e2);
 }
 
 #define IBX_PROF_BEGIN(k) \
@@ -332,7 +351,8 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.f4, Fhist);
     for (int mi = 2; mi <= ns; ++mi) {
         IBX_PROF_BEGIN(PK_SPREAD);
-        k_spread_tiles<T, P, 0><<<cfg.grid_s, 64, 0, st>>>(g, nl, dt, w.active, w.nactive,
+        k_spread_tiles<T, P, 0>
+            <<<resident_grid<k_spread_tiles<T, P, 0>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(g, nl, dt, w.active, w.nactive,
                                                            b->src_offs, b->src_idx, w.s, w.G,
                                                            u0, ustar, f, 0);
         IBX_PROF_END();
@@ -346,7 +366,8 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
                                             Fhist + (int64_t)(mi - 1) * 3 * nl);
     }
     IBX_PROF_BEGIN(PK_SPREAD_FINAL);
-    k_spread_tiles<T, P, 1><<<cfg.grid_s, 64, 0, st>>>(g, nl, dt, w.active, w.nactive,
+    k_spread_tiles<T, P, 1>
+        <<<resident_grid<k_spread_tiles<T, P, 1>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(g, nl, dt, w.active, w.nactive,
                                                        b->src_offs, b->src_idx, w.s, w.G, u0,
                                                        ustar, f, resid ? 1 : 0);
     IBX_PROF_END();

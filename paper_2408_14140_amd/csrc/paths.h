@@ -26,8 +26,8 @@ int plain_multidirect(const Grid& g, int P, ib_prec prec, const ib_particles* p,
 
 struct BatchedCfg {
     int bw;        // markers per interpolation work item (= threads per workgroup)
-    int grid_i;    // persistent workgroups of the interpolation kernels
-    int grid_s;    // persistent workgroups of the spreading kernel
+    int ncu;       // compute units of the device
+    int wgs_s;     // cap on resident spreading workgroups per CU (0 = as many as fit)
     Profiler* prof;  // nullable: per-kernel event timing
 };
 

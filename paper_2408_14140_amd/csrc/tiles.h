@@ -6,9 +6,9 @@
 // threads): the tile plus a ceil(P/2)-cell halo of the field is staged into
 // three LDS planes.  For every item the element offsets of the 27 tiles
 // around it are precomputed once per loop (k_item_bases), so a halo cell's
-// address is base[(j-g+8)>>3 per axis] + its position in that tile: no
-// division, no dependent lookup.  Marker data is fetched before the staging
-// barrier so both streams of loads are in flight together.
+// address is base[(j-g+8)>>3 per axis] + its position in that tile.  Items
+// with few markers spread each marker over 2 or 4 lanes (one z plane of the
+// stencil each), so all waves of the workgroup share the compute phase.
 //
 // Spreading (one work item = one tile with a non-empty source list, one
 // wavefront): lane = one (y, z) row of the tile, holding its 8 cells x 3
@@ -98,7 +98,6 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     constexpr int gh = Halo<P>::g, R = Halo<P>::R, R3 = Halo<P>::R3;
     constexpr int NPT = (R3 + BW - 1) / BW;
     __shared__ T fld[3][R3];
-    __shared__ int64_t nb[27];
     const int n_items = *nitems;
     const double h3 = g.h * g.h * g.h;
     const int tid = threadIdx.x;
@@ -106,16 +105,50 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     const int sy = MODE == 0 ? g.ext : TILE;
     const int sz = MODE == 0 ? g.ext * g.ext : TILE * TILE;
     const T* src = MODE == 0 ? u0 : G;
+    // halo cells of this thread: neighbour-tile selector and offset inside
+    // that tile, the same for every item
+    int hsel[NPT], hoff[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int q = tid + k * BW;
+        const int jx = q % R, jy = (q / R) % R, jz = q / (R * R);
+        hsel[k] = q < R3 ? ((jx - gh + TILE) >> 3) + 3 * (((jy - gh + TILE) >> 3) +
+                                                         3 * ((jz - gh + TILE) >> 3))
+                         : -1;
+        hoff[k] = ((jx - gh) & 7) + sy * ((jy - gh) & 7) + sz * ((jz - gh) & 7);
+    }
+    T v0[NPT], v1[NPT], v2[NPT];
+    auto fetch = [&](int it) {
+        const int64_t* nbp = nbase + (int64_t)it * 27;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            v0[k] = v1[k] = v2[k] = T(0);
+            if (hsel[k] >= 0) {
+                const int64_t b = nbp[hsel[k]];
+                if (b >= 0) {
+                    const int64_t off = b + hoff[k];
+                    v0[k] = src[off];
+                    v1[k] = src[off + comp];
+                    v2[k] = src[off + 2 * comp];
+                }
+            }
+        }
+    };
     const Slab sl = xcd_slab(n_items);
     for (int it = sl.begin; it < sl.end; it += sl.stride) {
+        fetch(it);
         const Item item = items[it];
         int lo[3];
         tile_coords(g, item.tile, lo);
-        if (tid < 27)
-            nb[tid] = nbase[(int64_t)it * 27 + tid];
-        // this thread's marker: fetch its records while the halo is staged
-        const bool mine = tid < item.count;
-        const int64_t i = item.start + (mine ? tid : 0);
+        // Small items spread each marker over `split` consecutive lanes, one
+        // z plane of the stencil per lane (then a shuffle sum), so every wave
+        // of the workgroup takes part in the compute phase.
+        const int cnt = item.count;
+        const int lg = 4 * cnt <= BW ? 2 : 2 * cnt <= BW ? 1 : 0;
+        const int split = 1 << lg;
+        const int sub = tid & (split - 1);
+        const bool mine = (tid >> lg) < cnt;
+        const int64_t i = item.start + (mine ? (tid >> lg) : 0);
         int lb[3];
         T w[3][P];
         T dd[3] = {T(0), T(0), T(0)};
@@ -132,32 +165,12 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                     w[a][o] = gm.w[a][o];
             }
             rs = gm.rs;
+            if (sub == 0) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                dd[c] = MODE == 0 ? s.ud[c * nl + i] : s.d[c * nl + i];
-            if (MODE == 1)
-                fv = s.f4[i];
-        }
-        __syncthreads();
-        T v0[NPT], v1[NPT], v2[NPT];
-#pragma unroll
-        for (int k = 0; k < NPT; ++k) {
-            const int q = tid + k * BW;
-            v0[k] = T(0);
-            v1[k] = T(0);
-            v2[k] = T(0);
-            if (q < R3) {
-                const int jx = q % R, jy = (q / R) % R, jz = q / (R * R);
-                const int sel = ((jx - gh + TILE) >> 3) + 3 * (((jy - gh + TILE) >> 3) +
-                                                              3 * ((jz - gh + TILE) >> 3));
-                const int64_t b = nb[sel];
-                if (b >= 0) {
-                    const int64_t off = b + ((jx - gh) & 7) + sy * ((jy - gh) & 7) +
-                                        sz * ((jz - gh) & 7);
-                    v0[k] = src[off];
-                    v1[k] = src[off + comp];
-                    v2[k] = src[off + 2 * comp];
-                }
+                for (int c = 0; c < 3; ++c)
+                    dd[c] = MODE == 0 ? s.ud[c * nl + i] : s.d[c * nl + i];
+                if (MODE == 1)
+                    fv = s.f4[i];
             }
         }
 #pragma unroll
@@ -170,28 +183,47 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
             }
         }
         __syncthreads();
+        T acc0 = 0, acc1 = 0, acc2 = 0;
         if (mine) {
             bool ok = true;
 #pragma unroll
             for (int a = 0; a < 3; ++a)
                 ok &= (lb[a] >= 0 && lb[a] <= R - P);
-            T acc0 = 0, acc1 = 0, acc2 = 0;
-            if (ok) {
+            // planes sub, sub + split, ...: the trip count is uniform per item
+            const int trips = (P + split - 1) >> lg;
+            for (int n = 0; n < trips; ++n) {
+                const int k = sub + (n << lg);
+                if (!ok || k >= P)
+                    continue;
+                T wz = w[2][0];
 #pragma unroll
-                for (int k = 0; k < P; ++k)
+                for (int o = 1; o < P; ++o)
+                    wz = k == o ? w[2][o] : wz;
 #pragma unroll
-                    for (int j = 0; j < P; ++j) {
-                        const T wyz = w[1][j] * w[2][k];
-                        const int row = ((lb[2] + k) * R + (lb[1] + j)) * R + lb[0];
+                for (int j = 0; j < P; ++j) {
+                    const T wyz = w[1][j] * wz;
+                    const int row = ((lb[2] + k) * R + (lb[1] + j)) * R + lb[0];
 #pragma unroll
-                        for (int q = 0; q < P; ++q) {
-                            const T wt = w[0][q] * wyz;
-                            acc0 += fld[0][row + q] * wt;
-                            acc1 += fld[1][row + q] * wt;
-                            acc2 += fld[2][row + q] * wt;
-                        }
+                    for (int q = 0; q < P; ++q) {
+                        const T wt = w[0][q] * wyz;
+                        acc0 += fld[0][row + q] * wt;
+                        acc1 += fld[1][row + q] * wt;
+                        acc2 += fld[2][row + q] * wt;
                     }
+                }
             }
+        }
+        if (lg >= 1) {
+            acc0 += __shfl_xor(acc0, 1);
+            acc1 += __shfl_xor(acc1, 1);
+            acc2 += __shfl_xor(acc2, 1);
+        }
+        if (lg >= 2) {
+            acc0 += __shfl_xor(acc0, 2);
+            acc1 += __shfl_xor(acc1, 2);
+            acc2 += __shfl_xor(acc2, 2);
+        }
+        if (mine && sub == 0) {
             const T acc[3] = {acc0, acc1, acc2};
             double err = 0.0;
             const T idt = (T)(1.0 / dt);
