@@ -12,6 +12,7 @@ dominant kernel's roofline, the adjoint (a11) on the 64-sphere 128^3 workload,
 and the FP64 oracle timed on the host.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Kernel sources whose hash tags the committed HBM counter summary: the traffic
+# figure is reported only while these are unchanged since the counters were taken.
+TRAFFIC_SOURCES = ("paper_2408_14140_amd/csrc/tiles.h", "paper_2408_14140_amd/csrc/batched.hip")
+TRAFFIC_FILE = "profiles/spread_spheres1000_256_hbm_counters.txt"
 
 
 def log(msg):
@@ -60,6 +65,48 @@ def model_bytes(kind, s, P, N, S, A, C):
     return None
 
 
+def sources_sha():
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration), or None if
+    the summary is absent or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    sha, val = None, None
+    for ln in open(path):
+        f = ln.split()
+        if len(f) == 2 and f[0] == "sources_sha256_16:":
+            sha = f[1]
+        if len(f) == 3 and f[0] == "traffic_bytes_per_launch:" and f[1] == kernel:
+            val = float(f[2])
+    return val if sha == sources_sha() else None
+
+
+def copy_probe(mib, reps):
+    """Plain device-to-device copy of `mib` MiB, `reps` times; returns GB/s."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    return 2 * 4 * n * reps / (s.elapsed_time(e) * 1e-3) / 1e9
+
+
 def main():
     if "--gpus" in sys.argv:
         i = sys.argv.index("--gpus")
@@ -85,7 +132,14 @@ def run():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--bucket-width", type=int, default=0)
     ap.add_argument("--spread-wgs", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only time a plain MiB-sized device copy (counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        gbs = copy_probe(args.copy_probe, 4)
+        print(json.dumps({"copy_probe_mib": args.copy_probe, "copy_gbs": gbs}), flush=True)
+        return
 
     import torch
 
@@ -160,8 +214,25 @@ def run():
     achieved = nb / avg_s / 1e9 if nb else None
     roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                "traffic": None, "bytes_per_launch": nb, "avg_launch_us": kern[dom]["avg_us"]}
+                "traffic": committed_traffic(dom), "bytes_per_launch": nb,
+                "avg_launch_us": kern[dom]["avg_us"]}
     log(f"kernels {json.dumps(kern)}")
+
+    # cold loop: a 512 MiB write between repetitions evicts the 256 MB MALL
+    flush = torch.empty(128 << 20, dtype=torch.float32, device=dev)
+    cold = []
+    for _ in range(5):
+        flush.fill_(1.0)
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        loop_only()
+        e.record()
+        torch.cuda.synchronize()
+        cold.append(s.elapsed_time(e))
+    ms_cold = float(np.median(cold))
+    del flush
+    copy_gbs = copy_probe(1024, 10)
+    log(f"cold loop {ms_cold:.3f} ms, copy {copy_gbs:.0f} GB/s")
 
     # SURVEY-style loop byte model: per iteration u0 on C + 60 B per marker, plus final writes
     bmodel = ns * (3 * 4 * C + N * 60) + 6 * 4 * C
@@ -187,6 +258,9 @@ def run():
         "loop_marker_iters_per_s": N * ns / (ms_loop * 1e-3),
         "loop_model_gbs": bmodel / (ms_loop * 1e-3) / 1e9,
         "loop_model_bytes": bmodel,
+        "loop_ms_cold": ms_cold,
+        "copy_gbs": copy_gbs,
+        "loop_model_frac_of_copy": bmodel / (ms_loop * 1e-3) / 1e9 / copy_gbs,
         "roofline": roofline,
         "kernels": kern,
     }
@@ -230,16 +304,19 @@ def run():
     if not args.no_cpu_baseline:
         import oracle as O
         mo = O.build_markers(wl.xc, wl.d, lev.h)
-        t = time.perf_counter()
-        O.multidirect(O.grid_of(lev), P, ns, dt, mo, wl.xc, wl.up, wl.om, wl.u0,
-                      residuals=False)
-        el = time.perf_counter() - t
-        out["cpu_baseline"] = {"value": mo.nl * ns / el, "unit": "marker-iters/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"the full workload's loop (a3-a9, {mo.nl} markers, "
-                                         f"N_s={ns}) in the FP64 C oracle, one thread, "
-                                         f"{el:.1f} s"}
-        log(f"oracle loop {el:.1f} s")
+        go = O.grid_of(lev)
+        reps, el = 0, 0.0
+        while el < 10.0:
+            t = time.perf_counter()
+            O.multidirect(go, P, ns, dt, mo, wl.xc, wl.up, wl.om, wl.u0, residuals=False)
+            el += time.perf_counter() - t
+            reps += 1
+        out["cpu_baseline"] = {"value": reps * mo.nl * ns / el, "unit": "marker-iters/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{reps} runs of the full workload's loop (a3-a9, "
+                                         f"{mo.nl} markers, N_s={ns}) in the FP64 C oracle, "
+                                         f"one thread, {el:.1f} s"}
+        log(f"oracle loop x{reps} {el:.1f} s")
     print(json.dumps(out), flush=True)
 
 
