@@ -153,7 +153,12 @@ def _wave_vectors(K: int) -> np.ndarray:
 
 
 def fourier_field(rng, n, h, lo, nmodes: int, K: int) -> np.ndarray:
-    """Velocity field of ``nmodes`` random divergence-free Fourier modes, FP64."""
+    """Velocity field of ``nmodes`` random divergence-free Fourier modes, FP64.
+
+    Each mode is evaluated separably, cos(A + B + C + theta) =
+    cos A cos(B + C + theta) - sin A sin(B + C + theta) with A, B, C the
+    phases along x, y, z, using torch's threaded CPU kernels."""
+    import torch
     ks = _wave_vectors(K)
     pick = rng.choice(ks.shape[0], size=nmodes, replace=False)
     modes = []
@@ -166,18 +171,20 @@ def fourier_field(rng, n, h, lo, nmodes: int, K: int) -> np.ndarray:
         modes.append((ks[j], a, theta))
     nx, ny, nz = n
     L = [n[i] * h for i in range(3)]
-    xs = [(np.arange(n[i], dtype=np.float64) + 0.5) * h for i in range(3)]
-    u = np.zeros((3, nz, ny, nx), dtype=np.float64)
+    xs = [(torch.arange(n[i], dtype=torch.float64) + 0.5) * h for i in range(3)]
+    u = torch.zeros((3, nz, ny, nx), dtype=torch.float64)
+    val = torch.empty((nz, ny, nx), dtype=torch.float64)
     for k, a, theta in modes:
-        ex = np.exp(2j * np.pi * k[0] * xs[0] / L[0])
-        ey = np.exp(2j * np.pi * k[1] * xs[1] / L[1])
-        ez = np.exp(2j * np.pi * k[2] * xs[2] / L[2]) * np.exp(1j * theta)
-        plane = (ez[:, None, None] * ey[None, :, None]) * ex[None, None, :]
-        re = plane.real
+        A = (2.0 * np.pi * float(k[0]) / L[0]) * xs[0]
+        B = (2.0 * np.pi * float(k[1]) / L[1]) * xs[1]
+        C = (2.0 * np.pi * float(k[2]) / L[2]) * xs[2]
+        bc = B[None, :] + C[:, None] + theta
+        torch.mul(torch.cos(bc)[:, :, None], torch.cos(A)[None, None, :], out=val)
+        val.addcmul_(torch.sin(bc)[:, :, None], torch.sin(A)[None, None, :], value=-1.0)
         for c in range(3):
             if a[c] != 0.0:
-                u[c] += a[c] * re
-    return u
+                u[c].add_(val, alpha=float(a[c]))
+    return u.numpy()
 
 
 def _rsa(rng, diam, nplace, max_tries=200000):
