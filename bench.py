@@ -132,6 +132,8 @@ def run():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--bucket-width", type=int, default=0)
     ap.add_argument("--spread-wgs", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the plan's default bucket width and spreading residency")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only time a plain MiB-sized device copy (counter calibration)")
     args = ap.parse_args()
@@ -172,6 +174,10 @@ def run():
     plan = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, bucket_width=args.bucket_width,
                     spread_wgs_per_cu=args.spread_wgs, use_graph=True)
     red = torch.zeros((wl.npart, 12), dtype=torch.float64, device=dev)
+    tuned = None
+    if not args.no_autotune and not args.bucket_width and not args.spread_wgs:
+        tuned = plan.autotune(dl, parts, m, b, ns, dt, u32)
+        log(f"autotune {tuned}")
 
     def step():
         ibx.build_markers_into(dl, parts, m)
@@ -262,6 +268,7 @@ def run():
         "copy_gbs": copy_gbs,
         "loop_model_frac_of_copy": bmodel / (ms_loop * 1e-3) / 1e9 / copy_gbs,
         "roofline": roofline,
+        "plan": plan.query() | ({"autotune_loop_ms": tuned["loop_ms"]} if tuned else {}),
         "kernels": kern,
     }
 

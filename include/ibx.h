@@ -187,6 +187,8 @@ void ib_plan_destroy(ib_plan* plan);
 /* Current tuning of a plan: out[0] = path, out[1] = bucket_width,
  * out[2] = spread_wgs_per_cu, out[3] = use_graph. */
 int ib_plan_query(const ib_plan* plan, int32_t* out);
+/* Workspace of ib_multidirect_force and ib_plan_autotune (device bytes); it
+ * does not depend on the plan's tuning. */
 size_t ib_workspace_bytes(const ib_plan* plan, const ib_level* lv, int64_t nl, int32_t ns);
 
 /* Per-kernel timing of the batched path.  ib_plan_profile(plan, 1) makes
@@ -214,6 +216,22 @@ int ib_multidirect_force(ib_plan* plan, const ib_level* lv, const ib_particles* 
                          const ib_markers* m, const ib_buckets* b, int32_t ns, double dt,
                          const void* u0, void* ustar, void* f, void* F, double* resid,
                          void* Fhist, void* ws, size_t ws_bytes, void* stream);
+
+/* Autotuning of a batched plan (the batching extension of the coupling loop:
+ * the work-item width and the spreading residency are chosen on the real
+ * inputs).  Times the loop of ib_multidirect_force for every bucket_width in
+ * {64, 128, 256} and spread_wgs_per_cu in {4, 8, 16, 32} (3 runs each after
+ * one warm-up) and keeps the fastest in the plan (see ib_plan_query).  The
+ * tile stays 8^3: one 64-wide wavefront holds the 64 rows of a tile.
+ * Arguments as ib_multidirect_force, except that ustar must not alias u0 and
+ * no residual or history is taken; ustar, f and F hold the result of the
+ * last run.  Synchronizes the stream (do not capture).  out_ms (host,
+ * nullable) receives the chosen configuration's loop time in ms.  Returns
+ * IB_EUNSUPPORTED for a plain plan; on any error the plan keeps its tuning. */
+int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_particles* p,
+                     const ib_markers* m, const ib_buckets* b, int32_t ns, double dt,
+                     const void* u0, void* ustar, void* f, void* F, void* ws, size_t ws_bytes,
+                     void* stream, double* out_ms);
 
 /* ---------------------------------------------------------------------- */
 /* a10 Per-particle sums for the rigid-body update, Eqs. (particle1),       */

@@ -221,7 +221,10 @@ extern "C" size_t ib_workspace_bytes(const ib_plan* plan, const ib_level* lv, in
     Grid g = make_grid(lv);
     if (resolved_path(plan) == IB_PATH_PLAIN)
         return plain_workspace(g, plan->prec, nl);
-    return batched_workspace(g, plan->prec, nl, cfg_of(plan));
+    // sized for the narrowest bucket width, so retuning never needs more
+    BatchedCfg c = cfg_of(plan);
+    c.bw = 64;
+    return batched_workspace(g, plan->prec, nl, c);
 }
 
 static int check_common(const ib_plan* plan, const ib_level* lv, const ib_particles* p,
@@ -339,6 +342,80 @@ extern "C" int ib_multidirect_force(ib_plan* plan, const ib_level* lv, const ib_
         set_hip_error(e);
         return IB_EHIP;
     }
+    return IB_OK;
+}
+
+// Autotuning: time the batched loop for every bucket width and spreading
+// residency on the caller's inputs and keep the fastest.
+extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_particles* p,
+                                const ib_markers* m, const ib_buckets* b, int32_t ns, double dt,
+                                const void* u0, void* ustar, void* f, void* F, void* ws,
+                                size_t ws_bytes, void* stream, double* out_ms)
+{
+    int rc = check_common(plan, lv, p, m, b, ns, dt);
+    if (rc)
+        return rc;
+    if (resolved_path(plan) != IB_PATH_BATCHED)
+        return IB_EUNSUPPORTED;
+    if (!u0 || !ustar || ustar == u0 || (m->nl > 0 && !F))
+        return IB_EINVAL;
+    if (ws_bytes < ib_workspace_bytes(plan, lv, m->nl, ns) || !ws)
+        return IB_EWORKSPACE;
+    static const int32_t widths[] = {64, 128, 256};
+    static const int32_t wgs[] = {4, 8, 16, 32};
+    constexpr int REPS = 3;
+    const Grid g = make_grid(lv);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    const int32_t keep_bw = plan->bucket_width, keep_wgs = plan->spread_wgs_per_cu;
+    float best = -1.f;
+    int32_t best_bw = keep_bw, best_wgs = keep_wgs;
+    Profiler* prof = plan->prof;
+    plan->prof = nullptr;
+    for (int i = 0; i < 3 && e == hipSuccess && rc == IB_OK; ++i)
+        for (int j = 0; j < 4 && e == hipSuccess && rc == IB_OK; ++j) {
+            plan->bucket_width = widths[i];
+            plan->spread_wgs_per_cu = wgs[j];
+            const BatchedCfg cfg = cfg_of(plan);
+            rc = batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0, ustar, f,
+                                     F, nullptr, nullptr, ws, ws_bytes, st);
+            e = hipEventRecord(e0, st);
+            for (int r = 0; r < REPS && rc == IB_OK; ++r)
+                rc = batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0, ustar,
+                                         f, F, nullptr, nullptr, ws, ws_bytes, st);
+            if (e == hipSuccess)
+                e = hipEventRecord(e1, st);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && rc == IB_OK && (best < 0.f || ms < best)) {
+                best = ms;
+                best_bw = widths[i];
+                best_wgs = wgs[j];
+            }
+        }
+    plan->prof = prof;
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    drop_graph(plan);
+    if (e != hipSuccess || rc != IB_OK) {
+        plan->bucket_width = keep_bw;
+        plan->spread_wgs_per_cu = keep_wgs;
+        if (e != hipSuccess)
+            set_hip_error(e);
+        return rc != IB_OK ? rc : IB_EHIP;
+    }
+    plan->bucket_width = best_bw;
+    plan->spread_wgs_per_cu = best_wgs;
+    if (out_ms)
+        *out_ms = best / REPS;
     return IB_OK;
 }
 

@@ -83,6 +83,8 @@ PROF_CLASSES = ("prep", "lists", "interp_u0", "spread", "interp_g", "spread_fina
                 "unsort", "resid")
 _multidirect = _sig("ib_multidirect_force", C.c_int,
                     [_p, _PL, _PP, _PM, _PB, _i32, _d, _p, _p, _p, _p, _p, _p, _p, _sz, _p])
+_autotune = _sig("ib_plan_autotune", C.c_int,
+                 [_p, _PL, _PP, _PM, _PB, _i32, _d, _p, _p, _p, _p, _p, _sz, _p, _p])
 _reductions = _sig("ib_particle_reductions", C.c_int, [_PL, _PP, _PM, C.c_int, _p, _p, _p, _p, _p])
 _bwd_ws = _sig("ib_backward_workspace_bytes", _sz, [_p, _PL, _i64])
 _backward = _sig("ib_multidirect_backward", C.c_int,
@@ -95,7 +97,7 @@ _version = _sig("ib_version", C.c_int, [])
 EXPORTED = ("ib_count_markers", "ib_build_markers", "ib_desired_velocity", "ib_bucket_workspace",
             "ib_bucket", "ib_interp", "ib_spread", "ib_plan_create", "ib_plan_destroy",
             "ib_plan_query", "ib_workspace_bytes", "ib_plan_profile", "ib_plan_profile_read",
-            "ib_multidirect_force",
+            "ib_multidirect_force", "ib_plan_autotune",
             "ib_particle_reductions", "ib_backward_workspace_bytes", "ib_multidirect_backward",
             "ib_status_string", "ib_last_hip_error", "ib_version")
 
@@ -432,6 +434,27 @@ class Plan:
                             _ptr(resid), _ptr(Fhist), _ptr(ws), int(ws.numel()), _stream()),
                "ib_multidirect_force")
         return ustar, f, F
+
+    def autotune(self, level: DeviceLevel, parts: Particles, m: Markers, b: Buckets, ns: int,
+                 dt: float, u0: torch.Tensor) -> dict:
+        """Pick bucket width and spreading residency by timing the loop on these
+        inputs (synchronizes the current stream).  Returns the choice and its
+        loop time in ms."""
+        dev = u0.device
+        if u0.dtype != self.dtype:
+            raise TypeError("u0 dtype differs from the plan precision")
+        ustar = torch.empty_like(u0)
+        f = torch.empty_like(u0)
+        F = torch.empty((m.nl, 3), dtype=u0.dtype, device=dev)
+        ws = self.workspace(level, m.nl, ns, dev)
+        ms = C.c_double(0.0)
+        lc, pc, mc, bc = level.c, parts.c, m.c, b.c
+        _check(_autotune(self._h, C.byref(lc), C.byref(pc), C.byref(mc), C.byref(bc), int(ns),
+                         float(dt), _ptr(u0), _ptr(ustar), _ptr(f), _ptr(F), _ptr(ws),
+                         int(ws.numel()), _stream(), C.byref(ms)), "ib_plan_autotune")
+        out = self.query()
+        out["loop_ms"] = ms.value
+        return out
 
     def backward(self, level, parts, m, b, ns, dt, u0, Fhist, g_ustar=None, g_f=None,
                  g_F=None):

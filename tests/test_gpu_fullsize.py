@@ -187,8 +187,9 @@ def test_spheres20000_512_sampled(dev, cfg4):
     Uref = O.interp(O.grid_of(lev), wl.delta, sub, wl.u0)
     torch.cuda.synchronize()
     assert rel(U.cpu().numpy()[pick], Uref) <= TOL32
-    # the benchmark's loop settings, in place, with residuals
+    # autotuned plan, in place, with residuals
     plan = ibx.Plan(wl.delta, torch.float32, ibx.IB_PATH_BATCHED)
+    plan.autotune(dl, parts, dm, b, wl.ns, wl.dt, u)
     f = torch.zeros_like(u)
     r = torch.zeros(wl.ns + 1, dtype=torch.float64, device=dev)
     ustar, f, F = plan.multidirect_force(dl, parts, dm, b, wl.ns, wl.dt, u, ustar=u, f=f,

@@ -271,3 +271,33 @@ def test_particle_reductions(dev, name, mk, dtype):
     scale[:, 6:9] = absref[:, 6:9]
     scale[:, 9:12] = absref[:, 6:9].sum(axis=1, keepdims=True) * Rmax
     assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_autotune_keeps_parity(dev, dtype):
+    import torch
+
+    import oracle as O
+    import paper_2408_14140_amd as ibx
+    announce(f"autotune {dtype}")
+    wl = small_workload(64, 16, 4, 3, 3, cover_all=False, k=5)
+    c = Case(wl, dev)
+    ref = O.multidirect(c.g, wl.delta, wl.ns, wl.dt, c.m, wl.xc, wl.up, wl.om, wl.u0)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    b = ibx.bucket(c.dl, c.dm, wl.delta)
+    plan = ibx.Plan(wl.delta, tdt, ibx.IB_PATH_BATCHED)
+    u0 = c.u0_boxes(tdt)
+    choice = plan.autotune(c.dl, c.parts, c.dm, b, wl.ns, wl.dt, u0)
+    assert choice["bucket_width"] in (64, 128, 256)
+    assert choice["spread_wgs_per_cu"] in (4, 8, 16, 32)
+    assert choice["loop_ms"] > 0.0
+    assert plan.query() == {k: v for k, v in choice.items() if k != "loop_ms"}
+    ustar, f, F = plan.multidirect_force(c.dl, c.parts, c.dm, b, wl.ns, wl.dt, u0)
+    torch.cuda.synchronize()
+    tol = TOL64 if dtype == "f64" else TOL32
+    assert rel(F.cpu().numpy(), ref["F"]) <= tol
+    assert c.field_rel(f, ref["f"]) <= tol
+    assert c.field_rel(ustar, ref["ustar"]) <= tol
+    with pytest.raises(ibx.IbxError):
+        ibx.Plan(wl.delta, tdt, ibx.IB_PATH_PLAIN).autotune(c.dl, c.parts, c.dm, b, wl.ns,
+                                                             wl.dt, u0)
