@@ -42,6 +42,17 @@ struct Item {
 };
 
 template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+
+template <typename T>
 struct Vec4;
 template <>
 struct Vec4<float> {

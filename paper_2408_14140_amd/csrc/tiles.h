@@ -95,9 +95,14 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                const T* __restrict__ G, const int64_t* __restrict__ nbase, MarkerData<T> s,
                double* __restrict__ e2)
 {
-    constexpr int gh = Halo<P>::g, R = Halo<P>::R, R3 = Halo<P>::R3;
-    constexpr int NPT = (R3 + BW - 1) / BW;
-    __shared__ T fld[3][R3];
+    constexpr int gh = Halo<P>::g, R = Halo<P>::R;
+    // LDS holds the halo as rows [c][jz][jy] of pitch RP = 12 with halo x
+    // index jx at position jx + XO, so the tile's own 8 cells sit at 2..9
+    // and every row segment lands on an aligned pair boundary.
+    constexpr int RP = 12, XO = 2 - gh, PL = R * R * RP, NROW = 3 * R * R;
+    using T2 = typename Vec2<T>::type;
+    __shared__ __align__(16) T fld[3 * PL];
+    __shared__ int64_t nb[27];
     const int n_items = *nitems;
     const double h3 = g.h * g.h * g.h;
     const int tid = threadIdx.x;
@@ -105,42 +110,17 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     const int sy = MODE == 0 ? g.ext : TILE;
     const int sz = MODE == 0 ? g.ext * g.ext : TILE * TILE;
     const T* src = MODE == 0 ? u0 : G;
-    // halo cells of this thread: neighbour-tile selector and offset inside
-    // that tile, the same for every item
-    int hsel[NPT], hoff[NPT];
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-        const int q = tid + k * BW;
-        const int jx = q % R, jy = (q / R) % R, jz = q / (R * R);
-        hsel[k] = q < R3 ? ((jx - gh + TILE) >> 3) + 3 * (((jy - gh + TILE) >> 3) +
-                                                         3 * ((jz - gh + TILE) >> 3))
-                         : -1;
-        hoff[k] = ((jx - gh) & 7) + sy * ((jy - gh) & 7) + sz * ((jz - gh) & 7);
-    }
-    T v0[NPT], v1[NPT], v2[NPT];
-    auto fetch = [&](int it) {
-        const int64_t* nbp = nbase + (int64_t)it * 27;
-#pragma unroll
-        for (int k = 0; k < NPT; ++k) {
-            v0[k] = v1[k] = v2[k] = T(0);
-            if (hsel[k] >= 0) {
-                const int64_t b = nbp[hsel[k]];
-                if (b >= 0) {
-                    const int64_t off = b + hoff[k];
-                    v0[k] = src[off];
-                    v1[k] = src[off + comp];
-                    v2[k] = src[off + 2 * comp];
-                }
-            }
-        }
-    };
+    const bool paired = true;   // tile slots: rows start on multiples of 8 elements
     const Slab sl = xcd_slab(n_items);
     for (int it = sl.begin; it < sl.end; it += sl.stride) {
-        fetch(it);
+        if (tid < 27)
+            nb[tid] = nbase[(int64_t)it * 27 + tid];
+        __syncthreads();
         const Item item = items[it];
         int lo[3];
         tile_coords(g, item.tile, lo);
-        // Small items spread each marker over `split` consecutive lanes, one
+        // Marker records are fetched just before the halo so both streams of
+        // loads are in flight together.  Small items spread each marker over `split` consecutive lanes, one
         // z plane of the stencil per lane (then a shuffle sum), so every wave
         // of the workgroup takes part in the compute phase.
         const int cnt = item.count;
@@ -173,13 +153,103 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                     fv = s.f4[i];
             }
         }
+        if (MODE == 0) {
+            // box layout: rows are a box extent apart, so consecutive lanes
+            // take consecutive cells of the halo
+            constexpr int R3 = R * R * R, NPT = (R3 + BW - 1) / BW;
 #pragma unroll
-        for (int k = 0; k < NPT; ++k) {
-            const int q = tid + k * BW;
-            if (q < R3) {
-                fld[0][q] = v0[k];
-                fld[1][q] = v1[k];
-                fld[2][q] = v2[k];
+            for (int k = 0; k < NPT; ++k) {
+                const int q = tid + k * BW;
+                if (q < R3) {
+                    const int jx = q % R, jy = (q / R) % R, jz = q / (R * R);
+                    const int sel = ((jx - gh + TILE) >> 3) + 3 * (((jy - gh + TILE) >> 3) +
+                                                                  3 * ((jz - gh + TILE) >> 3));
+                    const int64_t b = nb[sel];
+                    T v0 = T(0), v1 = T(0), v2 = T(0);
+                    if (b >= 0) {
+                        const int64_t off = b + ((jx - gh) & 7) + (int64_t)sy * ((jy - gh) & 7) +
+                                            (int64_t)sz * ((jz - gh) & 7);
+                        v0 = src[off];
+                        v1 = src[off + comp];
+                        v2 = src[off + 2 * comp];
+                    }
+                    const int at = (jz * R + jy) * RP + XO + jx;
+                    fld[at] = v0;
+                    fld[PL + at] = v1;
+                    fld[2 * PL + at] = v2;
+                }
+            }
+        }
+        // tile slots: stage the halo row by row -- left segment (gh cells of
+        // the -x neighbour), the 8 cells of the middle tile, right segment
+        for (int task = tid; MODE != 0 && task < NROW; task += BW) {
+            const int c = task / (R * R), rr = task - c * (R * R);
+            const int jy = rr % R, jz = rr / R;
+            const int ys = (jy - gh + TILE) >> 3, zs = (jz - gh + TILE) >> 3;
+            const int64_t roff = (int64_t)sy * ((jy - gh) & 7) + (int64_t)sz * ((jz - gh) & 7) +
+                                 c * comp;
+            const int64_t bl = nb[3 * (ys + 3 * zs)], bc = nb[1 + 3 * (ys + 3 * zs)],
+                          br = nb[2 + 3 * (ys + 3 * zs)];
+            T* row = fld + ((c * R + jz) * R + jy) * RP;
+            T m[TILE];
+            T l[gh], r[gh];
+            if (paired) {
+                if (bc >= 0) {
+                    const T2* q = reinterpret_cast<const T2*>(src + bc + roff);
+#pragma unroll
+                    for (int k = 0; k < TILE / 2; ++k) {
+                        const T2 v = q[k];
+                        m[2 * k] = v.x;
+                        m[2 * k + 1] = v.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < TILE; ++k)
+                        m[k] = T(0);
+                }
+                if (gh == 2) {
+                    T2 vl, vr;
+                    vl.x = vl.y = vr.x = vr.y = T(0);
+                    if (bl >= 0)
+                        vl = *reinterpret_cast<const T2*>(src + bl + roff + (TILE - 2));
+                    if (br >= 0)
+                        vr = *reinterpret_cast<const T2*>(src + br + roff);
+                    l[0] = vl.x;
+                    l[gh - 1] = vl.y;
+                    r[0] = vr.x;
+                    r[gh - 1] = vr.y;
+                } else {
+                    l[0] = bl >= 0 ? src[bl + roff + TILE - 1] : T(0);
+                    r[0] = br >= 0 ? src[br + roff] : T(0);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < TILE; ++k)
+                    m[k] = bc >= 0 ? src[bc + roff + k] : T(0);
+#pragma unroll
+                for (int k = 0; k < gh; ++k) {
+                    l[k] = bl >= 0 ? src[bl + roff + TILE - gh + k] : T(0);
+                    r[k] = br >= 0 ? src[br + roff + k] : T(0);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < TILE / 2; ++k) {
+                T2 v;
+                v.x = m[2 * k];
+                v.y = m[2 * k + 1];
+                *reinterpret_cast<T2*>(row + 2 + 2 * k) = v;
+            }
+            if (gh == 2) {
+                T2 v;
+                v.x = l[0];
+                v.y = l[gh - 1];
+                *reinterpret_cast<T2*>(row) = v;
+                v.x = r[0];
+                v.y = r[gh - 1];
+                *reinterpret_cast<T2*>(row + 2 + TILE) = v;
+            } else {
+                row[XO] = l[0];
+                row[2 + TILE] = r[0];
             }
         }
         __syncthreads();
@@ -202,13 +272,13 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
 #pragma unroll
                 for (int j = 0; j < P; ++j) {
                     const T wyz = w[1][j] * wz;
-                    const int row = ((lb[2] + k) * R + (lb[1] + j)) * R + lb[0];
+                    const int row = ((lb[2] + k) * R + (lb[1] + j)) * RP + XO + lb[0];
 #pragma unroll
                     for (int q = 0; q < P; ++q) {
                         const T wt = w[0][q] * wyz;
-                        acc0 += fld[0][row + q] * wt;
-                        acc1 += fld[1][row + q] * wt;
-                        acc2 += fld[2][row + q] * wt;
+                        acc0 += fld[row + q] * wt;
+                        acc1 += fld[PL + row + q] * wt;
+                        acc2 += fld[2 * PL + row + q] * wt;
                     }
                 }
             }
