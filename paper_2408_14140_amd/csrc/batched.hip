@@ -86,6 +86,20 @@ __device__ inline void tile_coords(const Grid& g, int t, int* lo)
     lo[2] = (t / (g.nt[0] * g.nt[1])) * TILE;
 }
 
+// Box-layout element offset of a tile's first cell (a tile never straddles
+// boxes: the box edge is a multiple of 8), or -1 in an uncovered box.
+__device__ inline int64_t tile_base(const Grid& g, const int* lo)
+{
+    const int bx = lo[0] / g.box, by = lo[1] / g.box, bz = lo[2] / g.box;
+    const int id = g.lut[bx + g.nb[0] * (by + g.nb[1] * bz)];
+    if (id < 0)
+        return -1;
+    return (int64_t)id * g.bstride +
+           ((int64_t)(lo[2] - bz * g.box + g.ngrow) * g.ext + (lo[1] - by * g.box + g.ngrow)) *
+               g.ext +
+           (lo[0] - bx * g.box + g.ngrow);
+}
+
 // ------------------------------------------------------------------ prep
 
 template <typename T, int P>
@@ -186,30 +200,31 @@ int resident_grid(int ncu, int cap)
 
 // ------------------------------------------------------------------ fill
 
-// Tiles of covered boxes that no marker reaches: f = 0, ustar = u0.
+// Tiles of covered boxes that no marker reaches: f = 0, ustar = u0 (all = 1:
+// every tile).  One workgroup per tile.
 template <typename T>
-__global__ void k_fill_inactive(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ u0,
-                                T* __restrict__ ustar, T* __restrict__ f, int all)
+__global__ void __launch_bounds__(256)
+k_fill_inactive(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ u0,
+                T* __restrict__ ustar, T* __restrict__ f, int all)
 {
-    const int64_t total = g.ntiles * TILE_CELLS;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int t = (int)(q / TILE_CELLS);
+    for (int64_t t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
         if (!all && slot[t] >= 0)
             continue;
-        const int r = (int)(q % TILE_CELLS);
         int lo[3];
-        tile_coords(g, t, lo);
-        const int64_t off = cell_offset(g, lo[0] + (r & 7), lo[1] + ((r >> 3) & 7), lo[2] + (r >> 6));
-        if (off < 0)
+        tile_coords(g, (int)t, lo);
+        const int64_t tb = tile_base(g, lo);
+        if (tb < 0)
             continue;
+        for (int r = threadIdx.x; r < TILE_CELLS; r += blockDim.x) {
+            const int64_t off = tb + (r & 7) + (int64_t)g.ext * (((r >> 3) & 7) + g.ext * (r >> 6));
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int64_t o = off + c * g.cstride;
-            if (f)
-                f[o] = T(0);
-            if (ustar != u0)
-                ustar[o] = u0[o];
+            for (int c = 0; c < 3; ++c) {
+                const int64_t o = off + c * g.cstride;
+                if (f)
+                    f[o] = T(0);
+                if (ustar != u0)
+                    ustar[o] = u0[o];
+            }
         }
     }
 }
@@ -322,8 +337,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     BatchedWs<T> w = carve_batched<T>(g, nl, cfg.bw, ws, ws_bytes, &need);
     const unsigned gm = (unsigned)((nl + 255) / 256 > 0 ? (nl + 255) / 256 : 1);
     const unsigned gt = (unsigned)((T_ + 255) / 256);
-    const unsigned gfill = (unsigned)((T_ * TILE_CELLS + 255) / 256 < 65536
-                                          ? (T_ * TILE_CELLS + 255) / 256 : 65536);
+    const unsigned gfill = (unsigned)(T_ < 8192 ? (T_ > 0 ? T_ : 1) : 8192);   // one block per tile
     if (nl == 0) {
         k_fill_inactive<T><<<gfill, 256, 0, st>>>(g, w.slot, u0, ustar, f, 1);
         if (resid)

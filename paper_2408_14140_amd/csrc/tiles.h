@@ -444,13 +444,12 @@ k_spread_tiles(Grid g, int64_t nl, double dt, const int32_t* __restrict__ active
                 gs[q + 2 * TILE_CELLS] = tr[2 * TILE_CELLS + q];
             }
         }
-        if (FINAL) {
+        const int64_t tb = FINAL ? tile_base(g, lo) : -1;
+        if (FINAL && tb >= 0) {
             const T tdt = (T)dt;
             for (int q = lane; q < TILE_CELLS; q += 64) {
-                const int64_t off = cell_offset(g, lo[0] + (q & 7), lo[1] + ((q >> 3) & 7),
-                                                lo[2] + (q >> 6));
-                if (off < 0)
-                    continue;
+                const int64_t off = tb + (q & 7) + (int64_t)g.ext * (((q >> 3) & 7) +
+                                                                     g.ext * (q >> 6));
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int64_t o = off + c * g.cstride;
