@@ -13,11 +13,14 @@
 // Spreading (one work item = one tile with a non-empty source list, one
 // wavefront): lane = one (y, z) row of the tile, holding its 8 cells x 3
 // components in registers.  Sources are staged 64 at a time in LDS; ballots
-// give each lane the set of staged sources whose stencil covers its row, and
-// the lane adds F w_x w_y w_z of exactly those, in list order.  No atomics and
-// no shared accumulator: each cell's sum is formed by one lane in a fixed
-// order, so the result is reproducible bit for bit.  The tile is then
-// transposed through LDS so the global stores are coalesced.
+// give each lane the set of staged sources whose stencil covers its row.
+// Rows near a particle surface are covered by several times more sources than
+// the mean, so the visits are balanced in two phases: each lane first takes up
+// to K sources of its own row, then the rest of the heavier rows is dealt out
+// in pieces of K to all lanes and added back by the row's owner in order.  No
+// atomics: each cell's sum is formed in a fixed order, so the result is
+// reproducible bit for bit.  The tile is then transposed through LDS so the
+// global stores are coalesced.
 #pragma once
 
 // XCD-aware static work split.  Workgroups are dispatched to the 8 XCDs of
@@ -333,6 +336,51 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     }
 }
 
+// floor(a / b) for 0 <= a < 128, 1 <= b <= 128: the quotient's distance to
+// the next integer is at least 1/b unless it is exact, far above the error
+// of the single-precision product, so a small bias makes the floor exact.
+__device__ inline int small_div(int a, int b)
+{
+    return (int)((float)a * __builtin_amdgcn_rcpf((float)b) + 1.0e-3f);
+}
+
+// Wavefront sums, maxima and prefix sums of small non-negative values
+// (below 128) from seven ballots: bit b of the result gathers 2^b times the
+// number of lanes with bit b set.  No cross-lane data movement.
+__device__ inline int wave_sum(int v)
+{
+    int s = 0;
+#pragma unroll
+    for (int b = 0; b < 7; ++b)
+        s += __popcll(__ballot((v >> b) & 1)) << b;
+    return s;
+}
+
+__device__ inline int wave_max(int v)
+{
+    int m = 0;
+#pragma unroll
+    for (int b = 6; b >= 0; --b) {
+        const int c = m | (1 << b);
+        if (__ballot(v >= c))
+            m = c;
+    }
+    return m;
+}
+
+__device__ inline int wave_exclusive_sum(int v)
+{
+    int s = 0;
+#pragma unroll
+    for (int b = 0; b < 7; ++b) {
+        const uint64_t bb = __ballot((v >> b) & 1);
+        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0u));
+        s += below << b;
+    }
+    return s;
+}
+
 // One wavefront per workgroup.  FINAL = 0: store the tile to its G slot.
 // FINAL = 1: store f (if any) and ustar = u0 + dt G on the tile; also the G
 // slot when keep_g is set (final residual).
@@ -357,6 +405,20 @@ k_spread_tiles(Grid g, int64_t nl, double dt, const int32_t* __restrict__ active
     T* const sy = buf + TILE * 64;      // [TILE][64] y weight of tile row y
     T* const sz = buf + 2 * TILE * 64;  // [TILE][64] z weight of tile row z
     T* const sf = buf + 3 * TILE * 64;  // [3][64]    F dV / h^3
+    __shared__ uint64_t rest[64];       // sources of each row left after phase A
+    __shared__ int32_t piece[64];       // phase-B slot -> row | piece << 8
+    // add source k's contribution to the 8 cells of row (y, z)
+    auto visit = [&](T (&a)[TILE][3], int y, int z, int k) {
+        const T wyz = sy[y * 64 + k] * sz[z * 64 + k];
+        const T c0 = sf[k] * wyz, c1 = sf[64 + k] * wyz, c2 = sf[128 + k] * wyz;
+#pragma unroll
+        for (int x = 0; x < TILE; ++x) {
+            const T wv = sx[x * 64 + k];
+            a[x][0] += c0 * wv;
+            a[x][1] += c1 * wv;
+            a[x][2] += c2 * wv;
+        }
+    };
     const int lane = threadIdx.x;
     const int ly = lane & 7, lz = lane >> 3;
     const int n_act = *nactive;
@@ -410,18 +472,71 @@ k_spread_tiles(Grid g, int64_t nl, double dt, const int32_t* __restrict__ active
                 mz = lz == k ? zk : mz;
             }
             __syncthreads();
+            // Phase A: every lane visits up to K sources of its own row.
+            // Phase B: what is left of the heavier rows is cut into pieces of
+            // K sources dealt out to all 64 lanes; the owners then add the
+            // pieces in order.  K is the smallest cap whose pieces fit.
             uint64_t M = my & mz;
-            while (M) {
+            const int n = __popcll(M);
+            const int nmax = wave_max(n);
+            int K = nmax;
+            if (nmax > 1) {
+                int lo_k = 1, hi_k = nmax;
+                while (lo_k < hi_k) {
+                    const int mid = (lo_k + hi_k) >> 1;
+                    const int pieces = wave_sum(n > mid ? small_div(n - 1, mid) : 0);
+                    if (pieces <= 64)
+                        hi_k = mid;
+                    else
+                        lo_k = mid + 1;
+                }
+                K = lo_k;
+            }
+            for (int t = 0; t < K && M; ++t) {
                 const int k = __builtin_ctzll(M);
                 M &= M - 1;
-                const T wyz = sy[ly * 64 + k] * sz[lz * 64 + k];
-                const T c0 = sf[k] * wyz, c1 = sf[64 + k] * wyz, c2 = sf[128 + k] * wyz;
+                visit(acc, ly, lz, k);
+            }
+            if (nmax > K) {
+                const int np = n > K ? small_div(n - 1, K) : 0;   // pieces of this row
+                const int ps = wave_exclusive_sum(np);
+                rest[lane] = M;
+                for (int q = 0; q < np; ++q)
+                    piece[ps + q] = lane | (q << 8);
+                const int NP = wave_sum(np);
+                __syncthreads();
+                T pacc[TILE][3];
 #pragma unroll
-                for (int x = 0; x < TILE; ++x) {
-                    const T wv = sx[x * 64 + k];
-                    acc[x][0] += c0 * wv;
-                    acc[x][1] += c1 * wv;
-                    acc[x][2] += c2 * wv;
+                for (int x = 0; x < TILE; ++x)
+                    pacc[x][0] = pacc[x][1] = pacc[x][2] = T(0);
+                if (lane < NP) {
+                    const int pr = piece[lane] & 255, pq = piece[lane] >> 8;
+                    uint64_t m = rest[pr];
+                    for (int q = 0; q < pq * K; ++q)
+                        m &= m - 1;
+                    for (int t = 0; t < K && m; ++t) {
+                        const int k = __builtin_ctzll(m);
+                        m &= m - 1;
+                        visit(pacc, pr & 7, pr >> 3, k);
+                    }
+                }
+                __syncthreads();
+                // the staged sources are no longer needed: pieces reuse them
+                if (lane < NP) {
+#pragma unroll
+                    for (int x = 0; x < TILE; ++x)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            buf[lane * 3 * TILE + 3 * x + c] = pacc[x][c];
+                }
+                __syncthreads();
+                for (int q = 0; q < np; ++q) {
+                    const T* pp = buf + (ps + q) * 3 * TILE;
+#pragma unroll
+                    for (int x = 0; x < TILE; ++x)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            acc[x][c] += pp[3 * x + c];
                 }
             }
             __syncthreads();
