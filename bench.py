@@ -206,6 +206,15 @@ def run():
     ms_loop = timed(loop_only, args.steps)
     log(f"step {ms_step:.3f} ms, loop {ms_loop:.3f} ms")
 
+    # the step's other parts, each timed alone over the same number of repetitions
+    parts_ms = {
+        "build_markers": timed(lambda: ibx.build_markers_into(dl, parts, m), args.steps),
+        "bucket": timed(lambda: ibx.bucket_into(dl, m, P, b), args.steps),
+        "reductions": timed(lambda: red.copy_(ibx.particle_reductions(dl, parts, m, F32, u32)),
+                            args.steps),
+    }
+    log(f"step parts {json.dumps(parts_ms)}")
+
     # per-kernel breakdown over the same number of loops, events on the launch stream
     plan.profile(True)
     for _ in range(args.steps):
@@ -261,6 +270,7 @@ def run():
                    "markers": N, "ns": ns, "seed": args.seed,
                    "steps_cover": "a1 markers, a2 bucket, a3-a9 loop, a10 reductions"},
         "loop_ms": ms_loop,
+        "step_parts_ms": parts_ms,
         "loop_marker_iters_per_s": N * ns / (ms_loop * 1e-3),
         "loop_model_gbs": bmodel / (ms_loop * 1e-3) / 1e9,
         "loop_model_bytes": bmodel,
