@@ -241,12 +241,14 @@ int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_particles* p,
 /* the eight nodal values of phi_p = |x - X_p|/(D_p/2) - 1 (Sec. 4.1).       */
 /* Raw sums: the caller applies -rho_f and the time derivatives.  F and u   */
 /* in precision prec; out: device double [np][12].  flag (device int32 or   */
-/* NULL) is set to 1 when a particle's cells leave the covered boxes.       */
+/* NULL) is set to 1 when a particle's cells leave the covered boxes.  ws:   */
+/* device workspace of ib_reductions_workspace(np) bytes (partial sums).     */
 /* Deterministic: fixed-order tree reductions in FP64.                      */
 /* ---------------------------------------------------------------------- */
+size_t ib_reductions_workspace(int32_t np);
 int ib_particle_reductions(const ib_level* lv, const ib_particles* p, const ib_markers* m,
                            ib_prec prec, const void* F, const void* u, double* out,
-                           int32_t* flag, void* stream);
+                           int32_t* flag, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* a11 Adjoint of ib_multidirect_force (reverse sweep; S and J adjoint,     */

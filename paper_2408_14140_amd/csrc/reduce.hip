@@ -7,15 +7,22 @@
 // alpha_p is the particle volume fraction of a cell from the eight nodal
 // level-set values phi = |x_node - X_p| / (D_p/2) - 1 (Sec. 4.1, Eq.
 // (level-set function)): alpha = sum over nodes with phi < 0 of -phi, divided
-// by sum |phi| (0 when that sum is 0).  One workgroup per particle; every sum
-// is accumulated in FP64 and combined by a fixed-shape tree, so results are
-// reproducible bit for bit.
+// by sum |phi| (0 when that sum is 0).
+//
+// The volume integrals run on RD_SLABS workgroups per particle, each taking
+// the z planes of the particle's bounding box congruent to its slab index,
+// and write FP64 partial sums; a second kernel adds the Lagrangian sums and
+// the slab partials in a fixed order.  Every sum is formed by fixed-shape
+// trees, so results are reproducible bit for bit.
 #include "paths.h"
 
 namespace ibx {
 
-constexpr int RD_THREADS = 1024;
+constexpr int RD_THREADS = 256;
 constexpr int RD_WAVES = RD_THREADS / 64;
+constexpr int RD_SLABS = 8;
+constexpr int RD_QCAP = 512;               // per-wavefront queue capacity (cells)
+constexpr int RD_TAB = 256;                // bounding-box cells per axis held in LDS tables
 
 __device__ inline double wave_sum_f64(double v)
 {
@@ -25,41 +32,49 @@ __device__ inline double wave_sum_f64(double v)
     return v;
 }
 
-// One workgroup per particle.  Lanes run along x (coalesced field reads) and
-// the workgroup's 32 lane groups take the y rows of the particle's bounding
-// box for every z plane; wraps and box indices are formed once per column,
-// plane and row rather than per cell.
+// Fixed-shape sum of n values over a workgroup of RD_THREADS: wavefronts
+// first, then the wavefront sums in order.  Result valid in thread 0.
+template <int N>
+__device__ inline void block_sums(double (&acc)[N], double (*red)[N])
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        acc[q] = wave_sum_f64(acc[q]);
+    if ((t & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            red[t >> 6][q] = acc[q];
+    }
+    __syncthreads();
+    if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            double v = 0.0;
+            for (int w = 0; w < RD_WAVES; ++w)
+                v += red[w][q];
+            acc[q] = v;
+        }
+    }
+}
+
+// Volume integrals of particle blockIdx.x over the z planes kk = slab,
+// slab + RD_SLABS, ... of its bounding box -> part[p][slab][6].
+// Each wavefront classifies 64 cells per round with no global access:
+// interior cells (alpha = 1) and cells near the surface go, in cell order, to
+// two queues of its own in LDS, drained in bulk with independent loads.
 template <typename T>
 __global__ void __launch_bounds__(RD_THREADS)
-k_particle_sums(Grid g, int32_t np, const double* __restrict__ xc, const double* __restrict__ d,
-                const int64_t* __restrict__ offs, const double* __restrict__ x,
-                const double* __restrict__ y, const double* __restrict__ z,
-                const double* __restrict__ dv, const T* __restrict__ F,
-                const T* __restrict__ u, double* __restrict__ out, int32_t* flag)
+k_volume_partials(Grid g, const double* __restrict__ xc, const double* __restrict__ d,
+                  const T* __restrict__ u, double* __restrict__ part, int32_t* flag)
 {
-    __shared__ double red[RD_WAVES][12];
-    const int p = blockIdx.x;
-    const int t = threadIdx.x;
+    __shared__ double red[RD_WAVES][6];
+    __shared__ int qin[RD_WAVES * RD_QCAP], qsurf[RD_WAVES * RD_QCAP];
+    __shared__ int2 ptab[3][RD_TAB];       // per axis: (box index or -1, index in the extent)
+    const int p = blockIdx.x, slab = blockIdx.y;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const double c[3] = {xc[3 * p], xc[3 * p + 1], xc[3 * p + 2]};
-    double acc[12];
-#pragma unroll
-    for (int q = 0; q < 12; ++q)
-        acc[q] = 0.0;
-
-    // Lagrangian sums over the particle's markers
-    const double dvp = dv[p];
-    for (int64_t l = offs[p] + t; l < offs[p + 1]; l += RD_THREADS) {
-        const double F0 = (double)F[3 * l], F1 = (double)F[3 * l + 1], F2 = (double)F[3 * l + 2];
-        const double R0 = x[l] - c[0], R1 = y[l] - c[1], R2 = z[l] - c[2];
-        acc[0] += F0 * dvp;
-        acc[1] += F1 * dvp;
-        acc[2] += F2 * dvp;
-        acc[3] += (R1 * F2 - R2 * F1) * dvp;
-        acc[4] += (R2 * F0 - R0 * F2) * dvp;
-        acc[5] += (R0 * F1 - R1 * F0) * dvp;
-    }
-
-    // Eulerian volume integrals over the particle's bounding cells
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double R = 0.5 * d[p];
     const double h = g.h, h3 = h * h * h;
     int i0[3], ne[3];
@@ -79,8 +94,24 @@ k_particle_sums(Grid g, int32_t np, const double* __restrict__ xc, const double*
     const double hc = 0.8660254037844386 * h, margin = 1e-9 * R;
     const double rin = R - hc - margin, rout = R + hc + margin;
     const double rin2 = rin > 0.0 ? rin * rin : -1.0, rout2 = rout * rout;
-    const int lx = t & 31, grp = t >> 5, ngrp = RD_THREADS / 32;
-    // per-axis cell -> (wrapped cell, box index, index inside the box's extent)
+    // floor(a / b) for 0 <= a < 2^31 and b < 2^20 from a double reciprocal:
+    // the product's error (a few units in 2^-52 relative) stays far below the
+    // bias, and the bias below the 1/b gap to the next integer
+    auto qdiv = [](int a, double rb) { return (int)((double)a * rb + 1e-6); };
+    const double r_ne0 = 1.0 / ne[0], r_ne1 = 1.0 / ne[1], r_box = 1.0 / g.box;
+    // this slab's cells: planes kk = slab + RD_SLABS * m
+    const int nplanes = ne[2] > slab ? (ne[2] - slab + RD_SLABS - 1) / RD_SLABS : 0;
+    const int plane = ne[0] * ne[1];
+    const int ncell = nplanes * plane;
+    const double r_plane = 1.0 / plane;
+    auto decode = [&](int q, int& i, int& j, int& k) {
+        const int m = qdiv(q, r_plane);
+        const int rem = q - m * plane;
+        const int row = qdiv(rem, r_ne0);
+        i = i0[0] + (rem - row * ne[0]);
+        j = i0[1] + row;
+        k = i0[2] + slab + RD_SLABS * m;
+    };
     auto place = [&](int a, int i, int& bi, int& li) {
         int cidx = i;
         if (g.periodic[a]) {
@@ -90,101 +121,166 @@ k_particle_sums(Grid g, int32_t np, const double* __restrict__ xc, const double*
         } else if (cidx < 0 || cidx >= g.n[a]) {
             return false;
         }
-        bi = cidx / g.box;
+        bi = qdiv(cidx, r_box);
         li = cidx - bi * g.box + g.ngrow;
         return true;
     };
-    int byq[2] = {0, 0}, lyq[2] = {0, 0};
-    bool oky[2] = {false, false};
+    auto alpha = [&](int i, int j, int k) {
+        double num = 0.0, den = 0.0;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int jj = grp + q * ngrp;
-        if (jj < ne[1])
-            oky[q] = place(1, i0[1] + jj, byq[q], lyq[q]);
-    }
-    for (int ii = lx; g.nbox > 0 && ii < ne[0]; ii += 32) {
-        const int i = i0[0] + ii;
-        const double r0 = g.lo[0] + ((double)i + 0.5) * h - c[0];
-        int bxi = 0, lxo = 0;
-        const bool okx = place(0, i, bxi, lxo);
-        for (int kk = 0; kk < ne[2]; ++kk) {
-            const int k = i0[2] + kk;
-            const double r2 = g.lo[2] + ((double)k + 0.5) * h - c[2];
-            int bzi = 0, lzo = 0;
-            const bool okz = place(2, k, bzi, lzo);
-            for (int q = 0; grp + q * ngrp < ne[1]; ++q) {
-                const int jj = grp + q * ngrp;
-                const int j = i0[1] + jj;
-                int by = 0, ly = 0;
-                bool okyq;
-                if (q < 2) {
-                    by = byq[q];
-                    ly = lyq[q];
-                    okyq = oky[q];
-                } else {
-                    okyq = place(1, j, by, ly);
+        for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+                for (int di = 0; di < 2; ++di) {
+                    const double ex = (g.lo[0] + (double)(i + di) * h - c[0]) * invR;
+                    const double ey = (g.lo[1] + (double)(j + dj) * h - c[1]) * invR;
+                    const double ez = (g.lo[2] + (double)(k + dk) * h - c[2]) * invR;
+                    const double phi = sqrt(ex * ex + ey * ey + ez * ez) - 1.0;
+                    if (phi < 0.0)
+                        num -= phi;
+                    den += fabs(phi);
                 }
-                const double r1 = g.lo[1] + ((double)j + 0.5) * h - c[1];
-                const double rc2 = r0 * r0 + r1 * r1 + r2 * r2;
-                if (rc2 > rout2)
-                    continue;
-                double al = 1.0;
-                if (rc2 >= rin2) {
-                    double num = 0.0, den = 0.0;
-#pragma unroll
-                    for (int dk = 0; dk < 2; ++dk)
-#pragma unroll
-                        for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-                            for (int di = 0; di < 2; ++di) {
-                                const double ex = (g.lo[0] + (double)(i + di) * h - c[0]) * invR;
-                                const double ey = (g.lo[1] + (double)(j + dj) * h - c[1]) * invR;
-                                const double ez = (g.lo[2] + (double)(k + dk) * h - c[2]) * invR;
-                                const double phi = sqrt(ex * ex + ey * ey + ez * ez) - 1.0;
-                                if (phi < 0.0)
-                                    num -= phi;
-                                den += fabs(phi);
-                            }
-                    al = den > 0.0 ? num / den : 0.0;
-                    if (al == 0.0)
-                        continue;
-                }
-                const int id = okx && okyq && okz ? g.lut[bxi + g.nb[0] * (by + g.nb[1] * bzi)]
-                                                  : -1;
-                if (id < 0) {
-                    if (flag)
-                        atomicOr(flag, 1);
-                    continue;
-                }
-                const int64_t off = (int64_t)id * g.bstride +
-                                    ((int64_t)lzo * g.ext + ly) * g.ext + lxo;
-                const double u0 = (double)u[off], u1 = (double)u[off + g.cstride],
-                             u2 = (double)u[off + 2 * g.cstride];
-                const double wgt = al * h3;
-                acc[6] += u0 * wgt;
-                acc[7] += u1 * wgt;
-                acc[8] += u2 * wgt;
-                acc[9] += (r1 * u2 - r2 * u1) * wgt;
-                acc[10] += (r2 * u0 - r0 * u2) * wgt;
-                acc[11] += (r0 * u1 - r1 * u0) * wgt;
-            }
+        return den > 0.0 ? num / den : 0.0;
+    };
+    // placement of the bounding box's cells along each axis, formed once
+    const bool tabled = ne[0] <= RD_TAB && ne[1] <= RD_TAB && nplanes <= RD_TAB;
+    if (tabled) {
+        for (int e = t; e < ne[0] + ne[1] + nplanes; e += RD_THREADS) {
+            const int a = e < ne[0] ? 0 : e < ne[0] + ne[1] ? 1 : 2;
+            const int idx = a == 0 ? e : a == 1 ? e - ne[0] : e - ne[0] - ne[1];
+            const int cell = a == 2 ? i0[2] + slab + RD_SLABS * idx : i0[a] + idx;
+            int bi = -1, li = 0;
+            if (!place(a, cell, bi, li))
+                bi = -1;
+            ptab[a][idx] = make_int2(bi, li);
         }
     }
-
-    // fixed-shape reduction: within each wavefront, then over the wavefronts
-#pragma unroll
-    for (int q = 0; q < 12; ++q)
-        acc[q] = wave_sum_f64(acc[q]);
-    if ((t & 63) == 0) {
-#pragma unroll
-        for (int q = 0; q < 12; ++q)
-            red[t >> 6][q] = acc[q];
-    }
     __syncthreads();
-    if (t < 12) {
+    auto add_cell = [&](int i, int j, int k, double al) {
+        int bx = -1, lxo = 0, by = -1, lyo = 0, bz = -1, lzo = 0;
+        if (tabled) {
+            const int2 px = ptab[0][i - i0[0]], py = ptab[1][j - i0[1]],
+                       pz = ptab[2][(k - i0[2] - slab) / RD_SLABS];
+            bx = px.x; lxo = px.y; by = py.x; lyo = py.y; bz = pz.x; lzo = pz.y;
+        } else if (!(place(0, i, bx, lxo) && place(1, j, by, lyo) && place(2, k, bz, lzo))) {
+            bx = -1;
+        }
+        const bool ok = bx >= 0 && by >= 0 && bz >= 0;
+        const int id = ok ? g.lut[bx + g.nb[0] * (by + g.nb[1] * bz)] : -1;
+        if (id < 0) {
+            if (flag)
+                atomicOr(flag, 1);
+            return;
+        }
+        const int64_t off = (int64_t)id * g.bstride + ((int64_t)lzo * g.ext + lyo) * g.ext + lxo;
+        const double u0 = (double)u[off], u1 = (double)u[off + g.cstride],
+                     u2 = (double)u[off + 2 * g.cstride];
+        const double r0 = g.lo[0] + ((double)i + 0.5) * h - c[0];
+        const double r1 = g.lo[1] + ((double)j + 0.5) * h - c[1];
+        const double r2 = g.lo[2] + ((double)k + 0.5) * h - c[2];
+        const double wgt = al * h3;
+        acc[0] += u0 * wgt;
+        acc[1] += u1 * wgt;
+        acc[2] += u2 * wgt;
+        acc[3] += (r1 * u2 - r2 * u1) * wgt;
+        acc[4] += (r2 * u0 - r0 * u2) * wgt;
+        acc[5] += (r0 * u1 - r1 * u0) * wgt;
+    };
+    // each wavefront queues and drains its own cells: no workgroup barrier
+    int* const qi = qin + wv * RD_QCAP;
+    int* const qs = qsurf + wv * RD_QCAP;
+    int nin = 0, nsurf = 0;
+    for (int base = wv * 64; g.nbox > 0 && base < ncell; base += RD_THREADS) {
+        const int q = base + lane;
+        int cls = 0;                       // 0 outside, 1 interior, 2 near the surface
+        if (q < ncell) {
+            int i, j, k;
+            decode(q, i, j, k);
+            const double r0 = g.lo[0] + ((double)i + 0.5) * h - c[0];
+            const double r1 = g.lo[1] + ((double)j + 0.5) * h - c[1];
+            const double r2 = g.lo[2] + ((double)k + 0.5) * h - c[2];
+            const double rc2 = r0 * r0 + r1 * r1 + r2 * r2;
+            cls = rc2 > rout2 ? 0 : rc2 < rin2 ? 1 : 2;
+        }
+        const uint64_t b1 = __ballot(cls == 1), b2 = __ballot(cls == 2);
+        if (cls == 1)
+            qi[nin + __builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0u))] = q;
+        if (cls == 2)
+            qs[nsurf + __builtin_amdgcn_mbcnt_hi((uint32_t)(b2 >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)b2, 0u))] = q;
+        nin += __popcll(b1);
+        nsurf += __popcll(b2);
+        const bool last = base + RD_THREADS >= ncell;
+        if (nin > RD_QCAP - 64 || last) {
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 4
+            for (int e = lane; e < nin; e += 64) {
+                int i, j, k;
+                decode(qi[e], i, j, k);
+                add_cell(i, j, k, 1.0);
+            }
+            nin = 0;
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (nsurf > RD_QCAP - 64 || last) {
+            __builtin_amdgcn_wave_barrier();
+            for (int e = lane; e < nsurf; e += 64) {
+                int i, j, k;
+                decode(qs[e], i, j, k);
+                const double al = alpha(i, j, k);
+                if (al != 0.0)
+                    add_cell(i, j, k, al);
+            }
+            nsurf = 0;
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    block_sums<6>(acc, red);
+    if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            part[((int64_t)p * RD_SLABS + slab) * 6 + q] = acc[q];
+    }
+}
+
+// Lagrangian sums of particle blockIdx.x, then out[p] with the slab partials
+// of the volume integrals added in slab order.
+template <typename T>
+__global__ void __launch_bounds__(RD_THREADS)
+k_particle_sums(const double* __restrict__ xc, const int64_t* __restrict__ offs,
+                const double* __restrict__ x, const double* __restrict__ y,
+                const double* __restrict__ z, const double* __restrict__ dv,
+                const T* __restrict__ F, const double* __restrict__ part,
+                double* __restrict__ out)
+{
+    __shared__ double red[RD_WAVES][6];
+    const int p = blockIdx.x;
+    const int t = threadIdx.x;
+    const double c[3] = {xc[3 * p], xc[3 * p + 1], xc[3 * p + 2]};
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double dvp = dv[p];
+    for (int64_t l = offs[p] + t; l < offs[p + 1]; l += RD_THREADS) {
+        const double F0 = (double)F[3 * l], F1 = (double)F[3 * l + 1], F2 = (double)F[3 * l + 2];
+        const double R0 = x[l] - c[0], R1 = y[l] - c[1], R2 = z[l] - c[2];
+        acc[0] += F0 * dvp;
+        acc[1] += F1 * dvp;
+        acc[2] += F2 * dvp;
+        acc[3] += (R1 * F2 - R2 * F1) * dvp;
+        acc[4] += (R2 * F0 - R0 * F2) * dvp;
+        acc[5] += (R0 * F1 - R1 * F0) * dvp;
+    }
+    block_sums<6>(acc, red);
+    if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            out[12 * (int64_t)p + q] = acc[q];
+    }
+    if (t >= 6 && t < 12) {
         double v = 0.0;
-        for (int w = 0; w < RD_WAVES; ++w)
-            v += red[w][t];
+        for (int sl = 0; sl < RD_SLABS; ++sl)
+            v += part[((int64_t)p * RD_SLABS + sl) * 6 + (t - 6)];
         out[12 * (int64_t)p + t] = v;
     }
 }
@@ -193,9 +289,15 @@ k_particle_sums(Grid g, int32_t np, const double* __restrict__ xc, const double*
 
 using namespace ibx;
 
+extern "C" size_t ib_reductions_workspace(int32_t np)
+{
+    return np > 0 ? (size_t)np * RD_SLABS * 6 * sizeof(double) : 0;
+}
+
 extern "C" int ib_particle_reductions(const ib_level* lv, const ib_particles* p,
                                       const ib_markers* m, ib_prec prec, const void* F,
-                                      const void* u, double* out, int32_t* flag, void* stream)
+                                      const void* u, double* out, int32_t* flag, void* ws,
+                                      size_t ws_bytes, void* stream)
 {
     int rc = check_level(lv);
     if (rc)
@@ -207,15 +309,22 @@ extern "C" int ib_particle_reductions(const ib_level* lv, const ib_particles* p,
     if (!p->xc || !p->d || !m->offs || !m->dv || !u || !out ||
         (m->nl > 0 && (!F || !m->x || !m->y || !m->z)))
         return IB_EINVAL;
+    if (!ws || ws_bytes < ib_reductions_workspace(p->np))
+        return IB_EWORKSPACE;
     Grid g = make_grid(lv);
     hipStream_t st = (hipStream_t)stream;
-    if (prec == IB_F64)
+    double* part = (double*)ws;
+    const dim3 gv((unsigned)p->np, RD_SLABS);
+    if (prec == IB_F64) {
+        k_volume_partials<double><<<gv, RD_THREADS, 0, st>>>(g, p->xc, p->d, (const double*)u,
+                                                              part, flag);
         k_particle_sums<double><<<(unsigned)p->np, RD_THREADS, 0, st>>>(
-            g, p->np, p->xc, p->d, m->offs, m->x, m->y, m->z, m->dv, (const double*)F,
-            (const double*)u, out, flag);
-    else
+            p->xc, m->offs, m->x, m->y, m->z, m->dv, (const double*)F, part, out);
+    } else {
+        k_volume_partials<float><<<gv, RD_THREADS, 0, st>>>(g, p->xc, p->d, (const float*)u,
+                                                             part, flag);
         k_particle_sums<float><<<(unsigned)p->np, RD_THREADS, 0, st>>>(
-            g, p->np, p->xc, p->d, m->offs, m->x, m->y, m->z, m->dv, (const float*)F,
-            (const float*)u, out, flag);
+            p->xc, m->offs, m->x, m->y, m->z, m->dv, (const float*)F, part, out);
+    }
     return launch_status();
 }

@@ -85,7 +85,9 @@ _multidirect = _sig("ib_multidirect_force", C.c_int,
                     [_p, _PL, _PP, _PM, _PB, _i32, _d, _p, _p, _p, _p, _p, _p, _p, _sz, _p])
 _autotune = _sig("ib_plan_autotune", C.c_int,
                  [_p, _PL, _PP, _PM, _PB, _i32, _d, _p, _p, _p, _p, _p, _sz, _p, _p])
-_reductions = _sig("ib_particle_reductions", C.c_int, [_PL, _PP, _PM, C.c_int, _p, _p, _p, _p, _p])
+_red_ws = _sig("ib_reductions_workspace", _sz, [_i32])
+_reductions = _sig("ib_particle_reductions", C.c_int,
+                   [_PL, _PP, _PM, C.c_int, _p, _p, _p, _p, _p, _sz, _p])
 _bwd_ws = _sig("ib_backward_workspace_bytes", _sz, [_p, _PL, _i64])
 _backward = _sig("ib_multidirect_backward", C.c_int,
                  [_p, _PL, _PP, _PM, _PB, _i32, _d, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
@@ -98,7 +100,7 @@ EXPORTED = ("ib_count_markers", "ib_build_markers", "ib_desired_velocity", "ib_b
             "ib_bucket", "ib_interp", "ib_spread", "ib_plan_create", "ib_plan_destroy",
             "ib_plan_query", "ib_workspace_bytes", "ib_plan_profile", "ib_plan_profile_read",
             "ib_multidirect_force", "ib_plan_autotune",
-            "ib_particle_reductions", "ib_backward_workspace_bytes", "ib_multidirect_backward",
+            "ib_reductions_workspace", "ib_particle_reductions", "ib_backward_workspace_bytes", "ib_multidirect_backward",
             "ib_status_string", "ib_last_hip_error", "ib_version")
 
 
@@ -487,9 +489,11 @@ class Plan:
 def particle_reductions(level: DeviceLevel, parts: Particles, m: Markers, F: torch.Tensor,
                         u: torch.Tensor, flag: torch.Tensor = None) -> torch.Tensor:
     out = torch.empty((parts.np, 12), dtype=torch.float64, device=u.device)
+    ws = torch.empty(max(int(_red_ws(parts.np)), 1), dtype=torch.uint8, device=u.device)
     lc, pc, mc = level.c, parts.c, m.c
     _check(_reductions(C.byref(lc), C.byref(pc), C.byref(mc), _prec_of(u.dtype), _ptr(F), _ptr(u),
-                       _ptr(out), _ptr(flag), _stream()), "ib_particle_reductions")
+                       _ptr(out), _ptr(flag), _ptr(ws), int(ws.numel()), _stream()),
+           "ib_particle_reductions")
     return out
 
 
