@@ -64,6 +64,10 @@ def _load():
     lib.ibo_reverse.argtypes = [C.POINTER(Grid), C.c_int, C.c_int, _d, _i32, _p, _p, _p,
                                 _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
                                 _p, _p]
+    lib.ibo_rigid_update.restype = None
+    lib.ibo_rigid_update.argtypes = [_i32] + [_p] * 10 + [_d, _p, _d, _p, _p, _p]
+    lib.ibo_advect_markers.restype = None
+    lib.ibo_advect_markers.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p, _d, _p, _p, _p]
     _lib = lib
     return lib
 
@@ -257,3 +261,33 @@ def reverse(g: Grid, P: int, ns: int, dt: float, m: Markers, xc, up, om, u0, Fhi
     if rc:
         raise ValueError("marker stencil leaves the grid")
     return dict(u0=gu0, up=gup, om=gom, X=gX)
+
+
+def rigid_update(xc, d, up, om, rho_p, sums_n, sums_np1, rho_f, grav, dt, Fc=None, Tc=None,
+                 prescribed=None):
+    """Rigid-body update of the particles (Eqs. (particle1), (particle2), (pr2));
+    returns (up_new, om_new, xc_new)."""
+    lib = _load()
+    xc, d, up, om = _f64(xc), _f64(d), _f64(up), _f64(om)
+    rho_p, sums_n, sums_np1 = _f64(rho_p), _f64(sums_n), _f64(sums_np1)
+    g3 = _f64(grav)
+    Fc = None if Fc is None else _f64(Fc)
+    Tc = None if Tc is None else _f64(Tc)
+    pr = None if prescribed is None else np.ascontiguousarray(prescribed, dtype=np.int32)
+    np_ = d.shape[0]
+    up1, om1, xc1 = np.zeros((np_, 3)), np.zeros((np_, 3)), np.zeros((np_, 3))
+    lib.ibo_rigid_update(np_, _ptr(xc), _ptr(d), _ptr(up), _ptr(om), _ptr(rho_p),
+                         _ptr(sums_n), _ptr(sums_np1), _ptr(Fc), _ptr(Tc), _ptr(pr),
+                         float(rho_f), _ptr(g3), float(dt), _ptr(up1), _ptr(om1), _ptr(xc1))
+    return up1, om1, xc1
+
+
+def advect_markers(m: Markers, xc_n, xc_np1, om_n, om_np1, dt) -> Markers:
+    """Markers moved with their particle's rigid motion (Eq. (x))."""
+    lib = _load()
+    xc_n, xc_np1, om_n, om_np1 = _f64(xc_n), _f64(xc_np1), _f64(om_n), _f64(om_np1)
+    xn, yn, zn = (np.zeros(m.nl) for _ in range(3))
+    lib.ibo_advect_markers(m.nl, _ptr(m.x), _ptr(m.y), _ptr(m.z), _ptr(m.pid), _ptr(xc_n),
+                           _ptr(xc_np1), _ptr(om_n), _ptr(om_np1), float(dt), _ptr(xn),
+                           _ptr(yn), _ptr(zn))
+    return Markers(xn, yn, zn, m.pid, m.dv, m.offs)

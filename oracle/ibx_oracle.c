@@ -747,3 +747,82 @@ int ibo_reverse(const ibo_grid* g, int P, int ns, double dt, int32_t np, const i
     free(fprev);
     return rc ? -1 : 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The particle side of a time step (Sec. 3.2; Step 4 of Sec. 3.1).         */
+/* ------------------------------------------------------------------------ */
+
+/* Rigid-body update of np spheres.  Free motion follows Eqs. (particle1)   */
+/* and (particle2) with their right-hand sides taken at the half step (the  */
+/* midpoint rule): the marker force is F^{n+1/2} of Algorithm 1 and the      */
+/* time derivatives of the volume integrals are their change over dt:        */
+/*   rho_p V_p (U^{n+1} - U^n)/dt = -rho_f S_F + rho_f (I_u' - I_u)/dt        */
+/*                                  + (rho_p - rho_f) V_p g + F_c             */
+/*   I_p (W^{n+1} - W^n)/dt = -rho_f S_T + rho_f (I_ru' - I_ru)/dt + T_c       */
+/* with V_p = pi D^3/6 and I_p = rho_p V_p D^2/10 (solid sphere).  sums_n and */
+/* sums_np1 are the per-particle sums [S_F, S_T, I_u, I_ru] at t^n and with  */
+/* u^{n+1}; only the volume integrals of sums_np1 are used.  Prescribed      */
+/* particles keep U and W.  The centroid then moves by Eq. (pr2):            */
+/*   X^{n+1} = X^n + dt/2 (U^n + U^{n+1}).                                   */
+void ibo_rigid_update(int32_t np, const double* xc, const double* d, const double* up,
+                      const double* om, const double* rho_p, const double* sums_n,
+                      const double* sums_np1, const double* Fc, const double* Tc,
+                      const int32_t* prescribed, double rho_f, const double* grav, double dt,
+                      double* up_new, double* om_new, double* xc_new)
+{
+    for (int32_t p = 0; p < np; ++p) {
+        const double D = d[p];
+        const double Vp = IBO_PI * D * D * D / 6.0;
+        const double mass = rho_p[p] * Vp;
+        const double Ip = mass * D * D / 10.0;
+        const double* s0 = sums_n + 12 * p;
+        const double* s1 = sums_np1 + 12 * p;
+        for (int c = 0; c < 3; ++c) {
+            double un = up[3 * p + c], wn = om[3 * p + c];
+            double u1 = un, w1 = wn;
+            if (!(prescribed && prescribed[p])) {
+                double force = -rho_f * s0[c] + rho_f * (s1[6 + c] - s0[6 + c]) / dt +
+                               (rho_p[p] - rho_f) * Vp * grav[c] + (Fc ? Fc[3 * p + c] : 0.0);
+                double torque = -rho_f * s0[3 + c] + rho_f * (s1[9 + c] - s0[9 + c]) / dt +
+                                (Tc ? Tc[3 * p + c] : 0.0);
+                u1 = un + dt * force / mass;
+                w1 = wn + dt * torque / Ip;
+            }
+            up_new[3 * p + c] = u1;
+            om_new[3 * p + c] = w1;
+            xc_new[3 * p + c] = xc[3 * p + c] + 0.5 * dt * (un + u1);
+        }
+    }
+}
+
+/* Markers follow their particle's rigid motion (Eq. (x) with U = U_r +      */
+/* W x R): X^{n+1} = X_r^{n+1} + Q R^n, R^n = X^n - X_r^n, Q the rotation by  */
+/* the angle |W| dt about W/|W| with W = (W^n + W^{n+1})/2 (Rodrigues'        */
+/* formula); Q = identity when W = 0.                                         */
+void ibo_advect_markers(int64_t nl, const double* x, const double* y, const double* z,
+                        const int32_t* pid, const double* xc_n, const double* xc_np1,
+                        const double* om_n, const double* om_np1, double dt, double* xn,
+                        double* yn, double* zn)
+{
+    for (int64_t l = 0; l < nl; ++l) {
+        const int p = pid[l];
+        double R[3] = {x[l] - xc_n[3 * p], y[l] - xc_n[3 * p + 1], z[l] - xc_n[3 * p + 2]};
+        double w[3];
+        for (int c = 0; c < 3; ++c)
+            w[c] = 0.5 * (om_n[3 * p + c] + om_np1[3 * p + c]);
+        double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        double out[3] = {R[0], R[1], R[2]};
+        if (wn > 0.0) {
+            double k[3] = {w[0] / wn, w[1] / wn, w[2] / wn};
+            double th = wn * dt, ct = cos(th), st = sin(th);
+            double kxr[3] = {k[1] * R[2] - k[2] * R[1], k[2] * R[0] - k[0] * R[2],
+                             k[0] * R[1] - k[1] * R[0]};
+            double kdr = k[0] * R[0] + k[1] * R[1] + k[2] * R[2];
+            for (int c = 0; c < 3; ++c)
+                out[c] = R[c] * ct + kxr[c] * st + k[c] * kdr * (1.0 - ct);
+        }
+        xn[l] = xc_np1[3 * p] + out[0];
+        yn[l] = xc_np1[3 * p + 1] + out[1];
+        zn[l] = xc_np1[3 * p + 2] + out[2];
+    }
+}
