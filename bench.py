@@ -215,6 +215,19 @@ def run():
     }
     log(f"step parts {json.dumps(parts_ms)}")
 
+    # the particle side of a time step: rigid-body update and marker advection
+    rho_p = torch.full((wl.npart,), 2.0, dtype=torch.float64, device=dev)
+    red1 = red.clone()
+    up1, om1, xc1 = ibx.rigid_update(parts, rho_p, red, red1, 1.0, [0.0, 0.0, -9.81], dt)
+    madv = ibx.advect_markers(m, parts.xc, xc1, parts.om, om1, dt)
+    particle_ms = {
+        "rigid_update": timed(lambda: ibx.rigid_update(parts, rho_p, red, red1, 1.0,
+                                                       [0.0, 0.0, -9.81], dt), args.steps),
+        "advect_markers": timed(lambda: ibx.advect_markers(m, parts.xc, xc1, parts.om, om1, dt,
+                                                           out=madv), args.steps),
+    }
+    log(f"particle step {json.dumps(particle_ms)}")
+
     # per-kernel breakdown over the same number of loops, events on the launch stream
     plan.profile(True)
     for _ in range(args.steps):
@@ -271,6 +284,7 @@ def run():
                    "steps_cover": "a1 markers, a2 bucket, a3-a9 loop, a10 reductions"},
         "loop_ms": ms_loop,
         "step_parts_ms": parts_ms,
+        "particle_step_ms": particle_ms,
         "loop_marker_iters_per_s": N * ns / (ms_loop * 1e-3),
         "loop_model_gbs": bmodel / (ms_loop * 1e-3) / 1e9,
         "loop_model_bytes": bmodel,

@@ -269,6 +269,37 @@ int ib_multidirect_backward(ib_plan* plan, const ib_level* lv, const ib_particle
                             double* g_om, double* g_X, void* ws, size_t ws_bytes, void* stream);
 
 /* Helpers. */
+/* ---------------------------------------------------------------------- */
+/* The particle side of a time step (Sec. 3.2; Step 4 of Sec. 3.1).        */
+/* ---------------------------------------------------------------------- */
+
+/* Rigid-body update of the spheres.  Free particles follow Eqs.            */
+/* (particle1) and (particle2) with the right-hand sides at the half step    */
+/* (the midpoint rule):                                                     */
+/*   rho_p V_p (U' - U)/dt = -rho_f S_F + rho_f (I_u' - I_u)/dt               */
+/*                           + (rho_p - rho_f) V_p g + F_c,                   */
+/*   I_p (W' - W)/dt       = -rho_f S_T + rho_f (I_ru' - I_ru)/dt + T_c,       */
+/* V_p = pi D^3/6, I_p = rho_p V_p D^2/10 (solid sphere).  sums_n: device    */
+/* [np][12] from ib_particle_reductions with F = F^{n+1/2} and u = u^n       */
+/* (S_F, S_T, I_u, I_ru); sums_np1: the same with u^{n+1} (only I_u', I_ru'  */
+/* used).  rho_p: device [np].  Fc, Tc (device [np][3]) and prescribed       */
+/* (device int32 [np]; nonzero = keep U and W) may be NULL.  grav: host [3]. */
+/* The centroid moves by Eq. (pr2), X' = X + dt/2 (U + U').  Outputs are     */
+/* device [np][3] and must not alias the inputs.                             */
+int ib_rigid_update(const ib_particles* p, const double* rho_p, const double* sums_n,
+                    const double* sums_np1, const double* Fc, const double* Tc,
+                    const int32_t* prescribed, double rho_f, const double* grav, double dt,
+                    double* up_new, double* om_new, double* xc_new, void* stream);
+
+/* Markers follow their particle's rigid motion (Eq. (x) with U = U_r +     */
+/* W x R): X' = X_r' + Q (X - X_r), Q the rotation by |W| dt about W with    */
+/* W = (W^n + W^{n+1})/2 (Rodrigues' formula), identity when W = 0.  m holds */
+/* the positions at t^n; xc_n, xc_np1, om_n, om_np1 are device [np][3]; the  */
+/* new positions (device [nl] each) may overwrite m's arrays.                */
+int ib_advect_markers(const ib_markers* m, const double* xc_n, const double* xc_np1,
+                      const double* om_n, const double* om_np1, double dt, double* x_new,
+                      double* y_new, double* z_new, void* stream);
+
 const char* ib_status_string(int status);
 const char* ib_last_hip_error(void);
 int ib_version(void);

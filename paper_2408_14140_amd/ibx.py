@@ -92,6 +92,9 @@ _bwd_ws = _sig("ib_backward_workspace_bytes", _sz, [_p, _PL, _i64])
 _backward = _sig("ib_multidirect_backward", C.c_int,
                  [_p, _PL, _PP, _PM, _PB, _i32, _d, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
                   _sz, _p])
+_rigid = _sig("ib_rigid_update", C.c_int,
+              [_PP, _p, _p, _p, _p, _p, _p, _d, _p, _d, _p, _p, _p, _p])
+_advect = _sig("ib_advect_markers", C.c_int, [_PM, _p, _p, _p, _p, _d, _p, _p, _p, _p])
 _status_string = _sig("ib_status_string", C.c_char_p, [C.c_int])
 _last_hip_error = _sig("ib_last_hip_error", C.c_char_p, [])
 _version = _sig("ib_version", C.c_int, [])
@@ -101,6 +104,7 @@ EXPORTED = ("ib_count_markers", "ib_build_markers", "ib_desired_velocity", "ib_b
             "ib_plan_query", "ib_workspace_bytes", "ib_plan_profile", "ib_plan_profile_read",
             "ib_multidirect_force", "ib_plan_autotune",
             "ib_reductions_workspace", "ib_particle_reductions", "ib_backward_workspace_bytes", "ib_multidirect_backward",
+            "ib_rigid_update", "ib_advect_markers",
             "ib_status_string", "ib_last_hip_error", "ib_version")
 
 
@@ -494,6 +498,37 @@ def particle_reductions(level: DeviceLevel, parts: Particles, m: Markers, F: tor
     _check(_reductions(C.byref(lc), C.byref(pc), C.byref(mc), _prec_of(u.dtype), _ptr(F), _ptr(u),
                        _ptr(out), _ptr(flag), _ptr(ws), int(ws.numel()), _stream()),
            "ib_particle_reductions")
+    return out
+
+
+# ---------------------------------------------------------------- particle update
+
+def rigid_update(parts: Particles, rho_p: torch.Tensor, sums_n: torch.Tensor,
+                 sums_np1: torch.Tensor, rho_f: float, grav, dt: float, Fc=None, Tc=None,
+                 prescribed=None):
+    """Rigid-body update (Eqs. (particle1), (particle2), (pr2)); returns the new
+    particle velocities, angular velocities and centroids."""
+    dev = parts.xc.device
+    up1 = torch.empty_like(parts.up)
+    om1 = torch.empty_like(parts.om)
+    xc1 = torch.empty_like(parts.xc)
+    g3 = (C.c_double * 3)(*[float(v) for v in grav])
+    pc = parts.c
+    _check(_rigid(C.byref(pc), _ptr(rho_p), _ptr(sums_n), _ptr(sums_np1), _ptr(Fc), _ptr(Tc),
+                  _ptr(prescribed), float(rho_f), C.cast(g3, C.c_void_p), float(dt), _ptr(up1),
+                  _ptr(om1), _ptr(xc1), _stream()), "ib_rigid_update")
+    return up1, om1, xc1
+
+
+def advect_markers(m: Markers, xc_n, xc_np1, om_n, om_np1, dt: float, out: Markers = None):
+    """Markers moved with their particle's rigid motion (Eq. (x)); in place when
+    out is m."""
+    if out is None:
+        out = Markers(m.offs, torch.empty_like(m.x), torch.empty_like(m.y),
+                      torch.empty_like(m.z), m.pid, m.dv)
+    mc = m.c
+    _check(_advect(C.byref(mc), _ptr(xc_n), _ptr(xc_np1), _ptr(om_n), _ptr(om_np1), float(dt),
+                   _ptr(out.x), _ptr(out.y), _ptr(out.z), _stream()), "ib_advect_markers")
     return out
 
 
