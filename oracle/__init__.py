@@ -68,6 +68,8 @@ def _load():
     lib.ibo_rigid_update.argtypes = [_i32] + [_p] * 10 + [_d, _p, _d, _p, _p, _p]
     lib.ibo_advect_markers.restype = None
     lib.ibo_advect_markers.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p, _d, _p, _p, _p]
+    lib.ibo_collision_forces.restype = None
+    lib.ibo_collision_forces.argtypes = [_i32, _p, _p, _p, _d, _d, _d, _p, _p]
     _lib = lib
     return lib
 
@@ -291,3 +293,13 @@ def advect_markers(m: Markers, xc_n, xc_np1, om_n, om_np1, dt) -> Markers:
                            _ptr(xc_np1), _ptr(om_n), _ptr(om_np1), float(dt), _ptr(xn),
                            _ptr(yn), _ptr(zn))
     return Markers(xn, yn, zn, m.pid, m.dv, m.offs)
+
+
+def collision_forces(xc, d, rho_p, gnorm, h, eps_c=1e-4, L=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Repulsive collision force of Eq. (DKT_model) on every particle, [np][3]."""
+    lib = _load()
+    xc, d, rho_p, L = _f64(xc), _f64(d), _f64(rho_p), _f64(L)
+    Fc = np.zeros((d.shape[0], 3))
+    lib.ibo_collision_forces(d.shape[0], _ptr(xc), _ptr(d), _ptr(rho_p), float(gnorm), float(h),
+                             float(eps_c), _ptr(L), _ptr(Fc))
+    return Fc

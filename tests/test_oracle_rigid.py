@@ -118,3 +118,41 @@ def test_rotation_matches_a_library_rotation(oracle_mod, axis):
                            R0[sel, 2]], 1)
             assert np.allclose(R1[sel], rz, rtol=0, atol=1e-15)
     assert np.allclose(np.linalg.norm(R1, axis=1), np.linalg.norm(R0, axis=1), rtol=1e-14)
+
+
+def test_collision_force_of_two_spheres(oracle_mod):
+    """Eq. (DKT_model) by hand: D = 0.1, h = 0.01, so D_c = 0.11; at a centre
+    distance 0.105 the gap term is ((0.105 - 0.11)/0.01)^2 = 1/4."""
+    xc = np.array([[0.3, 0.4, 0.5], [0.3, 0.4, 0.605]])
+    d = np.array([0.1, 0.1])
+    rho = np.array([1140.0, 1140.0])
+    F = oracle_mod.collision_forces(xc, d, rho, 9.81, 0.01)
+    m = 1140.0 * np.pi * 0.1 ** 3 / 6.0
+    mag = m * 9.81 / 1e-4 * 0.25
+    assert np.allclose(F[0], [0.0, 0.0, -mag], rtol=1e-12, atol=0)
+    assert np.allclose(F[1], [0.0, 0.0, mag], rtol=1e-12, atol=0)
+    # zero beyond the contact distance, continuous at it
+    far = oracle_mod.collision_forces(xc + [[0, 0, 0], [0, 0, 0.006]], d, rho, 9.81, 0.01)
+    assert np.array_equal(far, np.zeros((2, 3)))
+    near = oracle_mod.collision_forces(xc + [[0, 0, 0], [0, 0, 0.005 - 1e-9]], d, rho, 9.81, 0.01)
+    assert np.abs(near).max() < 1e-7 * mag
+
+
+def test_collision_forces_balance_and_wrap(oracle_mod):
+    """Pairwise equal and opposite (total zero), and across a periodic face by
+    the minimum image."""
+    rng = np.random.default_rng(9)
+    n = 60
+    xc = rng.uniform(0, 1, (n, 3))
+    d = rng.uniform(0.1, 0.2, n)
+    rho = rng.uniform(1000, 3000, n)
+    F = oracle_mod.collision_forces(xc, d, rho, 9.81, 1 / 64, L=(1.0, 1.0, 1.0))
+    assert np.abs(F).max() > 0
+    assert np.abs(F.sum(axis=0)).max() <= 1e-12 * np.abs(F).sum()
+    pair = np.array([[0.01, 0.5, 0.5], [0.99, 0.5, 0.5]])
+    dd = np.array([0.02, 0.02])
+    rr = np.array([1000.0, 1000.0])
+    Fp = oracle_mod.collision_forces(pair, dd, rr, 9.81, 0.01, L=(1.0, 1.0, 1.0))
+    Fb = oracle_mod.collision_forces(pair, dd, rr, 9.81, 0.01)
+    assert Fp[0, 0] > 0 and Fp[1, 0] < 0          # pushed apart across the face
+    assert np.array_equal(Fb, np.zeros((2, 3)))   # bounded axes: far apart
