@@ -225,6 +225,8 @@ def run():
                                                        [0.0, 0.0, -9.81], dt), args.steps),
         "advect_markers": timed(lambda: ibx.advect_markers(m, parts.xc, xc1, parts.om, om1, dt,
                                                            out=madv), args.steps),
+        "collision_forces": timed(lambda: ibx.collision_forces(dl, parts, rho_p, 9.81, 1e-4),
+                                  args.steps),
     }
     log(f"particle step {json.dumps(particle_ms)}")
 

@@ -300,6 +300,17 @@ int ib_advect_markers(const ib_markers* m, const double* xc_n, const double* xc_
                       const double* om_n, const double* om_np1, double dt, double* x_new,
                       double* y_new, double* z_new, void* stream);
 
+/* Repulsive collision force between particles, Eq. (DKT_model) (after      */
+/* Breugem 2012): for every pair closer than D_c = R_i + R_j + h,             */
+/*   F_c,ij = -(m |g| / eps_c) ((|delta| - D_c)/h)^2 delta/|delta|,           */
+/* delta = X_j - X_i by the minimum image on the level's periodic axes, h   */
+/* the finest spacing, m the mean of the two masses rho V (the paper's case  */
+/* has equal spheres).  Fc (device [np][3], out) = sum over j of F_c,ij; the */
+/* force is central, so the collision torque is zero.  rho_p: device [np];  */
+/* the paper uses eps_c = 1e-4.  Every sum runs in a fixed order.          */
+int ib_collision_forces(const ib_level* lv, const ib_particles* p, const double* rho_p,
+                        double g_norm, double eps_c, double* Fc, void* stream);
+
 const char* ib_status_string(int status);
 const char* ib_last_hip_error(void);
 int ib_version(void);

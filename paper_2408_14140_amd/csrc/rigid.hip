@@ -86,9 +86,86 @@ k_advect_markers(int64_t nl, const double* x, const double* y, const double* z,
     zn[l] = xc_np1[3 * p + 2] + o[2];
 }
 
+// Eq. (DKT_model): F_c,ij = -(m |g| / eps_c) ((|delta| - D_c)/h)^2 delta/|delta|
+// for |delta| < D_c = R_i + R_j + h, delta = X_j - X_i by the minimum image on
+// periodic axes, m the mean of the two masses.  One wavefront per particle
+// i: lane k takes the partners j = k, k + 64, ... in order, and the lanes'
+// sums are combined by a fixed butterfly, so the result is reproducible.
+constexpr int CL_WAVES = 4;
+
+__global__ void __launch_bounds__(64 * CL_WAVES)
+k_collision_forces(int32_t np, const double* __restrict__ xc, const double* __restrict__ d,
+                   const double* __restrict__ rho_p, double gnorm, double h, double eps_c,
+                   double L0, double L1, double L2, double* __restrict__ Fc)
+{
+    const int i = blockIdx.x * CL_WAVES + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= np)
+        return;
+    const double L[3] = {L0, L1, L2};
+    const double xi[3] = {xc[3 * i], xc[3 * i + 1], xc[3 * i + 2]};
+    const double di = d[i];
+    const double mi = rho_p[i] * 3.14159265358979323846 * di * di * di / 6.0;
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int j = lane; j < np; j += 64) {
+        if (j == i)
+            continue;
+        double del[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            del[c] = xc[3 * j + c] - xi[c];
+            if (L[c] > 0.0)
+                del[c] -= L[c] * floor(del[c] / L[c] + 0.5);
+        }
+        const double r2 = del[0] * del[0] + del[1] * del[1] + del[2] * del[2];
+        const double dj = d[j];
+        const double Dc = 0.5 * (di + dj) + h;
+        if (!(r2 < Dc * Dc) || r2 == 0.0)
+            continue;
+        const double dist = sqrt(r2);
+        if (!(dist < Dc))
+            continue;
+        const double mj = rho_p[j] * 3.14159265358979323846 * dj * dj * dj / 6.0;
+        const double q = (dist - Dc) / h;
+        const double mag = 0.5 * (mi + mj) * gnorm / eps_c * q * q;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            f[c] -= mag * del[c] / dist;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            f[c] += __shfl_xor(f[c], o);
+    if (lane == 0)
+        for (int c = 0; c < 3; ++c)
+            Fc[3 * i + c] = f[c];
+}
+
 }  // namespace ibx
 
 using namespace ibx;
+
+extern "C" int ib_collision_forces(const ib_level* lv, const ib_particles* p, const double* rho_p,
+                                   double g_norm, double eps_c, double* Fc, void* stream)
+{
+    int rc = check_level(lv);
+    if (rc)
+        return rc;
+    if (!p || p->np < 0 || !(eps_c > 0.0) || !(g_norm >= 0.0))
+        return IB_EINVAL;
+    if (p->np == 0)
+        return IB_OK;
+    if (!p->xc || !p->d || !rho_p || !Fc)
+        return IB_EINVAL;
+    double L[3];
+    for (int a = 0; a < 3; ++a)
+        L[a] = lv->periodic[a] ? lv->n[a] * lv->h : 0.0;
+    k_collision_forces<<<(unsigned)((p->np + CL_WAVES - 1) / CL_WAVES), 64 * CL_WAVES, 0,
+                         (hipStream_t)stream>>>(p->np, p->xc, p->d, rho_p, g_norm, lv->h, eps_c,
+                                                L[0], L[1], L[2], Fc);
+    return launch_status();
+}
 
 extern "C" int ib_rigid_update(const ib_particles* p, const double* rho_p, const double* sums_n,
                                const double* sums_np1, const double* Fc, const double* Tc,

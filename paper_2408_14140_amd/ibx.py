@@ -95,6 +95,7 @@ _backward = _sig("ib_multidirect_backward", C.c_int,
 _rigid = _sig("ib_rigid_update", C.c_int,
               [_PP, _p, _p, _p, _p, _p, _p, _d, _p, _d, _p, _p, _p, _p])
 _advect = _sig("ib_advect_markers", C.c_int, [_PM, _p, _p, _p, _p, _d, _p, _p, _p, _p])
+_collide = _sig("ib_collision_forces", C.c_int, [_PL, _PP, _p, _d, _d, _p, _p])
 _status_string = _sig("ib_status_string", C.c_char_p, [C.c_int])
 _last_hip_error = _sig("ib_last_hip_error", C.c_char_p, [])
 _version = _sig("ib_version", C.c_int, [])
@@ -104,7 +105,7 @@ EXPORTED = ("ib_count_markers", "ib_build_markers", "ib_desired_velocity", "ib_b
             "ib_plan_query", "ib_workspace_bytes", "ib_plan_profile", "ib_plan_profile_read",
             "ib_multidirect_force", "ib_plan_autotune",
             "ib_reductions_workspace", "ib_particle_reductions", "ib_backward_workspace_bytes", "ib_multidirect_backward",
-            "ib_rigid_update", "ib_advect_markers",
+            "ib_rigid_update", "ib_advect_markers", "ib_collision_forces",
             "ib_status_string", "ib_last_hip_error", "ib_version")
 
 
@@ -530,6 +531,16 @@ def advect_markers(m: Markers, xc_n, xc_np1, om_n, om_np1, dt: float, out: Marke
     _check(_advect(C.byref(mc), _ptr(xc_n), _ptr(xc_np1), _ptr(om_n), _ptr(om_np1), float(dt),
                    _ptr(out.x), _ptr(out.y), _ptr(out.z), _stream()), "ib_advect_markers")
     return out
+
+
+def collision_forces(level: DeviceLevel, parts: Particles, rho_p: torch.Tensor, g_norm: float,
+                     eps_c: float = 1e-4) -> torch.Tensor:
+    """Repulsive collision force of Eq. (DKT_model) on every particle, [np][3]."""
+    Fc = torch.empty_like(parts.xc)
+    lc, pc = level.c, parts.c
+    _check(_collide(C.byref(lc), C.byref(pc), _ptr(rho_p), float(g_norm), float(eps_c), _ptr(Fc),
+                    _stream()), "ib_collision_forces")
+    return Fc
 
 
 def version() -> int:

@@ -109,3 +109,29 @@ def test_coupled_particle_step(dev, dtype, path):
     assert rel(gw.cpu().numpy(), om1) <= 1e-11
     assert rel(gx.cpu().numpy(), xc1) <= 1e-14
     assert np.max(np.abs(gm.xyz().cpu().numpy() - m1.xyz())) <= 1e-14
+
+
+@pytest.mark.parametrize("cfg", [3, 4], ids=["spheres1000_256", "spheres20000_512"])
+def test_collision_forces_match_oracle(dev, cfg):
+    """Every particle's collision force at full size (the clumped 20000-sphere
+    workload overlaps heavily), periodic minimum image, against the oracle."""
+    import torch
+
+    import oracle as O
+    import paper_2408_14140_amd as ibx
+    announce(f"collision forces config {cfg}")
+    wl = W.config(cfg, 0, with_field=False)
+    rng = np.random.default_rng(14)
+    rho = rng.uniform(1000.0, 3000.0, wl.npart)
+    lev = wl.level
+    L = [lev.n[a] * lev.h if lev.periodic[a] else 0.0 for a in range(3)]
+    ref = O.collision_forces(wl.xc, wl.d, rho, 9.81, lev.h, 1e-4, L)
+    dl = ibx.device_level(lev, dev)
+    parts = ibx.particles(wl.xc, wl.d, wl.up, wl.om, dev)
+    got = ibx.collision_forces(dl, parts, torch.as_tensor(rho, device=dev), 9.81, 1e-4)
+    torch.cuda.synchronize()
+    g = got.cpu().numpy()
+    assert np.abs(ref).max() > 0
+    assert rel(g, ref) <= 1e-13
+    assert np.abs(g.sum(axis=0)).max() <= 1e-12 * np.abs(g).sum()
+

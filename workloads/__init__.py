@@ -208,11 +208,13 @@ def _rsa(rng, diam, nplace, max_tries=200000):
 
 def make_workload(name, n, box, ngrow, delta, ns, diam_cells, *, seed=0,
                   placement="rsa", centres=None, nmodes=32, K=8, cover_all=False,
-                  periodic=(1, 1, 1), clumps=64, clump_sigma=0.05, dt_cells=0.5):
+                  periodic=(1, 1, 1), clumps=64, clump_sigma=0.05, dt_cells=0.5,
+                  with_field=True):
     """Generic builder on the periodic unit cube with ``n`` cells per axis.
 
     ``diam_cells``: array of diameters in cells (already drawn) or a callable
-    ``rng -> array``.
+    ``rng -> array``.  ``with_field=False`` skips the velocity field (u0 is
+    None); every other draw is unchanged.
     """
     rng = np.random.default_rng(seed)
     h = 1.0 / n
@@ -233,7 +235,7 @@ def make_workload(name, n, box, ngrow, delta, ns, diam_cells, *, seed=0,
     up = rng.normal(0.0, 0.1, size=(npart, 3))
     om = rng.normal(0.0, 1.0, size=(npart, 3))
     ntup = (n, n, n)
-    u0 = fourier_field(rng, ntup, h, lo, nmodes, K)
+    u0 = fourier_field(rng, ntup, h, lo, nmodes, K) if with_field else None
     cov = None if cover_all else _coverage(ntup, h, lo, box, xc, d, delta)
     level = make_level(ntup, h, lo, periodic, box, ngrow, cov)
     return Workload(name=name, level=level, delta=delta, ns=ns, dt=dt_cells * h,
@@ -244,29 +246,30 @@ CONFIG_NAMES = ("sphere1_64", "spheres8_256", "spheres1000_256",
                 "spheres20000_512", "spheres64_128")
 
 
-def config(k, seed=0) -> Workload:
+def config(k, seed=0, with_field=True) -> Workload:
     """The five reference workloads (index 1..5 or name)."""
     if isinstance(k, str):
         k = CONFIG_NAMES.index(k) + 1
     if k == 1:
         return make_workload("sphere1_64", 64, 64, 2, 3, 2, np.array([16.0]),
                              seed=seed, centres=[[0.5, 0.5, 0.5]], nmodes=8, K=4,
-                             cover_all=True)
+                             cover_all=True, with_field=with_field)
     if k == 2:
         return make_workload("spheres8_256", 256, 32, 2, 4, 5, np.full(8, 24.0),
-                             seed=seed, cover_all=True)
+                             seed=seed, cover_all=True, with_field=with_field)
     if k == 3:
         def lognormal(rng):
             return np.clip(np.exp(np.log(16.0) + 0.3 * rng.normal(size=1000)), 8.0, 32.0)
-        return make_workload("spheres1000_256", 256, 32, 2, 4, 5, lognormal, seed=seed)
+        return make_workload("spheres1000_256", 256, 32, 2, 4, 5, lognormal, seed=seed,
+                             with_field=with_field)
     if k == 4:
         def uniform(rng):
             return rng.uniform(8.0, 24.0, size=20000)
         return make_workload("spheres20000_512", 512, 32, 2, 3, 5, uniform, seed=seed,
-                             placement="clumps")
+                             placement="clumps", with_field=with_field)
     if k == 5:
         return make_workload("spheres64_128", 128, 32, 2, 4, 3, np.full(64, 16.0),
-                             seed=seed, cover_all=True)
+                             seed=seed, cover_all=True, with_field=with_field)
     raise ValueError(k)
 
 
