@@ -174,7 +174,8 @@ int ib_spread(const ib_level* lv, const ib_markers* m, const ib_buckets* b, ib_d
 /*   Fhist (device [ns][nl][3] or NULL) receives F^1..F^ns for the adjoint. */
 /* The plan fixes kernel width, precision and path (plain: one kernel per   */
 /* sub-step, straight from global memory; batched: tile-staged LDS kernels  */
-/* fed by the buckets, ustar may alias u0).  bucket_width: markers per      */
+/* fed by the buckets, ustar may alias u0; needs at least 16 cells per axis */
+/* and box <= 512, else IB_EUNSUPPORTED).  bucket_width: markers per        */
 /* interpolation work item (64, 128 or 256; 0 = 256).  spread_wgs_per_cu:   */
 /* cap on resident spreading workgroups per compute unit (1..32; 0 = 16),  */
 /* lowered to what fits.  Interpolation runs as many workgroups as fit.     */

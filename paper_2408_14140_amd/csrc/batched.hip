@@ -24,8 +24,9 @@
 //            staged in LDS, one thread per marker.
 //   spread   work item = one tile with a non-empty source list; one wavefront,
 //            lane = (y, z) row of the tile accumulated in registers.  Result
-//            to the compact per-tile G slots, or in the last iteration to the
-//            caller's f and ustar.  No float atomics anywhere.
+//            to the compact per-tile G slots.
+//   finalize f and ustar = u0 + dt G on every valid cell of the covered boxes,
+//            box-wide rows per workgroup.  No float atomics anywhere.
 #include "paths.h"
 
 namespace ibx {
@@ -200,32 +201,51 @@ int resident_grid(int ncu, int cap)
 
 // ------------------------------------------------------------------ fill
 
-// Tiles of covered boxes that no marker reaches: f = 0, ustar = u0 (all = 1:
-// every tile).  One workgroup per tile.
+// Last step of Algorithm 1 on every valid cell of the covered boxes:
+// f = G^ns and ustar = u0 + dt G^ns, with G = 0 on tiles no marker reaches
+// (and everywhere when use_g is 0).  One workgroup per (box, row of tiles in
+// y, z plane): box-wide x rows, so the box layout is written in long runs.
+// In place (ustar == u0) only the cells with a force are rewritten.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_fill_inactive(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ u0,
-                T* __restrict__ ustar, T* __restrict__ f, int all)
+k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, const T* u0,
+           T* ustar, T* __restrict__ f, double dt, int use_g)
 {
-    for (int64_t t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
-        if (!all && slot[t] >= 0)
-            continue;
-        int lo[3];
-        tile_coords(g, (int)t, lo);
-        const int64_t tb = tile_base(g, lo);
-        if (tb < 0)
-            continue;
-        for (int r = threadIdx.x; r < TILE_CELLS; r += blockDim.x) {
-            const int64_t off = tb + (r & 7) + (int64_t)g.ext * (((r >> 3) & 7) + g.ext * (r >> 6));
+    __shared__ int tslot[64];                 // G slot of each tile along the row
+    const int B = g.box;
+    const int nty = B / TILE, ntx = B / TILE;
+    const int64_t items = (int64_t)g.nbox * nty * B;
+    const T tdt = (T)dt;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int bid = (int)(it / ((int64_t)nty * B));
+        const int rem = (int)(it - (int64_t)bid * nty * B);
+        const int ty = rem / B, lz = rem - ty * B;
+        const int bx0 = g.box_lo[3 * bid], by0 = g.box_lo[3 * bid + 1], bz0 = g.box_lo[3 * bid + 2];
+        const int cz = bz0 + lz, cyt = (by0 >> 3) + ty;
+        for (int k = threadIdx.x; k < ntx; k += blockDim.x)
+            tslot[k] = use_g ? slot[(bx0 >> 3) + k + g.nt[0] * (cyt + g.nt[1] * (cz >> 3))] : -1;
+        __syncthreads();
+        for (int q = threadIdx.x; q < TILE * B; q += blockDim.x) {
+            const int yy = q / B, lx = q - yy * B;
+            const int ly = ty * TILE + yy;
+            const int s = tslot[lx >> 3];
+            const int64_t off = (int64_t)bid * g.bstride +
+                                ((int64_t)(lz + g.ngrow) * g.ext + (ly + g.ngrow)) * g.ext +
+                                (lx + g.ngrow);
+            const int64_t go = (int64_t)s * 3 * TILE_CELLS + (lx & 7) + TILE * (yy + TILE * (cz & 7));
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
+                const T v = s >= 0 ? G[go + c * TILE_CELLS] : T(0);
                 const int64_t o = off + c * g.cstride;
                 if (f)
-                    f[o] = T(0);
-                if (ustar != u0)
+                    f[o] = v;
+                if (s >= 0)
+                    ustar[o] = u0[o] + tdt * v;
+                else if (ustar != u0)
                     ustar[o] = u0[o];
             }
         }
+        __syncthreads();
     }
 }
 
@@ -337,9 +357,10 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     BatchedWs<T> w = carve_batched<T>(g, nl, cfg.bw, ws, ws_bytes, &need);
     const unsigned gm = (unsigned)((nl + 255) / 256 > 0 ? (nl + 255) / 256 : 1);
     const unsigned gt = (unsigned)((T_ + 255) / 256);
-    const unsigned gfill = (unsigned)(T_ < 8192 ? (T_ > 0 ? T_ : 1) : 8192);   // one block per tile
+    const int64_t nfin = (int64_t)g.nbox * (g.box / TILE) * g.box;
+    const unsigned gfin = (unsigned)(nfin < 65535 ? (nfin > 0 ? nfin : 1) : 65535);
     if (nl == 0) {
-        k_fill_inactive<T><<<gfill, 256, 0, st>>>(g, w.slot, u0, ustar, f, 1);
+        k_finalize<T><<<gfin, 256, 0, st>>>(g, w.slot, w.G, u0, ustar, f, dt, 0);
         if (resid)
             k_zero<double><<<1, 64, 0, st>>>(ns + 1, resid);
         return launch_status();
@@ -368,7 +389,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         sum_to(w.e2, nl, w.part, resid + 0, true, st);
     if (ns == 0) {
         // no iteration: ustar = u0, f = 0, F = 0
-        k_fill_inactive<T><<<gfill, 256, 0, st>>>(g, w.slot, u0, ustar, f, 1);
+        k_finalize<T><<<gfin, 256, 0, st>>>(g, w.slot, w.G, u0, ustar, f, dt, 0);
         k_zero<T><<<gm, 256, 0, st>>>(3 * nl, F);
         return launch_status();
     }
@@ -376,10 +397,9 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.f4, Fhist);
     for (int mi = 2; mi <= ns; ++mi) {
         IBX_PROF_BEGIN(PK_SPREAD);
-        k_spread_tiles<T, P, 0>
-            <<<resident_grid<k_spread_tiles<T, P, 0>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(g, nl, dt, w.active, w.nactive,
-                                                           b->src_offs, b->src_idx, w.s, w.G,
-                                                           u0, ustar, f, 0);
+        k_spread_tiles<T, P>
+            <<<resident_grid<k_spread_tiles<T, P>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
+                w.active, w.nactive, b->src_offs, b->src_idx, g, w.s, w.G);
         IBX_PROF_END();
         IBX_PROF_BEGIN(PK_INTERP_G);
         launch_interp<T, P, 1>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_g, w.s, e2);
@@ -391,16 +411,13 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
                                             Fhist + (int64_t)(mi - 1) * 3 * nl);
     }
     IBX_PROF_BEGIN(PK_SPREAD_FINAL);
-    k_spread_tiles<T, P, 1>
-        <<<resident_grid<k_spread_tiles<T, P, 1>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(g, nl, dt, w.active, w.nactive,
-                                                       b->src_offs, b->src_idx, w.s, w.G, u0,
-                                                       ustar, f, resid ? 1 : 0);
+    k_spread_tiles<T, P>
+        <<<resident_grid<k_spread_tiles<T, P>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
+            w.active, w.nactive, b->src_offs, b->src_idx, g, w.s, w.G);
     IBX_PROF_END();
-    if (f || ustar != u0) {
-        IBX_PROF_BEGIN(PK_FILL);
-        k_fill_inactive<T><<<gfill, 256, 0, st>>>(g, w.slot, u0, ustar, f, 0);
-        IBX_PROF_END();
-    }
+    IBX_PROF_BEGIN(PK_FILL);
+    k_finalize<T><<<gfin, 256, 0, st>>>(g, w.slot, w.G, u0, ustar, f, dt, 1);
+    IBX_PROF_END();
     if (resid) {
         IBX_PROF_BEGIN(PK_RESID);
         launch_interp<T, P, 2>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_g, w.s,
@@ -431,6 +448,9 @@ int batched_multidirect(const Grid& g, int P, ib_prec prec, const BatchedCfg& cf
 {
     // a stencil must never reach the same tile from both sides of a periodic axis
     if (g.n[0] < 2 * TILE || g.n[1] < 2 * TILE || g.n[2] < 2 * TILE)
+        return IB_EUNSUPPORTED;
+    // the finalize step holds one box row of tile slots in LDS
+    if (g.box > 64 * TILE)
         return IB_EUNSUPPORTED;
     if (prec == IB_F64) {
         if (P == 3)

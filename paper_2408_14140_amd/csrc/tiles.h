@@ -381,9 +381,7 @@ __device__ inline int wave_exclusive_sum(int v)
     return s;
 }
 
-// One wavefront per workgroup.  FINAL = 0: store the tile to its G slot.
-// FINAL = 1: store f (if any) and ustar = u0 + dt G on the tile; also the G
-// slot when keep_g is set (final residual).
+// One wavefront per workgroup; the tile is stored to its G slot.
 //
 // Sources are staged 64 at a time as structure-of-arrays in LDS: the weight
 // of every tile x cell, y row and z row (zero outside the stencil) and
@@ -391,12 +389,11 @@ __device__ inline int wave_exclusive_sum(int v)
 // 64-bit set of staged sources whose stencil covers it; a lane's own set is
 // the AND of its two, and the lane visits exactly those sources in list
 // order.  The staging arrays share LDS with the transpose buffer.
-template <typename T, int P, int FINAL>
+template <typename T, int P>
 __global__ void __launch_bounds__(64)
-k_spread_tiles(Grid g, int64_t nl, double dt, const int32_t* __restrict__ active,
-               const int32_t* __restrict__ nactive, const int32_t* __restrict__ src_offs,
-               const int32_t* __restrict__ src_idx, MarkerData<T> s, T* __restrict__ G,
-               const T* __restrict__ u0, T* __restrict__ ustar, T* __restrict__ f, int keep_g)
+k_spread_tiles(const int32_t* __restrict__ active, const int32_t* __restrict__ nactive,
+               const int32_t* __restrict__ src_offs, const int32_t* __restrict__ src_idx,
+               Grid g, MarkerData<T> s, T* __restrict__ G)
 {
     constexpr int NW = 3 * TILE + 3;                       // staged values per source
     constexpr int NBUF = NW * 64 > 3 * TILE_CELLS ? NW * 64 : 3 * TILE_CELLS;
@@ -551,29 +548,11 @@ k_spread_tiles(Grid g, int64_t nl, double dt, const int32_t* __restrict__ active
             tr[2 * TILE_CELLS + cell0 + x] = acc[x][2];
         }
         __syncthreads();
-        if (!FINAL || keep_g) {
-            T* gs = G + (int64_t)a * 3 * TILE_CELLS;
-            for (int q = lane; q < TILE_CELLS; q += 64) {
-                gs[q] = tr[q];
-                gs[q + TILE_CELLS] = tr[TILE_CELLS + q];
-                gs[q + 2 * TILE_CELLS] = tr[2 * TILE_CELLS + q];
-            }
-        }
-        const int64_t tb = FINAL ? tile_base(g, lo) : -1;
-        if (FINAL && tb >= 0) {
-            const T tdt = (T)dt;
-            for (int q = lane; q < TILE_CELLS; q += 64) {
-                const int64_t off = tb + (q & 7) + (int64_t)g.ext * (((q >> 3) & 7) +
-                                                                     g.ext * (q >> 6));
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const int64_t o = off + c * g.cstride;
-                    const T v = tr[c * TILE_CELLS + q];
-                    if (f)
-                        f[o] = v;
-                    ustar[o] = u0[o] + tdt * v;
-                }
-            }
+        T* gs = G + (int64_t)a * 3 * TILE_CELLS;
+        for (int q = lane; q < TILE_CELLS; q += 64) {
+            gs[q] = tr[q];
+            gs[q + TILE_CELLS] = tr[TILE_CELLS + q];
+            gs[q + 2 * TILE_CELLS] = tr[2 * TILE_CELLS + q];
         }
         __syncthreads();
     }
