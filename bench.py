@@ -47,21 +47,23 @@ def support_cells(level, b, delta):
     return int(torch.unique(lin.reshape(-1)).numel())
 
 
-def model_bytes(kind, s, P, N, S, A, C):
+def model_bytes(kind, s, P, N, S, A, C, ncov):
     """Compulsory bytes of one launch of a batched-path kernel class.
 
     N markers, S source-list entries, A active tiles (512 cells each), C
-    support cells, s field bytes.  Marker records: stencil base 12 B, weights
-    3P*s, dV/h^3 s, U^d / D / F 3s each."""
+    support cells, ncov cells of the covered boxes, s field bytes.  Marker
+    records: stencil base 12 B, weights 3P*s, dV/h^3 s, U^d / D / F 3s each.
+    The loop runs in place (u* overwrites u0)."""
     rec = 12 + 3 * P * s
     if kind == "interp_u0":
         return 3 * s * C + N * (rec + 3 * s + 6 * s)
-    if kind == "spread":
+    if kind in ("spread", "spread_final"):
         return N * (rec + s + 3 * s) + 4 * S + 3 * s * 512 * A
     if kind == "interp_g":
         return 3 * s * 512 * A + N * (rec + 3 * s + 3 * s + 3 * s)
-    if kind == "spread_final":
-        return N * (rec + s + 3 * s) + 4 * S + 3 * 3 * s * 512 * A
+    if kind == "fill":
+        # f on every covered cell; G read, u0 read and u* written on active tiles
+        return 3 * s * ncov + 9 * s * 512 * A
     return None
 
 
@@ -236,10 +238,17 @@ def run():
         loop_only()
     prof = plan.profile_read(reset=True)
     plan.profile(False)
-    kern = {k: {"ms_total": v[0], "calls": v[1], "avg_us": 1e3 * v[0] / v[1]}
-            for k, v in prof.items() if v[1] > 0}
+    ncov = lev.nbox * lev.box ** 3
+    kern = {}
+    for k, v in prof.items():
+        if v[1] > 0:
+            kern[k] = {"ms_total": v[0], "calls": v[1], "avg_us": 1e3 * v[0] / v[1]}
+            mb = model_bytes(k, 4, P, N, S, A, C, ncov)
+            if mb:
+                kern[k]["model_bytes"] = mb
+                kern[k]["model_gbs"] = mb / (1e-3 * v[0] / v[1]) / 1e9
     dom = max(kern, key=lambda k: kern[k]["ms_total"])
-    nb = model_bytes(dom, 4, P, N, S, A, C)
+    nb = model_bytes(dom, 4, P, N, S, A, C, ncov)
     avg_s = kern[dom]["avg_us"] * 1e-6
     achieved = nb / avg_s / 1e9 if nb else None
     roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
