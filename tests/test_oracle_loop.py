@@ -154,3 +154,44 @@ def test_sequential_equals_jacobi_for_disjoint_supports(oracle_mod):
     b = oracle_mod.multidirect(g, 4, 3, 0.5 * h, m, xc, up, om, u0, order="sequential")
     assert np.max(np.abs(a["F"] - b["F"])) <= 1e-14 * np.abs(a["F"]).max()
     assert np.max(np.abs(a["ustar"] - b["ustar"])) <= 1e-14 * np.abs(a["ustar"]).max()
+
+
+def _sub(oracle_mod, m, p):
+    """Markers of particle p alone (pid 0)."""
+    a, z = int(m.offs[p]), int(m.offs[p + 1])
+    return oracle_mod.Markers(m.x[a:z], m.y[a:z], m.z[a:z], np.zeros(z - a, np.int32),
+                              m.dv[p:p + 1], np.array([0, z - a], np.int64))
+
+
+def test_sequential_order_composes_single_particle_loops(oracle_mod):
+    """Sec. 3.1: with several particles each runs the N_s loop in turn.  For
+    two particles whose supports overlap, the sequential order equals particle
+    0's loop from u0 followed by particle 1's loop from the field particle 0
+    left, with f the sum of the two; it differs from the Jacobi order and from
+    the other particle order."""
+    n = 40
+    h = 1.0 / n
+    g = oracle_mod.grid(n, h)
+    xc = np.array([[0.4, 0.5, 0.5], [0.4 + 10.5 * h, 0.52, 0.49]])
+    d = np.array([9.0 * h, 10.0 * h])
+    m = oracle_mod.build_markers(xc, d, h)
+    rng = np.random.default_rng(21)
+    u0 = rng.normal(size=(3, n, n, n))
+    up = rng.normal(0, 0.1, (2, 3))
+    om = rng.normal(0, 1, (2, 3))
+    dt, ns, P = 0.5 * h, 3, 4
+    seq = oracle_mod.multidirect(g, P, ns, dt, m, xc, up, om, u0, order="sequential")
+    r0 = oracle_mod.multidirect(g, P, ns, dt, _sub(oracle_mod, m, 0), xc[:1], up[:1], om[:1], u0)
+    r1 = oracle_mod.multidirect(g, P, ns, dt, _sub(oracle_mod, m, 1), xc[1:], up[1:], om[1:],
+                                r0["ustar"])
+    k = int(m.offs[1])
+    scale = np.abs(seq["F"]).max()
+    assert np.max(np.abs(seq["F"][:k] - r0["F"])) <= 1e-14 * scale
+    assert np.max(np.abs(seq["F"][k:] - r1["F"])) <= 1e-14 * scale
+    assert np.max(np.abs(seq["ustar"] - r1["ustar"])) <= 1e-14 * np.abs(u0).max()
+    assert np.max(np.abs(seq["f"] - (r0["f"] + r1["f"]))) <= 1e-14 * np.abs(seq["f"]).max()
+    jac = oracle_mod.multidirect(g, P, ns, dt, m, xc, up, om, u0)
+    assert np.max(np.abs(jac["F"] - seq["F"])) > 1e-6 * scale
+    # particle 1 first
+    rb = oracle_mod.multidirect(g, P, ns, dt, _sub(oracle_mod, m, 1), xc[1:], up[1:], om[1:], u0)
+    assert np.max(np.abs(seq["F"][k:] - rb["F"])) > 1e-6 * scale
