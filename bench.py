@@ -134,6 +134,8 @@ def run():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--bucket-width", type=int, default=0)
     ap.add_argument("--spread-wgs", type=int, default=0)
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the particle-by-particle (level by level) loop")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the plan's default bucket width and spreading residency")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -323,6 +325,28 @@ def run():
         out["speedup_fp32_batched_vs_fp64_plain"] = ms64 / ms_loop
         log(f"fp64 plain loop {ms64:.3f} ms")
         del u64, us64, f64, F64
+
+    if not args.no_sequential:
+        # the particle-by-particle order: conflict levels, then one loop per level
+        q = plan.query()
+        pseq = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, bucket_width=q["bucket_width"],
+                        spread_wgs_per_cu=q["spread_wgs_per_cu"])
+        useq = torch.empty_like(u32)
+        fseq = torch.empty_like(u32)
+        Fseq = torch.empty_like(F32)
+        levels = ibx.particle_levels(dl, parts, P)
+        ms_lv = timed(lambda: ibx.particle_levels(dl, parts, P), max(2, args.steps // 5))
+
+        def seq():
+            pseq.multidirect_sequential(dl, parts, m, ns, dt, u32, levels=levels, ustar=useq,
+                                        f=fseq, F=Fseq)
+
+        seq()
+        ms_seq = timed(seq, max(2, args.steps // 5))
+        out["sequential"] = {"levels": levels[1], "levels_ms": ms_lv, "loop_ms": ms_seq,
+                             "vs_jacobi_loop": ms_seq / ms_loop}
+        log(f"sequential: {levels[1]} levels in {ms_lv:.3f} ms, loop {ms_seq:.3f} ms")
+        del useq, fseq, Fseq
 
     if not args.no_backward:
         wl5 = W.config(5, args.seed)

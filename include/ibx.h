@@ -312,6 +312,51 @@ int ib_advect_markers(const ib_markers* m, const double* xc_n, const double* xc_
 int ib_collision_forces(const ib_level* lv, const ib_particles* p, const double* rho_p,
                         double g_norm, double eps_c, double* Fc, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Particle-by-particle order of the coupling loop (Sec. 3.1, the remarks   */
+/* after Algorithm 1: each particle runs the N_s loop in turn on the field  */
+/* its predecessors left; the corrected forces of all particles add up).    */
+/* ---------------------------------------------------------------------- */
+
+/* Conflict levels.  level[j] (device int32 [np], out) = 0 when no earlier   */
+/* particle's kernel support may share a cell with particle j's, else 1 +   */
+/* the largest level among those that may.  "May share" is the conservative */
+/* test |X_i - X_j| < (D_i + D_j)/2 + 2 P h (minimum image on periodic      */
+/* axes; it assumes every marker lies within D/2 of its centroid).  Particles */
+/* of one level have disjoint supports, and every conflicting pair keeps    */
+/* its index order across levels.  *nlevels (host, out) = 1 + max level (0  */
+/* when np = 0).  ws: device workspace of ib_levels_workspace(np) bytes.    */
+/* Iterates on the device until the levels stop changing, reading a flag    */
+/* back after every pass: synchronizes the stream (do not capture).         */
+size_t ib_levels_workspace(int32_t np);
+int ib_particle_levels(const ib_level* lv, const ib_particles* p, ib_delta delta,
+                       int32_t* level, int32_t* nlevels, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* The loop in particle order.  Particles are grouped by level (stable in    */
+/* index), and the levels run one after another, each as one batched loop  */
+/* of ib_multidirect_force over its particles on the field the previous     */
+/* levels left: u^(0) of level c is u* of level c-1 (u0 for the first).     */
+/* Outputs: ustar = u* after the last level, f = the sum of every level's    */
+/* f^ns, F = every marker's F^ns (marker order), as the particle-by-particle */
+/* sweep gives them up to rounding.  ustar may equal u0; f may be NULL.      */
+/* level/nlevels as from ib_particle_levels (any level function with        */
+/* disjoint supports within a level gives a valid order; nlevels <= 4096,   */
+/* else IB_EUNSUPPORTED).  Markers must be contiguous per particle as given */
+/* by m->offs (pid is not read).  flag (device int32 [2] or NULL) receives  */
+/* the OR of the per-level bucketing flags (ib_buckets.flag).  Batched plans */
+/* only (IB_EUNSUPPORTED otherwise); no graph replay, no residuals.  Reads  */
+/* the level boundaries back once: synchronizes the stream (do not capture). */
+/* ws: device workspace of ib_sequential_workspace_bytes(plan, lv, np, nl,   */
+/* ns) bytes.  IB_EINVAL (after that synchronization, nothing else run) for */
+/* a level outside [0, nlevels) or offs not a partition of [0, nl).         */
+size_t ib_sequential_workspace_bytes(const ib_plan* plan, const ib_level* lv, int32_t np,
+                                     int64_t nl, int32_t ns);
+int ib_multidirect_sequential(ib_plan* plan, const ib_level* lv, const ib_particles* p,
+                              const ib_markers* m, int32_t ns, double dt, const int32_t* level,
+                              int32_t nlevels, const void* u0, void* ustar, void* f, void* F,
+                              int32_t* flag, void* ws, size_t ws_bytes, void* stream);
+
 const char* ib_status_string(int status);
 const char* ib_last_hip_error(void);
 int ib_version(void);

@@ -345,6 +345,53 @@ extern "C" int ib_multidirect_force(ib_plan* plan, const ib_level* lv, const ib_
     return IB_OK;
 }
 
+// Particle-by-particle order (Sec. 3.1): conflict levels run one after
+// another, each as a batched loop over its particles.
+extern "C" size_t ib_sequential_workspace_bytes(const ib_plan* plan, const ib_level* lv,
+                                                int32_t np, int64_t nl, int32_t ns)
+{
+    (void)ns;
+    if (!plan || check_level(lv) || nl < 0 || np < 0 ||
+        resolved_path(plan) != IB_PATH_BATCHED)
+        return 0;
+    Grid g = make_grid(lv);
+    return sequential_workspace(lv, g, plan->prec, np, nl, cfg_of(plan));
+}
+
+extern "C" int ib_multidirect_sequential(ib_plan* plan, const ib_level* lv,
+                                         const ib_particles* p, const ib_markers* m, int32_t ns,
+                                         double dt, const int32_t* level, int32_t nlevels,
+                                         const void* u0, void* ustar, void* f, void* F,
+                                         int32_t* flag, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!plan)
+        return IB_EINVAL;
+    int rc = check_level(lv);
+    if (rc)
+        return rc;
+    if (!p || !m || ns < 0 || ns > 1000 || !(dt > 0.0) || m->nl < 0 || p->np < 0 ||
+        m->nl > (int64_t)INT32_MAX / 8 || !u0 || !ustar)
+        return IB_EINVAL;
+    if (resolved_path(plan) != IB_PATH_BATCHED)
+        return IB_EUNSUPPORTED;
+    if (m->nl > 0) {
+        if (!m->x || !m->y || !m->z || !m->dv || !m->offs || !p->xc || !p->d || !p->up ||
+            !p->om || !F || !level)
+            return IB_EINVAL;
+        if (nlevels < 1 || nlevels > p->np)
+            return IB_EINVAL;
+        if (nlevels > SEQ_MAX_LEVELS)
+            return IB_EUNSUPPORTED;
+    }
+    const size_t need = ib_sequential_workspace_bytes(plan, lv, p->np, m->nl, ns);
+    if (!ws || ws_bytes < need)
+        return IB_EWORKSPACE;
+    Grid g = make_grid(lv);
+    return sequential_multidirect(lv, g, plan->P, plan->prec, cfg_of(plan), p, m, ns, dt, level,
+                                  nlevels, u0, ustar, f, F, flag, ws, ws_bytes,
+                                  (hipStream_t)stream);
+}
+
 // Autotuning: time the batched loop for every bucket width and spreading
 // residency on the caller's inputs and keep the fastest.
 extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_particles* p,

@@ -205,11 +205,12 @@ int resident_grid(int ncu, int cap)
 // f = G^ns and ustar = u0 + dt G^ns, with G = 0 on tiles no marker reaches
 // (and everywhere when use_g is 0).  One workgroup per (box, row of tiles in
 // y, z plane): box-wide x rows, so the box layout is written in long runs.
-// In place (ustar == u0) only the cells with a force are rewritten.
+// In place (ustar == u0) only the cells with a force are rewritten.  With
+// f_acc, f += G^ns instead, on the cells with a force only.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, const T* u0,
-           T* ustar, T* __restrict__ f, double dt, int use_g)
+           T* ustar, T* __restrict__ f, double dt, int use_g, int f_acc)
 {
     __shared__ int tslot[64];                 // G slot of each tile along the row
     const int B = g.box;
@@ -237,8 +238,10 @@ k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, co
             for (int c = 0; c < 3; ++c) {
                 const T v = s >= 0 ? G[go + c * TILE_CELLS] : T(0);
                 const int64_t o = off + c * g.cstride;
-                if (f)
+                if (f && !f_acc)
                     f[o] = v;
+                else if (f && s >= 0)
+                    f[o] += v;
                 if (s >= 0)
                     ustar[o] = u0[o] + tdt * v;
                 else if (ustar != u0)
@@ -346,7 +349,7 @@ template <typename T, int P>
 static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles* p,
                        const ib_markers* m, const ib_buckets* b, int ns, double dt,
                        const T* u0, T* ustar, T* f, T* F, double* resid, T* Fhist, void* ws,
-                       size_t ws_bytes, hipStream_t st)
+                       size_t ws_bytes, hipStream_t st, int f_acc)
 {
     const int64_t nl = m->nl;
     const int64_t T_ = g.ntiles;
@@ -360,7 +363,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     const int64_t nfin = (int64_t)g.nbox * (g.box / TILE) * g.box;
     const unsigned gfin = (unsigned)(nfin < 65535 ? (nfin > 0 ? nfin : 1) : 65535);
     if (nl == 0) {
-        k_finalize<T><<<gfin, 256, 0, st>>>(g, w.slot, w.G, u0, ustar, f, dt, 0);
+        k_finalize<T><<<gfin, 256, 0, st>>>(g, w.slot, w.G, u0, ustar, f, dt, 0, f_acc);
         if (resid)
             k_zero<double><<<1, 64, 0, st>>>(ns + 1, resid);
         return launch_status();
@@ -389,7 +392,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         sum_to(w.e2, nl, w.part, resid + 0, true, st);
     if (ns == 0) {
         // no iteration: ustar = u0, f = 0, F = 0
-        k_finalize<T><<<gfin, 256, 0, st>>>(g, w.slot, w.G, u0, ustar, f, dt, 0);
+        k_finalize<T><<<gfin, 256, 0, st>>>(g, w.slot, w.G, u0, ustar, f, dt, 0, f_acc);
         k_zero<T><<<gm, 256, 0, st>>>(3 * nl, F);
         return launch_status();
     }
@@ -416,7 +419,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
             w.active, w.nactive, b->src_offs, b->src_idx, g, w.s, w.G);
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_FILL);
-    k_finalize<T><<<gfin, 256, 0, st>>>(g, w.slot, w.G, u0, ustar, f, dt, 1);
+    k_finalize<T><<<gfin, 256, 0, st>>>(g, w.slot, w.G, u0, ustar, f, dt, 1, f_acc);
     IBX_PROF_END();
     if (resid) {
         IBX_PROF_BEGIN(PK_RESID);
@@ -444,7 +447,7 @@ size_t batched_workspace(const Grid& g, ib_prec prec, int64_t nl, const BatchedC
 int batched_multidirect(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg,
                         const ib_particles* p, const ib_markers* m, const ib_buckets* b, int ns,
                         double dt, const void* u0, void* ustar, void* f, void* F, double* resid,
-                        void* Fhist, void* ws, size_t ws_bytes, hipStream_t st)
+                        void* Fhist, void* ws, size_t ws_bytes, hipStream_t st, int f_acc)
 {
     // a stencil must never reach the same tile from both sides of a periodic axis
     if (g.n[0] < 2 * TILE || g.n[1] < 2 * TILE || g.n[2] < 2 * TILE)
@@ -456,17 +459,18 @@ int batched_multidirect(const Grid& g, int P, ib_prec prec, const BatchedCfg& cf
         if (P == 3)
             return run_batched<double, 3>(g, cfg, p, m, b, ns, dt, (const double*)u0,
                                           (double*)ustar, (double*)f, (double*)F, resid,
-                                          (double*)Fhist, ws, ws_bytes, st);
+                                          (double*)Fhist, ws, ws_bytes, st, f_acc);
         return run_batched<double, 4>(g, cfg, p, m, b, ns, dt, (const double*)u0,
                                       (double*)ustar, (double*)f, (double*)F, resid,
-                                      (double*)Fhist, ws, ws_bytes, st);
+                                      (double*)Fhist, ws, ws_bytes, st, f_acc);
     }
     if (P == 3)
         return run_batched<float, 3>(g, cfg, p, m, b, ns, dt, (const float*)u0, (float*)ustar,
                                      (float*)f, (float*)F, resid, (float*)Fhist, ws, ws_bytes,
-                                     st);
+                                     st, f_acc);
     return run_batched<float, 4>(g, cfg, p, m, b, ns, dt, (const float*)u0, (float*)ustar,
-                                 (float*)f, (float*)F, resid, (float*)Fhist, ws, ws_bytes, st);
+                                 (float*)f, (float*)F, resid, (float*)Fhist, ws, ws_bytes, st,
+                                 f_acc);
 }
 
 }  // namespace ibx

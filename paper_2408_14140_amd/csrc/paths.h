@@ -35,7 +35,17 @@ size_t batched_workspace(const Grid& g, ib_prec prec, int64_t nl, const BatchedC
 int batched_multidirect(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg,
                         const ib_particles* p, const ib_markers* m, const ib_buckets* b, int ns,
                         double dt, const void* u0, void* ustar, void* f, void* F, double* resid,
-                        void* Fhist, void* ws, size_t ws_bytes, hipStream_t st);
+                        void* Fhist, void* ws, size_t ws_bytes, hipStream_t st, int f_acc = 0);
+
+// Particle-by-particle order of the loop, run level by level (sequential.hip).
+constexpr int SEQ_MAX_LEVELS = 4096;
+size_t sequential_workspace(const ib_level* lv, const Grid& g, ib_prec prec, int32_t np,
+                            int64_t nl, const BatchedCfg& cfg);
+int sequential_multidirect(const ib_level* lv, const Grid& g, int P, ib_prec prec,
+                           const BatchedCfg& cfg, const ib_particles* p, const ib_markers* m,
+                           int ns, double dt, const int32_t* level, int32_t nlevels,
+                           const void* u0, void* ustar, void* f, void* F, int32_t* flag,
+                           void* ws, size_t ws_bytes, hipStream_t st);
 
 }  // namespace ibx
 

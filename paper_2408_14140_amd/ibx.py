@@ -96,6 +96,11 @@ _rigid = _sig("ib_rigid_update", C.c_int,
               [_PP, _p, _p, _p, _p, _p, _p, _d, _p, _d, _p, _p, _p, _p])
 _advect = _sig("ib_advect_markers", C.c_int, [_PM, _p, _p, _p, _p, _d, _p, _p, _p, _p])
 _collide = _sig("ib_collision_forces", C.c_int, [_PL, _PP, _p, _d, _d, _p, _p])
+_lv_ws = _sig("ib_levels_workspace", _sz, [_i32])
+_levels = _sig("ib_particle_levels", C.c_int, [_PL, _PP, C.c_int, _p, _p, _p, _sz, _p])
+_seq_ws = _sig("ib_sequential_workspace_bytes", _sz, [_p, _PL, _i32, _i64, _i32])
+_sequential = _sig("ib_multidirect_sequential", C.c_int,
+                   [_p, _PL, _PP, _PM, _i32, _d, _p, _i32, _p, _p, _p, _p, _p, _p, _sz, _p])
 _status_string = _sig("ib_status_string", C.c_char_p, [C.c_int])
 _last_hip_error = _sig("ib_last_hip_error", C.c_char_p, [])
 _version = _sig("ib_version", C.c_int, [])
@@ -106,7 +111,8 @@ EXPORTED = ("ib_count_markers", "ib_build_markers", "ib_desired_velocity", "ib_b
             "ib_multidirect_force", "ib_plan_autotune",
             "ib_reductions_workspace", "ib_particle_reductions", "ib_backward_workspace_bytes", "ib_multidirect_backward",
             "ib_rigid_update", "ib_advect_markers", "ib_collision_forces",
-            "ib_status_string", "ib_last_hip_error", "ib_version")
+            "ib_levels_workspace", "ib_particle_levels", "ib_sequential_workspace_bytes",
+            "ib_multidirect_sequential", "ib_status_string", "ib_last_hip_error", "ib_version")
 
 
 class IbxError(RuntimeError):
@@ -463,6 +469,34 @@ class Plan:
         out["loop_ms"] = ms.value
         return out
 
+    def multidirect_sequential(self, level: DeviceLevel, parts: Particles, m: Markers, ns: int,
+                               dt: float, u0: torch.Tensor, levels=None, ustar=None, f=None,
+                               F=None, flag=None, want_f: bool = True):
+        """Algorithm 1 particle by particle, run as conflict levels one after
+        another (batched plans only; synchronizes the current stream).
+        ``levels`` = (level tensor, count) from :func:`particle_levels`, computed
+        here when omitted."""
+        dev = u0.device
+        if u0.dtype != self.dtype:
+            raise TypeError("u0 dtype differs from the plan precision")
+        if levels is None:
+            levels = particle_levels(level, parts, self.delta)
+        lvl, nlev = levels
+        if ustar is None:
+            ustar = torch.empty_like(u0)
+        if f is None and want_f:
+            f = torch.empty_like(u0)
+        if F is None:
+            F = torch.empty((m.nl, 3), dtype=u0.dtype, device=dev)
+        lc, pc, mc = level.c, parts.c, m.c
+        nb = int(_seq_ws(self._h, C.byref(lc), parts.np, m.nl, int(ns)))
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+        _check(_sequential(self._h, C.byref(lc), C.byref(pc), C.byref(mc), int(ns), float(dt),
+                           _ptr(lvl), int(nlev), _ptr(u0), _ptr(ustar), _ptr(f), _ptr(F),
+                           _ptr(flag), _ptr(ws), int(ws.numel()), _stream()),
+               "ib_multidirect_sequential")
+        return ustar, f, F
+
     def backward(self, level, parts, m, b, ns, dt, u0, Fhist, g_ustar=None, g_f=None,
                  g_F=None):
         dev = u0.device
@@ -541,6 +575,20 @@ def collision_forces(level: DeviceLevel, parts: Particles, rho_p: torch.Tensor, 
     _check(_collide(C.byref(lc), C.byref(pc), _ptr(rho_p), float(g_norm), float(eps_c), _ptr(Fc),
                     _stream()), "ib_collision_forces")
     return Fc
+
+
+def particle_levels(level: DeviceLevel, parts: Particles, delta: int):
+    """Conflict level of every particle for the particle-by-particle order of
+    the loop: (int32 tensor [np], number of levels).  Synchronizes the current
+    stream."""
+    dev = parts.xc.device
+    lvl = torch.empty(max(parts.np, 1), dtype=torch.int32, device=dev)[:parts.np]
+    ws = torch.empty(max(int(_lv_ws(parts.np)), 1), dtype=torch.uint8, device=dev)
+    n = C.c_int32(0)
+    lc, pc = level.c, parts.c
+    _check(_levels(C.byref(lc), C.byref(pc), int(delta), _ptr(lvl), C.byref(n), _ptr(ws),
+                   int(ws.numel()), _stream()), "ib_particle_levels")
+    return lvl, int(n.value)
 
 
 def version() -> int:
