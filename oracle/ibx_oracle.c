@@ -27,9 +27,10 @@
  *     F^0 = 0; f^m is recomputed from zero every iteration.  A particle-by-
  *     particle ("sequential") variant is provided for comparison.
  *
- * parity unpinned: the Fibonacci spiral's orientation and the sequential
- * variant on particles with overlapping supports are fixed by the readings
- * above, not by the paper.
+ * parity unpinned: the Fibonacci spiral's orientation is fixed by the reading
+ * above, not by the paper.  The sequential variant is pinned by composition
+ * (two overlapping particles = the first one's loop, then the second one's
+ * loop on the field the first left).
  */
 #include <math.h>
 #include <stdint.h>

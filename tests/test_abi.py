@@ -83,3 +83,19 @@ def test_count_markers_rejects_bad_arguments(lib, np_, h, d):
     offs = np.zeros(2, np.int64)
     assert f(np_, dd.ctypes.data, h, offs.ctypes.data) == -1
     assert f(1, dd.ctypes.data, 0.1, None) == -1
+
+
+def test_build_entry_calls_both_builders(monkeypatch):
+    """build() compiles the library and the oracle (stand-ins record the calls)."""
+    import importlib
+
+    # import_module returns the submodules themselves (the oracle package
+    # re-exports a function of the same name)
+    ob = importlib.import_module("oracle.build")
+    lb = importlib.import_module("paper_2408_14140_amd.build")
+    calls = []
+    monkeypatch.setattr(ob, "build", lambda *a, **k: calls.append("oracle"))
+    monkeypatch.setattr(lb, "build", lambda *a, **k: calls.append("library"))
+    import __graft_entry__ as ge
+    importlib.reload(ge).build()
+    assert sorted(calls) == ["library", "oracle"]
