@@ -141,44 +141,103 @@ k_prep(Grid g, int64_t nl, const double* __restrict__ x, const double* __restric
 
 // ------------------------------------------------------------------ work lists
 
-__global__ void k_tile_counts(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
-                              const int32_t* __restrict__ src_offs, int32_t* item_cnt,
-                              int32_t* act)
+// Spreading order: active positions by decreasing source count, so that a
+// static snake deal of the list over the workgroups gives every workgroup a
+// similar load.  Cost bins (source count, clamped) are counted per block in
+// LDS and then globally; the visiting order inside a bin is whatever the
+// atomics give, which moves no result (each tile is summed by one wavefront
+// in its own fixed order and stored to its own slot).
+constexpr int COST_BINS = 512;
+
+// Per tile: interpolation items and whether it is active; the active tiles'
+// cost bins are added to hist (zeroed beforehand).
+__global__ void __launch_bounds__(256)
+k_tile_counts(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
+              const int32_t* __restrict__ src_offs, int32_t* item_cnt, int32_t* act,
+              int32_t* __restrict__ hist)
 {
+    __shared__ int32_t lh[COST_BINS];
+    for (int b = threadIdx.x; b < COST_BINS; b += blockDim.x)
+        lh[b] = 0;
+    __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T)
-        return;
-    const int cnt = tile_offs[t + 1] - tile_offs[t];
-    item_cnt[t] = (cnt + bw - 1) / bw;
-    act[t] = src_offs[t + 1] > src_offs[t] ? 1 : 0;
+    if (t < T) {
+        const int cnt = tile_offs[t + 1] - tile_offs[t];
+        item_cnt[t] = (cnt + bw - 1) / bw;
+        const int c = src_offs[t + 1] - src_offs[t];
+        act[t] = c > 0 ? 1 : 0;
+        if (c > 0)
+            atomicAdd(&lh[min(c, COST_BINS - 1)], 1);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < COST_BINS; b += blockDim.x)
+        if (lh[b])
+            atomicAdd(&hist[b], lh[b]);
 }
 
-__global__ void k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
-                             const int32_t* __restrict__ src_offs,
-                             const int32_t* __restrict__ item_offs,
-                             const int32_t* __restrict__ act_offs, Item* items,
-                             int32_t* active, int32_t* slot)
+// cur[b] = number of active tiles in bins above b (descending cost).
+__global__ void __launch_bounds__(COST_BINS) k_bin_scan(const int32_t* __restrict__ hist,
+                                                       int32_t* __restrict__ cur)
 {
+    __shared__ int32_t v[COST_BINS];
+    const int b = threadIdx.x;
+    v[b] = hist[COST_BINS - 1 - b];
+    __syncthreads();
+    for (int o = 1; o < COST_BINS; o <<= 1) {
+        const int add = b >= o ? v[b - o] : 0;
+        __syncthreads();
+        v[b] += add;
+        __syncthreads();
+    }
+    // inclusive over reversed bins -> exclusive start of bin COST_BINS-1-b
+    cur[COST_BINS - 1 - b] = v[b] - hist[COST_BINS - 1 - b];
+}
+
+// Work lists: interpolation items in tile order, active tiles and their slots
+// in tile order, and the spreading order (cur[b] holds the first free
+// position of bin b).
+__global__ void __launch_bounds__(256)
+k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
+             const int32_t* __restrict__ src_offs, const int32_t* __restrict__ item_offs,
+             const int32_t* __restrict__ act_offs, Item* items, int32_t* active, int32_t* slot,
+             int32_t* __restrict__ cur, int32_t* __restrict__ sorder)
+{
+    __shared__ int32_t lc[COST_BINS];
+    __shared__ int32_t base[COST_BINS];
+    for (int b = threadIdx.x; b < COST_BINS; b += blockDim.x)
+        lc[b] = 0;
+    __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T)
-        return;
-    const int start = tile_offs[t];
-    const int cnt = tile_offs[t + 1] - start;
-    const int io = item_offs[t];
-    for (int k = 0; k * bw < cnt; ++k) {
-        Item it;
-        it.tile = (int32_t)t;
-        it.start = start + k * bw;
-        it.count = min(bw, cnt - k * bw);
-        it.pad = 0;
-        items[io + k] = it;
+    int bin = -1, rank = 0;
+    if (t < T) {
+        const int start = tile_offs[t];
+        const int cnt = tile_offs[t + 1] - start;
+        const int io = item_offs[t];
+        for (int k = 0; k * bw < cnt; ++k) {
+            Item it;
+            it.tile = (int32_t)t;
+            it.start = start + k * bw;
+            it.count = min(bw, cnt - k * bw);
+            it.pad = 0;
+            items[io + k] = it;
+        }
+        const int c = src_offs[t + 1] - src_offs[t];
+        if (c > 0) {
+            active[act_offs[t]] = (int32_t)t;
+            slot[t] = act_offs[t];
+            bin = min(c, COST_BINS - 1);
+            rank = atomicAdd(&lc[bin], 1);
+        } else {
+            slot[t] = -1;
+        }
     }
-    if (src_offs[t + 1] > src_offs[t]) {
-        active[act_offs[t]] = (int32_t)t;
-        slot[t] = act_offs[t];
-    } else {
-        slot[t] = -1;
-    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < COST_BINS; b += blockDim.x)
+        if (lc[b])
+            base[b] = atomicAdd(&cur[b], lc[b]);
+    __syncthreads();
+    if (bin >= 0)
+        sorder[base[bin] + rank] = act_offs[t];
 }
 
 #include "tiles.h"
@@ -207,10 +266,10 @@ int resident_grid(int ncu, int cap)
 // y, z plane): box-wide x rows, so the box layout is written in long runs.
 // In place (ustar == u0) only the cells with a force are rewritten.  With
 // f_acc, f += G^ns instead, on the cells with a force only.
-template <typename T>
+template <typename T, bool F_ACC>
 __global__ void __launch_bounds__(256)
 k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, const T* u0,
-           T* ustar, T* __restrict__ f, double dt, int use_g, int f_acc)
+           T* ustar, T* __restrict__ f, double dt, int use_g)
 {
     __shared__ int tslot[64];                 // G slot of each tile along the row
     const int B = g.box;
@@ -238,7 +297,7 @@ k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, co
             for (int c = 0; c < 3; ++c) {
                 const T v = s >= 0 ? G[go + c * TILE_CELLS] : T(0);
                 const int64_t o = off + c * g.cstride;
-                if (f && !f_acc)
+                if (f && !F_ACC)
                     f[o] = v;
                 else if (f && s >= 0)
                     f[o] += v;
@@ -250,6 +309,17 @@ k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, co
         }
         __syncthreads();
     }
+}
+
+template <typename T>
+static void launch_finalize(unsigned grid, hipStream_t st, const Grid& g, const int32_t* slot,
+                            const T* G, const T* u0, T* ustar, T* f, double dt, int use_g,
+                            int f_acc)
+{
+    if (f_acc)
+        k_finalize<T, true><<<grid, 256, 0, st>>>(g, slot, G, u0, ustar, f, dt, use_g);
+    else
+        k_finalize<T, false><<<grid, 256, 0, st>>>(g, slot, G, u0, ustar, f, dt, use_g);
 }
 
 template <typename T>
@@ -283,6 +353,7 @@ struct BatchedWs {
     double* part;
     Item* items;
     int32_t *item_cnt, *item_offs, *act, *act_offs, *active, *slot, *nitems, *nactive;
+    int32_t *hist, *cur, *sorder;   // spreading order by decreasing cost
     T* G;
     void* scan;
     int64_t max_items;
@@ -308,6 +379,9 @@ static BatchedWs<T> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, s
     w.item_offs = cv.take<int32_t>(T_);
     w.act = cv.take<int32_t>(T_);
     w.act_offs = cv.take<int32_t>(T_);
+    w.hist = cv.take<int32_t>(COST_BINS);
+    w.cur = cv.take<int32_t>(COST_BINS);
+    w.sorder = cv.take<int32_t>(T_);
     w.active = cv.take<int32_t>(T_);
     w.slot = cv.take<int32_t>(T_);
     w.nitems = cv.take<int32_t>(1);
@@ -363,7 +437,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     const int64_t nfin = (int64_t)g.nbox * (g.box / TILE) * g.box;
     const unsigned gfin = (unsigned)(nfin < 65535 ? (nfin > 0 ? nfin : 1) : 65535);
     if (nl == 0) {
-        k_finalize<T><<<gfin, 256, 0, st>>>(g, w.slot, w.G, u0, ustar, f, dt, 0, f_acc);
+        launch_finalize<T>(gfin, st, g, w.slot, w.G, u0, ustar, f, dt, 0, f_acc);
         if (resid)
             k_zero<double><<<1, 64, 0, st>>>(ns + 1, resid);
         return launch_status();
@@ -373,11 +447,14 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
                                      p->up, p->om, w.s);
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_LISTS);
-    k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt, w.act);
+    k_zero<int32_t><<<2, 256, 0, st>>>(COST_BINS, w.hist);
+    k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt, w.act,
+                                      w.hist);
     scan_exclusive(w.item_cnt, w.item_offs, T_, w.nitems, w.scan, st);
     scan_exclusive(w.act, w.act_offs, T_, w.nactive, w.scan, st);
+    k_bin_scan<<<1, COST_BINS, 0, st>>>(w.hist, w.cur);
     k_fill_lists<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs,
-                                     w.act_offs, w.items, w.active, w.slot);
+                                     w.act_offs, w.items, w.active, w.slot, w.cur, w.sorder);
     {
         const int64_t nth = 27 * w.max_items;
         k_item_bases<<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(g, w.items, w.nitems, w.slot,
@@ -392,7 +469,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         sum_to(w.e2, nl, w.part, resid + 0, true, st);
     if (ns == 0) {
         // no iteration: ustar = u0, f = 0, F = 0
-        k_finalize<T><<<gfin, 256, 0, st>>>(g, w.slot, w.G, u0, ustar, f, dt, 0, f_acc);
+        launch_finalize<T>(gfin, st, g, w.slot, w.G, u0, ustar, f, dt, 0, f_acc);
         k_zero<T><<<gm, 256, 0, st>>>(3 * nl, F);
         return launch_status();
     }
@@ -402,7 +479,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         IBX_PROF_BEGIN(PK_SPREAD);
         k_spread_tiles<T, P>
             <<<resident_grid<k_spread_tiles<T, P>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
-                w.active, w.nactive, b->src_offs, b->src_idx, g, w.s, w.G);
+                w.sorder, w.active, w.nactive, b->src_offs, b->src_idx, g, w.s, w.G);
         IBX_PROF_END();
         IBX_PROF_BEGIN(PK_INTERP_G);
         launch_interp<T, P, 1>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_g, w.s, e2);
@@ -416,10 +493,10 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     IBX_PROF_BEGIN(PK_SPREAD_FINAL);
     k_spread_tiles<T, P>
         <<<resident_grid<k_spread_tiles<T, P>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
-            w.active, w.nactive, b->src_offs, b->src_idx, g, w.s, w.G);
+            w.sorder, w.active, w.nactive, b->src_offs, b->src_idx, g, w.s, w.G);
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_FILL);
-    k_finalize<T><<<gfin, 256, 0, st>>>(g, w.slot, w.G, u0, ustar, f, dt, 1, f_acc);
+    launch_finalize<T>(gfin, st, g, w.slot, w.G, u0, ustar, f, dt, 1, f_acc);
     IBX_PROF_END();
     if (resid) {
         IBX_PROF_BEGIN(PK_RESID);

@@ -381,7 +381,9 @@ __device__ inline int wave_exclusive_sum(int v)
     return s;
 }
 
-// One wavefront per workgroup; the tile is stored to its G slot.
+// One wavefront per workgroup; the tile is stored to its G slot.  Workgroups
+// take the active positions of `order` (decreasing cost) dealt in a snake:
+// round r gives workgroup w entry r G + w (r even) or r G + G - 1 - w (r odd).
 //
 // Sources are staged 64 at a time as structure-of-arrays in LDS: the weight
 // of every tile x cell, y row and z row (zero outside the stencil) and
@@ -391,7 +393,8 @@ __device__ inline int wave_exclusive_sum(int v)
 // order.  The staging arrays share LDS with the transpose buffer.
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
-k_spread_tiles(const int32_t* __restrict__ active, const int32_t* __restrict__ nactive,
+k_spread_tiles(const int32_t* __restrict__ order, const int32_t* __restrict__ active,
+               const int32_t* __restrict__ nactive,
                const int32_t* __restrict__ src_offs, const int32_t* __restrict__ src_idx,
                Grid g, MarkerData<T> s, T* __restrict__ G)
 {
@@ -419,8 +422,12 @@ k_spread_tiles(const int32_t* __restrict__ active, const int32_t* __restrict__ n
     const int lane = threadIdx.x;
     const int ly = lane & 7, lz = lane >> 3;
     const int n_act = *nactive;
-    const Slab sl = xcd_slab(n_act);
-    for (int a = sl.begin; a < sl.end; a += sl.stride) {
+    const int nwg = gridDim.x, wg = blockIdx.x;
+    for (int r = 0;; ++r) {
+        const int idx = r * nwg + ((r & 1) ? nwg - 1 - wg : wg);
+        if (idx >= n_act)
+            break;
+        const int a = order[idx];
         const int t = active[a];
         int lo[3];
         tile_coords(g, t, lo);
