@@ -202,20 +202,38 @@ def run():
         torch.cuda.synchronize()
         return s.elapsed_time(e) / k
 
+    def captured(fn):
+        """fn recorded once into a graph (every call in it only enqueues work);
+        returns its replay."""
+        gph = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(gph):
+            fn()
+        torch.cuda.synchronize()
+        keep.append(gph)
+        return gph.replay
+
+    keep = []
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     log("warm")
-    ms_step = timed(step, args.steps)
+    # the step as one graph replay: no host launch cost inside the timed region
+    step_g = captured(step)
+    for _ in range(args.warmup):
+        step_g()
+    ms_step = timed(step_g, args.steps)
+    ms_step_eager = timed(step, args.steps)
     ms_loop = timed(loop_only, args.steps)
-    log(f"step {ms_step:.3f} ms, loop {ms_loop:.3f} ms")
+    log(f"step {ms_step:.3f} ms (eager launches {ms_step_eager:.3f} ms), loop {ms_loop:.3f} ms")
 
-    # the step's other parts, each timed alone over the same number of repetitions
+    # the step's other parts, each captured alone and timed over the same repetitions
     parts_ms = {
-        "build_markers": timed(lambda: ibx.build_markers_into(dl, parts, m), args.steps),
-        "bucket": timed(lambda: ibx.bucket_into(dl, m, P, b), args.steps),
-        "reductions": timed(lambda: red.copy_(ibx.particle_reductions(dl, parts, m, F32, u32)),
-                            args.steps),
+        "build_markers": timed(captured(lambda: ibx.build_markers_into(dl, parts, m)),
+                               args.steps),
+        "bucket": timed(captured(lambda: ibx.bucket_into(dl, m, P, b)), args.steps),
+        "reductions": timed(captured(
+            lambda: red.copy_(ibx.particle_reductions(dl, parts, m, F32, u32))), args.steps),
     }
     log(f"step parts {json.dumps(parts_ms)}")
 
@@ -225,12 +243,12 @@ def run():
     up1, om1, xc1 = ibx.rigid_update(parts, rho_p, red, red1, 1.0, [0.0, 0.0, -9.81], dt)
     madv = ibx.advect_markers(m, parts.xc, xc1, parts.om, om1, dt)
     particle_ms = {
-        "rigid_update": timed(lambda: ibx.rigid_update(parts, rho_p, red, red1, 1.0,
-                                                       [0.0, 0.0, -9.81], dt), args.steps),
-        "advect_markers": timed(lambda: ibx.advect_markers(m, parts.xc, xc1, parts.om, om1, dt,
-                                                           out=madv), args.steps),
-        "collision_forces": timed(lambda: ibx.collision_forces(dl, parts, rho_p, 9.81, 1e-4),
-                                  args.steps),
+        "rigid_update": timed(captured(lambda: ibx.rigid_update(
+            parts, rho_p, red, red1, 1.0, [0.0, 0.0, -9.81], dt)), args.steps),
+        "advect_markers": timed(captured(lambda: ibx.advect_markers(
+            m, parts.xc, xc1, parts.om, om1, dt, out=madv)), args.steps),
+        "collision_forces": timed(captured(
+            lambda: ibx.collision_forces(dl, parts, rho_p, 9.81, 1e-4)), args.steps),
     }
     log(f"particle step {json.dumps(particle_ms)}")
 
@@ -285,6 +303,7 @@ def run():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_eager_launches": ms_step_eager,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -180,7 +180,11 @@ int ib_spread(const ib_level* lv, const ib_markers* m, const ib_buckets* b, ib_d
 /* cap on resident spreading workgroups per compute unit (1..32; 0 = 16),  */
 /* lowered to what fits.  Interpolation runs as many workgroups as fit.     */
 /* use_graph: replay the launch sequence from a captured hipGraph when the  */
-/* arguments repeat (batched path, non-null stream).                        */
+/* arguments repeat (batched path, non-null stream).  On a stream that is   */
+/* already being captured the launches go into the caller's graph instead.  */
+/* ib_plan_autotune, ib_plan_profile_read, ib_particle_levels and           */
+/* ib_multidirect_sequential synchronize and must not be captured; every    */
+/* other call only enqueues work on its stream and may be.                  */
 /* ---------------------------------------------------------------------- */
 int ib_plan_create(ib_plan** plan, ib_delta delta, ib_prec prec, ib_path path,
                    int32_t bucket_width, int32_t spread_wgs_per_cu, int32_t use_graph);

@@ -302,7 +302,12 @@ extern "C" int ib_multidirect_force(ib_plan* plan, const ib_level* lv, const ib_
         return plain_multidirect(g, plan->P, plan->prec, p, m, b, ns, dt, u0, ustar, f, F, resid,
                                  Fhist, ws, ws_bytes, st);
     const BatchedCfg cfg = cfg_of(plan);
-    if (!plan->use_graph || !stream || plan->prof)
+    // a stream that is already being captured records the launches into the
+    // caller's graph
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (stream && hipStreamIsCapturing(st, &cap) != hipSuccess)
+        cap = hipStreamCaptureStatusNone;
+    if (!plan->use_graph || !stream || plan->prof || cap != hipStreamCaptureStatusNone)
         return batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0, ustar, f, F,
                                    resid, Fhist, ws, ws_bytes, st);
     uint64_t key[24];

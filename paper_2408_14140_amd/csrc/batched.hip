@@ -297,14 +297,15 @@ k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, co
             for (int c = 0; c < 3; ++c) {
                 const T v = s >= 0 ? G[go + c * TILE_CELLS] : T(0);
                 const int64_t o = off + c * g.cstride;
+                // streaming stores: nothing here is read again by this kernel
                 if (f && !F_ACC)
-                    f[o] = v;
+                    __builtin_nontemporal_store(v, &f[o]);
                 else if (f && s >= 0)
                     f[o] += v;
                 if (s >= 0)
-                    ustar[o] = u0[o] + tdt * v;
+                    __builtin_nontemporal_store(u0[o] + tdt * v, &ustar[o]);
                 else if (ustar != u0)
-                    ustar[o] = u0[o];
+                    __builtin_nontemporal_store(u0[o], &ustar[o]);
             }
         }
         __syncthreads();

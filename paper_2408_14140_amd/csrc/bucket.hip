@@ -19,7 +19,7 @@ constexpr int SCAN_ITEMS = 4;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 
 __global__ void __launch_bounds__(SCAN_THREADS)
-k_scan_tile(const int32_t* in, int32_t* out, int64_t n, int32_t* sums)
+k_scan_tile(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, int shift)
 {
     __shared__ int32_t ts[SCAN_THREADS];
     const int t = threadIdx.x;
@@ -28,7 +28,7 @@ k_scan_tile(const int32_t* in, int32_t* out, int64_t n, int32_t* sums)
     int32_t tsum = 0;
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
-        v[k] = (base + k < n) ? in[base + k] : 0;
+        v[k] = (base + k < n) ? (in[base + k] >> shift) : 0;
         tsum += v[k];
     }
     ts[t] = tsum;
@@ -76,7 +76,7 @@ size_t scan_workspace(int64_t n)
 }
 
 void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* total, void* ws,
-                    hipStream_t st)
+                    hipStream_t st, int shift)
 {
     if (n <= 0) {
         if (total)
@@ -85,13 +85,13 @@ void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* total, 
     }
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     int32_t* sums = (int32_t*)ws;
-    k_scan_tile<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, out, n, sums);
+    k_scan_tile<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, out, n, sums, shift);
     if (nb == 1) {
         if (total)
             k_copy1<<<1, 1, 0, st>>>(total, sums);
         return;
     }
-    scan_exclusive(sums, sums, nb, total, (char*)ws + align_up(sizeof(int32_t) * nb), st);
+    scan_exclusive(sums, sums, nb, total, (char*)ws + align_up(sizeof(int32_t) * nb), st, 0);
     k_scan_add<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(out, n, sums);
 }
 
@@ -128,20 +128,80 @@ k_radix_hist(const int32_t* keys, int64_t n_max, const int32_t* n_dev, int shift
     hist[(int64_t)t * nblocks + blockIdx.x] = h[t];
 }
 
+// Exclusive scan of one digit's row of block counts (workgroup d scans
+// hist[d][0 .. nblocks)); rowtot[d] receives the row's total.
+__global__ void __launch_bounds__(RS_THREADS)
+k_radix_rowscan(int32_t* hist, int nblocks, int32_t* rowtot)
+{
+    __shared__ int32_t ts[RS_THREADS];
+    const int t = threadIdx.x;
+    int32_t* row = hist + (int64_t)blockIdx.x * nblocks;
+    int32_t carry = 0;
+    for (int c0 = 0; c0 < nblocks; c0 += RS_THREADS * 4) {
+        int32_t v[4];
+        int32_t tsum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int j = c0 + 4 * t + k;
+            v[k] = j < nblocks ? row[j] : 0;
+            tsum += v[k];
+        }
+        ts[t] = tsum;
+        __syncthreads();
+        for (int off = 1; off < RS_THREADS; off <<= 1) {
+            const int32_t x = t >= off ? ts[t - off] : 0;
+            __syncthreads();
+            ts[t] += x;
+            __syncthreads();
+        }
+        int32_t run = carry + ts[t] - tsum;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int j = c0 + 4 * t + k;
+            if (j < nblocks)
+                row[j] = run;
+            run += v[k];
+        }
+        carry += ts[RS_THREADS - 1];
+        __syncthreads();
+    }
+    if (t == 0)
+        rowtot[blockIdx.x] = carry;
+}
+
+// digit_off[d] = number of elements with a smaller digit.
+__global__ void __launch_bounds__(256) k_radix_digits(const int32_t* rowtot, int32_t* digit_off)
+{
+    __shared__ int32_t ts[256];
+    const int t = threadIdx.x;
+    const int32_t v = rowtot[t];
+    ts[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int32_t x = t >= off ? ts[t - off] : 0;
+        __syncthreads();
+        ts[t] += x;
+        __syncthreads();
+    }
+    digit_off[t] = ts[t] - v;
+}
+
 // Stable scatter: elements keep their input order within each digit.  Ranks
 // inside a wave come from ballot matching on the 8 digit bits; ranks across
 // the block's waves and rounds from per-digit counters in LDS.
 __global__ void __launch_bounds__(RS_THREADS)
 k_radix_scatter(const int32_t* kin, const int32_t* vin, int32_t* kout, int32_t* vout,
                 int64_t n_max, const int32_t* n_dev, int shift, const int32_t* hist_scan,
-                int nblocks)
+                const int32_t* digit_off, int nblocks)
 {
     __shared__ int32_t run[256];
     __shared__ int32_t wc[RS_WAVES][256];
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
     const int64_t n = live_count(n_max, n_dev);
-    run[t] = hist_scan[(int64_t)t * nblocks + blockIdx.x];
+    if ((int64_t)blockIdx.x * RS_TILE >= n)
+        return;                             // whole block past the live count
+    run[t] = digit_off[t] + hist_scan[(int64_t)t * nblocks + blockIdx.x];
 #pragma unroll
     for (int w = 0; w < RS_WAVES; ++w)
         wc[w][t] = 0;
@@ -199,7 +259,7 @@ static int64_t rs_blocks(int64_t n_max) { return (n_max + RS_TILE - 1) / RS_TILE
 size_t radix_workspace(int64_t n_max)
 {
     int64_t nb = rs_blocks(n_max > 0 ? n_max : 1);
-    return align_up(sizeof(int32_t) * 256 * nb) + scan_workspace(256 * nb);
+    return align_up(sizeof(int32_t) * 256 * nb) + 2 * align_up(sizeof(int32_t) * 256);
 }
 
 void radix_sort_pairs(int32_t* keys, int32_t* vals, int32_t* tk, int32_t* tv, int64_t n_max,
@@ -209,15 +269,17 @@ void radix_sort_pairs(int32_t* keys, int32_t* vals, int32_t* tk, int32_t* tv, in
         return;
     const int64_t nb = rs_blocks(n_max);
     int32_t* hist = (int32_t*)ws;
-    void* sws = (char*)ws + align_up(sizeof(int32_t) * 256 * nb);
+    int32_t* rowtot = (int32_t*)((char*)ws + align_up(sizeof(int32_t) * 256 * nb));
+    int32_t* digit_off = rowtot + align_up(sizeof(int32_t) * 256) / sizeof(int32_t);
     int32_t *ka = keys, *va = vals, *kb = tk, *vb = tv;
     const int passes = (bits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         k_radix_hist<<<(unsigned)nb, RS_THREADS, 0, st>>>(ka, n_max, n_dev, shift, hist, (int)nb);
-        scan_exclusive(hist, hist, 256 * nb, nullptr, sws, st);
+        k_radix_rowscan<<<256, RS_THREADS, 0, st>>>(hist, (int)nb, rowtot);
+        k_radix_digits<<<1, 256, 0, st>>>(rowtot, digit_off);
         k_radix_scatter<<<(unsigned)nb, RS_THREADS, 0, st>>>(ka, va, kb, vb, n_max, n_dev, shift,
-                                                             hist, (int)nb);
+                                                             hist, digit_off, (int)nb);
         int32_t* t0 = ka; ka = kb; kb = t0;
         t0 = va; va = vb; vb = t0;
     }
@@ -230,7 +292,7 @@ void radix_sort_pairs(int32_t* keys, int32_t* vals, int32_t* tk, int32_t* tv, in
 }
 
 __global__ void k_lower_bounds(const int32_t* keys, int64_t n_max, const int32_t* n_dev,
-                               int32_t* offs, int64_t T)
+                               int32_t* offs, int64_t T, int32_t mask)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t > T)
@@ -238,7 +300,7 @@ __global__ void k_lower_bounds(const int32_t* keys, int64_t n_max, const int32_t
     int64_t lo = 0, hi = live_count(n_max, n_dev);
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
-        if (keys[mid] < t)
+        if ((keys[mid] & mask) < t)
             lo = mid + 1;
         else
             hi = mid;
@@ -247,9 +309,10 @@ __global__ void k_lower_bounds(const int32_t* keys, int64_t n_max, const int32_t
 }
 
 void lower_bounds(const int32_t* keys, int64_t n_max, const int32_t* n_dev, int32_t* offs,
-                  int64_t T, hipStream_t st)
+                  int64_t T, hipStream_t st, int32_t mask)
 {
-    k_lower_bounds<<<(unsigned)((T + 1 + 255) / 256), 256, 0, st>>>(keys, n_max, n_dev, offs, T);
+    k_lower_bounds<<<(unsigned)((T + 1 + 255) / 256), 256, 0, st>>>(keys, n_max, n_dev, offs, T,
+                                                                    mask);
 }
 
 // ------------------------------------------------------------------ bucket keys
@@ -260,13 +323,33 @@ __global__ void k_init_flags(int32_t* flag)
         flag[threadIdx.x] = 0;
 }
 
+// Tiles touched on one axis by the stencil cells b .. b+P-1 (1 or 2 tiles).
+template <int P>
+__device__ inline int axis_tiles(const Grid& g, int a, int b, int* tl)
+{
+    int nt = 0;
+    for (int o = 0; o < P; ++o) {
+        int q = b + o;
+        if (g.periodic[a])
+            q = wrapi(q, g.n[a]);
+        else if (q < 0 || q >= g.n[a])
+            continue;
+        const int tq = q / TILE;
+        if (nt == 0 || (tl[nt - 1] != tq && nt < 2 && tl[0] != tq))
+            tl[nt++] = tq;
+    }
+    return nt;
+}
+
 // Per marker: owning cell c = floor(s) (wrapped on periodic axes), its tile,
-// the unwrapped stencil base, and whether all stencil cells are covered.
+// the unwrapped stencil base, and whether all stencil cells are covered.  The
+// sort key is the tile; with kb > 0 the number of tiles the stencil touches
+// rides above the sorted digits, at bit kb.
 template <int P>
 __global__ void k_bucket_keys(Grid g, int64_t nl, const double* __restrict__ x,
                               const double* __restrict__ y, const double* __restrict__ z,
                               int32_t* cell, int32_t* tileid, int32_t* base, int32_t* keys,
-                              int32_t* vals, int32_t* flag)
+                              int32_t* vals, int32_t* flag, int kb)
 {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= nl)
@@ -312,31 +395,21 @@ __global__ void k_bucket_keys(Grid g, int64_t nl, const double* __restrict__ x,
     cell[l] = c[0] + g.n[0] * (c[1] + g.n[1] * c[2]);
     const int t = c[0] / TILE + g.nt[0] * (c[1] / TILE + g.nt[1] * (c[2] / TILE));
     tileid[l] = t;
-    keys[l] = t;
+    int key = t;
+    if (kb > 0) {
+        int tl[2], cnt = 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            cnt *= axis_tiles<P>(g, a, b[a], tl);
+        key |= cnt << kb;
+    }
+    keys[l] = key;
     vals[l] = (int32_t)l;
     base[3 * l + 0] = b[0];
     base[3 * l + 1] = b[1];
     base[3 * l + 2] = b[2];
     if (bad)
         atomicAdd(&flag[0], 1);
-}
-
-// Tiles touched on one axis by the stencil cells b .. b+P-1 (1 or 2 tiles).
-template <int P>
-__device__ inline int axis_tiles(const Grid& g, int a, int b, int* tl)
-{
-    int nt = 0;
-    for (int o = 0; o < P; ++o) {
-        int q = b + o;
-        if (g.periodic[a])
-            q = wrapi(q, g.n[a]);
-        else if (q < 0 || q >= g.n[a])
-            continue;
-        const int tq = q / TILE;
-        if (nt == 0 || (tl[nt - 1] != tq && nt < 2 && tl[0] != tq))
-            tl[nt++] = tq;
-    }
-    return nt;
 }
 
 template <int P>
@@ -354,10 +427,11 @@ __global__ void k_src_count(Grid g, int64_t nl, const int32_t* perm, const int32
     cnt[i] = c;
 }
 
+// npairs[0] = min(total pairs, cap), written by the last marker.
 template <int P>
 __global__ void k_src_emit(Grid g, int64_t nl, const int32_t* perm, const int32_t* base,
                            const int32_t* offs, int32_t* keys2, int32_t* vals2, int64_t cap,
-                           int32_t* flag)
+                           int32_t* flag, int32_t* npairs)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nl)
@@ -379,12 +453,8 @@ __global__ void k_src_emit(Grid g, int64_t nl, const int32_t* perm, const int32_
                 }
                 ++pos;
             }
-}
-
-__global__ void k_clamp_count(int32_t* npairs, const int32_t* total, int64_t cap)
-{
-    int64_t v = *total;
-    *npairs = (int32_t)(v < cap ? v : cap);
+    if (i == nl - 1)
+        npairs[0] = (int32_t)(pos < cap ? pos : cap);
 }
 
 static int key_bits(int64_t T)
@@ -466,28 +536,33 @@ extern "C" int ib_bucket(const ib_level* lv, const ib_markers* m, ib_delta delta
         return launch_status();
     }
     const unsigned gb = (unsigned)((nl + 255) / 256);
+    const int bits = key_bits(T);
+    const int passes = (bits + 7) / 8;
+    const int kb = 8 * passes + 4 <= 31 ? 8 * passes : 0;   // 4 count bits above the digits
     if (delta == IB_DELTA3)
         k_bucket_keys<3><<<gb, 256, 0, st>>>(g, nl, m->x, m->y, m->z, b->cell, b->tileid,
-                                             b->base, w.keys, b->perm, b->flag);
+                                             b->base, w.keys, b->perm, b->flag, kb);
     else
         k_bucket_keys<4><<<gb, 256, 0, st>>>(g, nl, m->x, m->y, m->z, b->cell, b->tileid,
-                                             b->base, w.keys, b->perm, b->flag);
-    const int bits = key_bits(T);
+                                             b->base, w.keys, b->perm, b->flag, kb);
     radix_sort_pairs(w.keys, b->perm, w.tk, w.tv, nl, nullptr, bits, w.rs, st);
-    lower_bounds(w.keys, nl, nullptr, b->tile_offs, T, st);
+    lower_bounds(w.keys, nl, nullptr, b->tile_offs, T, st, kb > 0 ? (1 << kb) - 1 : -1);
 
-    if (delta == IB_DELTA3)
-        k_src_count<3><<<gb, 256, 0, st>>>(g, nl, b->perm, b->base, w.cnt);
-    else
-        k_src_count<4><<<gb, 256, 0, st>>>(g, nl, b->perm, b->base, w.cnt);
-    scan_exclusive(w.cnt, w.cnt, nl, w.total, w.scan, st);
+    if (kb > 0) {
+        scan_exclusive(w.keys, w.cnt, nl, nullptr, w.scan, st, kb);
+    } else {
+        if (delta == IB_DELTA3)
+            k_src_count<3><<<gb, 256, 0, st>>>(g, nl, b->perm, b->base, w.cnt);
+        else
+            k_src_count<4><<<gb, 256, 0, st>>>(g, nl, b->perm, b->base, w.cnt);
+        scan_exclusive(w.cnt, w.cnt, nl, nullptr, w.scan, st);
+    }
     if (delta == IB_DELTA3)
         k_src_emit<3><<<gb, 256, 0, st>>>(g, nl, b->perm, b->base, w.cnt, w.keys2, b->src_idx,
-                                          cap, b->flag);
+                                          cap, b->flag, w.npairs);
     else
         k_src_emit<4><<<gb, 256, 0, st>>>(g, nl, b->perm, b->base, w.cnt, w.keys2, b->src_idx,
-                                          cap, b->flag);
-    k_clamp_count<<<1, 1, 0, st>>>(w.npairs, w.total, cap);
+                                          cap, b->flag, w.npairs);
     radix_sort_pairs(w.keys2, b->src_idx, w.tk2, w.tv2, cap, w.npairs, bits, w.rs, st);
     lower_bounds(w.keys2, cap, w.npairs, b->src_offs, T, st);
     return launch_status();

@@ -179,8 +179,9 @@ int launch_status();
 // Device-wide exclusive scan of int32 (in may alias out).  total (device,
 // nullable) receives the sum.  Workspace bytes from scan_workspace(n).
 size_t scan_workspace(int64_t n);
+// With shift > 0 the scanned values are in[i] >> shift.
 void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* total, void* ws,
-                    hipStream_t st);
+                    hipStream_t st, int shift = 0);
 
 // Stable LSD radix sort of (key, val) int32 pairs on the low `bits` bits of
 // the key.  n_dev (device, nullable) holds the live count <= n_max.  Result
@@ -189,9 +190,10 @@ size_t radix_workspace(int64_t n_max);
 void radix_sort_pairs(int32_t* keys, int32_t* vals, int32_t* tk, int32_t* tv, int64_t n_max,
                       const int32_t* n_dev, int bits, void* ws, hipStream_t st);
 
-// offs[t] = first i with keys[i] >= t, t = 0..T (keys sorted ascending).
+// offs[t] = first i with (keys[i] & mask) >= t, t = 0..T (masked keys sorted
+// ascending).
 void lower_bounds(const int32_t* keys, int64_t n_max, const int32_t* n_dev, int32_t* offs,
-                  int64_t T, hipStream_t st);
+                  int64_t T, hipStream_t st, int32_t mask = -1);
 
 inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
