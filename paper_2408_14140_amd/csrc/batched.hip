@@ -139,49 +139,71 @@ k_prep(Grid g, int64_t nl, const double* __restrict__ x, const double* __restric
     s.ud[2 * nl + i] = (T)(up[3 * p + 2] + (w0 * R1 - w1 * R0));
 }
 
+#include "tiles.h"
+
 // ------------------------------------------------------------------ work lists
 
-// Spreading order: active positions by decreasing source count, so that a
-// static snake deal of the list over the workgroups gives every workgroup a
-// similar load.  Cost bins (source count, clamped) are counted per block in
-// LDS and then globally; the visiting order inside a bin is whatever the
-// atomics give, which moves no result (each tile is summed by one wavefront
-// in its own fixed order and stored to its own slot).
-constexpr int COST_BINS = 512;
+// Spreading order.  The active positions are cut into NXCD equal slabs, one
+// per XCD (workgroups are dealt to the XCDs round-robin by id, and each XCD
+// has its own L2, so neighbouring tiles -- which share source markers -- stay
+// on one XCD); inside a slab they are ordered by decreasing source count, so
+// that a static snake deal over the slab's workgroups gives each a similar
+// load.  Cost bins (source count, clamped) are counted per block in LDS and
+// then globally; the order inside a bin is whatever the atomics give, which
+// moves no result (each tile is summed by one wavefront in its own fixed
+// order and stored to its own slot).
+constexpr int COST_BINS = 256;
 
-// Per tile: interpolation items and whether it is active; the active tiles'
-// cost bins are added to hist (zeroed beforehand).
-__global__ void __launch_bounds__(256)
-k_tile_counts(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
-              const int32_t* __restrict__ src_offs, int32_t* item_cnt, int32_t* act,
-              int32_t* __restrict__ hist)
+__device__ inline int slab_of(int a, int n_act)
 {
-    __shared__ int32_t lh[COST_BINS];
-    for (int b = threadIdx.x; b < COST_BINS; b += blockDim.x)
+    const int per = (n_act + NXCD - 1) / NXCD;
+    return a / per;
+}
+
+__global__ void k_tile_counts(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
+                              const int32_t* __restrict__ src_offs, int32_t* item_cnt,
+                              int32_t* act)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T)
+        return;
+    const int cnt = tile_offs[t + 1] - tile_offs[t];
+    item_cnt[t] = (cnt + bw - 1) / bw;
+    act[t] = src_offs[t + 1] > src_offs[t] ? 1 : 0;
+}
+
+// hist[x][b]: active tiles of slab x in cost bin b (zeroed beforehand).
+__global__ void __launch_bounds__(256)
+k_cost_hist(int64_t T, const int32_t* __restrict__ src_offs, const int32_t* __restrict__ act_offs,
+            const int32_t* __restrict__ nactive, int32_t* __restrict__ hist)
+{
+    __shared__ int32_t lh[NXCD * COST_BINS];
+    for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
         lh[b] = 0;
     __syncthreads();
+    const int n_act = *nactive;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < T) {
-        const int cnt = tile_offs[t + 1] - tile_offs[t];
-        item_cnt[t] = (cnt + bw - 1) / bw;
         const int c = src_offs[t + 1] - src_offs[t];
-        act[t] = c > 0 ? 1 : 0;
         if (c > 0)
-            atomicAdd(&lh[min(c, COST_BINS - 1)], 1);
+            atomicAdd(&lh[slab_of(act_offs[t], n_act) * COST_BINS + min(c, COST_BINS - 1)], 1);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < COST_BINS; b += blockDim.x)
+    for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
         if (lh[b])
             atomicAdd(&hist[b], lh[b]);
 }
 
-// cur[b] = number of active tiles in bins above b (descending cost).
-__global__ void __launch_bounds__(COST_BINS) k_bin_scan(const int32_t* __restrict__ hist,
-                                                       int32_t* __restrict__ cur)
+// cur[x][b] = first position of slab x plus its tiles in bins above b.
+__global__ void __launch_bounds__(COST_BINS)
+k_bin_scan(const int32_t* __restrict__ hist, const int32_t* __restrict__ nactive,
+           int32_t* __restrict__ cur)
 {
     __shared__ int32_t v[COST_BINS];
-    const int b = threadIdx.x;
-    v[b] = hist[COST_BINS - 1 - b];
+    const int b = threadIdx.x, x = blockIdx.x;
+    const int per = (*nactive + NXCD - 1) / NXCD;
+    const int32_t* h = hist + x * COST_BINS;
+    v[b] = h[COST_BINS - 1 - b];
     __syncthreads();
     for (int o = 1; o < COST_BINS; o <<= 1) {
         const int add = b >= o ? v[b - o] : 0;
@@ -190,23 +212,25 @@ __global__ void __launch_bounds__(COST_BINS) k_bin_scan(const int32_t* __restric
         __syncthreads();
     }
     // inclusive over reversed bins -> exclusive start of bin COST_BINS-1-b
-    cur[COST_BINS - 1 - b] = v[b] - hist[COST_BINS - 1 - b];
+    cur[x * COST_BINS + COST_BINS - 1 - b] = x * per + v[b] - h[COST_BINS - 1 - b];
 }
 
 // Work lists: interpolation items in tile order, active tiles and their slots
-// in tile order, and the spreading order (cur[b] holds the first free
-// position of bin b).
+// in tile order, and the spreading order (cur[x][b] holds the first free
+// position of bin b of slab x).
 __global__ void __launch_bounds__(256)
 k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
              const int32_t* __restrict__ src_offs, const int32_t* __restrict__ item_offs,
-             const int32_t* __restrict__ act_offs, Item* items, int32_t* active, int32_t* slot,
-             int32_t* __restrict__ cur, int32_t* __restrict__ sorder)
+             const int32_t* __restrict__ act_offs, const int32_t* __restrict__ nactive,
+             Item* items, int32_t* active, int32_t* slot, int32_t* __restrict__ cur,
+             int32_t* __restrict__ sorder)
 {
-    __shared__ int32_t lc[COST_BINS];
-    __shared__ int32_t base[COST_BINS];
-    for (int b = threadIdx.x; b < COST_BINS; b += blockDim.x)
+    __shared__ int32_t lc[NXCD * COST_BINS];
+    __shared__ int32_t base[NXCD * COST_BINS];
+    for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
         lc[b] = 0;
     __syncthreads();
+    const int n_act = *nactive;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int bin = -1, rank = 0;
     if (t < T) {
@@ -223,16 +247,17 @@ k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
         }
         const int c = src_offs[t + 1] - src_offs[t];
         if (c > 0) {
-            active[act_offs[t]] = (int32_t)t;
-            slot[t] = act_offs[t];
-            bin = min(c, COST_BINS - 1);
+            const int a = act_offs[t];
+            active[a] = (int32_t)t;
+            slot[t] = a;
+            bin = slab_of(a, n_act) * COST_BINS + min(c, COST_BINS - 1);
             rank = atomicAdd(&lc[bin], 1);
         } else {
             slot[t] = -1;
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < COST_BINS; b += blockDim.x)
+    for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
         if (lc[b])
             base[b] = atomicAdd(&cur[b], lc[b]);
     __syncthreads();
@@ -240,7 +265,6 @@ k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
         sorder[base[bin] + rank] = act_offs[t];
 }
 
-#include "tiles.h"
 
 // Persistent grid of a tile kernel: the workgroups that can be resident at
 // once (optionally capped per CU), a multiple of 8 for the XCD split.
@@ -380,8 +404,8 @@ static BatchedWs<T> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, s
     w.item_offs = cv.take<int32_t>(T_);
     w.act = cv.take<int32_t>(T_);
     w.act_offs = cv.take<int32_t>(T_);
-    w.hist = cv.take<int32_t>(COST_BINS);
-    w.cur = cv.take<int32_t>(COST_BINS);
+    w.hist = cv.take<int32_t>(NXCD * COST_BINS);
+    w.cur = cv.take<int32_t>(NXCD * COST_BINS);
     w.sorder = cv.take<int32_t>(T_);
     w.active = cv.take<int32_t>(T_);
     w.slot = cv.take<int32_t>(T_);
@@ -448,14 +472,15 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
                                      p->up, p->om, w.s);
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_LISTS);
-    k_zero<int32_t><<<2, 256, 0, st>>>(COST_BINS, w.hist);
-    k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt, w.act,
-                                      w.hist);
+    k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt, w.act);
     scan_exclusive(w.item_cnt, w.item_offs, T_, w.nitems, w.scan, st);
     scan_exclusive(w.act, w.act_offs, T_, w.nactive, w.scan, st);
-    k_bin_scan<<<1, COST_BINS, 0, st>>>(w.hist, w.cur);
+    k_zero<int32_t><<<NXCD, 256, 0, st>>>(NXCD * COST_BINS, w.hist);
+    k_cost_hist<<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.hist);
+    k_bin_scan<<<NXCD, COST_BINS, 0, st>>>(w.hist, w.nactive, w.cur);
     k_fill_lists<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs,
-                                     w.act_offs, w.items, w.active, w.slot, w.cur, w.sorder);
+                                     w.act_offs, w.nactive, w.items, w.active, w.slot, w.cur,
+                                     w.sorder);
     {
         const int64_t nth = 27 * w.max_items;
         k_item_bases<<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(g, w.items, w.nitems, w.slot,

@@ -381,9 +381,11 @@ __device__ inline int wave_exclusive_sum(int v)
     return s;
 }
 
-// One wavefront per workgroup; the tile is stored to its G slot.  Workgroups
-// take the active positions of `order` (decreasing cost) dealt in a snake:
-// round r gives workgroup w entry r G + w (r even) or r G + G - 1 - w (r odd).
+// One wavefront per workgroup; the tile is stored to its G slot.  The
+// workgroups of XCD x (ids = x mod 8) take the entries of slab x of `order`
+// (the x-th of 8 equal cuts, each by decreasing cost) dealt in a snake: with
+// W workgroups on the XCD, round r gives its w-th workgroup entry r W + w
+// (r even) or r W + W - 1 - w (r odd) of the slab.
 //
 // Sources are staged 64 at a time as structure-of-arrays in LDS: the weight
 // of every tile x cell, y row and z row (zero outside the stencil) and
@@ -422,10 +424,12 @@ k_spread_tiles(const int32_t* __restrict__ order, const int32_t* __restrict__ ac
     const int lane = threadIdx.x;
     const int ly = lane & 7, lz = lane >> 3;
     const int n_act = *nactive;
-    const int nwg = gridDim.x, wg = blockIdx.x;
+    const int per = (n_act + NXCD - 1) / NXCD;
+    const int x = blockIdx.x % NXCD, nwg = gridDim.x / NXCD, wg = blockIdx.x / NXCD;
+    const int s_end = min(n_act, (x + 1) * per);
     for (int r = 0;; ++r) {
-        const int idx = r * nwg + ((r & 1) ? nwg - 1 - wg : wg);
-        if (idx >= n_act)
+        const int idx = x * per + r * nwg + ((r & 1) ? nwg - 1 - wg : wg);
+        if (idx >= s_end)
             break;
         const int a = order[idx];
         const int t = active[a];
