@@ -361,6 +361,45 @@ int ib_multidirect_sequential(ib_plan* plan, const ib_level* lv, const ib_partic
                               int32_t nlevels, const void* u0, void* ustar, void* f, void* F,
                               int32_t* flag, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Single-level periodic fluid steps around the IB loop (Sec. 3.1).         */
+/* Grid: n^3 cells of edge h, periodic on every axis, n a power of two in   */
+/* [8, 1024] (else IB_EUNSUPPORTED).  Velocity is cell-centred, device      */
+/* [3][n][n][n] x fastest, in precision prec; pressure is node-centred      */
+/* (the semi-staggered grid), device [n][n][n], node (i, j, k) at the low   */
+/* corner of cell (i, j, k).  Discrete operators: G p = cell gradient of    */
+/* nodal p (the difference across the cell averaged over its four edges     */
+/* along the axis); D V = nodal divergence of cell V, D = -G^T; L = 7-point */
+/* Laplacian; the convective term in central flux form (face value = mean   */
+/* of the two cells), standing in for the Godunov scheme the paper cites.   */
+/* Constant rho and mu.  Both solves are exact (FFT).  ws: device workspace */
+/* of ib_fluid_workspace(n, prec) bytes.  Enqueue-only.                     */
+/* ---------------------------------------------------------------------- */
+size_t ib_fluid_workspace(int32_t n, ib_prec prec);
+/* Step 1, Eq. (31): ustar = u~*, solving                                   */
+/*   (I - nu dt/2 L) u~* = u - dt div(uu) - (dt/rho) G p + (nu dt/2) L u     */
+/*                         + dt g,   nu = mu / rho,                           */
+/* from u = u^n and p = p^{n-1/2}; grav: host [3].  ustar may alias u.      */
+int ib_fluid_predict(int32_t n, double h, ib_prec prec, double rho, double mu, double dt,
+                     const double* grav, const void* u, const void* p, void* ustar, void* ws,
+                     size_t ws_bytes, void* stream);
+/* Step 3, Eqs. (ns_lp1)-(ns_lp3): V = ustar / dt + G p_old / rho;         */
+/* (1/rho) D G                                                              */
+/* p_new = D V (Fourier modes where the symbol of D G vanishes -- the      */
+/* constant and those with two or more Nyquist components -- get p_new = 0); */
+/* u_new = dt (V - G p_new / rho), so D u_new = 0.  u_new may alias ustar,  */
+/* p_new may alias p_old.                                                   */
+int ib_fluid_project(int32_t n, double h, ib_prec prec, double rho, double dt,
+                     const void* ustar, const void* p_old, void* u_new, void* p_new, void* ws,
+                     size_t ws_bytes, void* stream);
+/* Layout moves between a global field [3][n2][n1][n0] (x fastest) and the  */
+/* box layout of lv (valid cells of the covered boxes only; ghost cells of  */
+/* boxed and cells of uncovered boxes in glob are left alone).              */
+int ib_field_to_boxes(const ib_level* lv, ib_prec prec, const void* glob, void* boxed,
+                      void* stream);
+int ib_field_from_boxes(const ib_level* lv, ib_prec prec, const void* boxed, void* glob,
+                        void* stream);
+
 const char* ib_status_string(int status);
 const char* ib_last_hip_error(void);
 int ib_version(void);

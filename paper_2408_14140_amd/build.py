@@ -15,7 +15,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libibx.so")
 SOURCES = ["common.hip", "bucket.hip", "plain.hip", "batched.hip", "reduce.hip",
-           "backward.hip", "rigid.hip", "sequential.hip", "api.hip"]
+           "backward.hip", "rigid.hip", "sequential.hip", "fluid.hip",
+           "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -101,6 +101,13 @@ _levels = _sig("ib_particle_levels", C.c_int, [_PL, _PP, C.c_int, _p, _p, _p, _s
 _seq_ws = _sig("ib_sequential_workspace_bytes", _sz, [_p, _PL, _i32, _i64, _i32])
 _sequential = _sig("ib_multidirect_sequential", C.c_int,
                    [_p, _PL, _PP, _PM, _i32, _d, _p, _i32, _p, _p, _p, _p, _p, _p, _sz, _p])
+_fl_ws = _sig("ib_fluid_workspace", _sz, [_i32, C.c_int])
+_fl_predict = _sig("ib_fluid_predict", C.c_int,
+                   [_i32, _d, C.c_int, _d, _d, _d, _p, _p, _p, _p, _p, _sz, _p])
+_fl_project = _sig("ib_fluid_project", C.c_int,
+                   [_i32, _d, C.c_int, _d, _d, _p, _p, _p, _p, _p, _sz, _p])
+_to_boxes = _sig("ib_field_to_boxes", C.c_int, [_PL, C.c_int, _p, _p, _p])
+_from_boxes = _sig("ib_field_from_boxes", C.c_int, [_PL, C.c_int, _p, _p, _p])
 _status_string = _sig("ib_status_string", C.c_char_p, [C.c_int])
 _last_hip_error = _sig("ib_last_hip_error", C.c_char_p, [])
 _version = _sig("ib_version", C.c_int, [])
@@ -112,7 +119,8 @@ EXPORTED = ("ib_count_markers", "ib_build_markers", "ib_desired_velocity", "ib_b
             "ib_reductions_workspace", "ib_particle_reductions", "ib_backward_workspace_bytes", "ib_multidirect_backward",
             "ib_rigid_update", "ib_advect_markers", "ib_collision_forces",
             "ib_levels_workspace", "ib_particle_levels", "ib_sequential_workspace_bytes",
-            "ib_multidirect_sequential", "ib_status_string", "ib_last_hip_error", "ib_version")
+            "ib_multidirect_sequential", "ib_fluid_workspace", "ib_fluid_predict",
+            "ib_fluid_project", "ib_field_to_boxes", "ib_field_from_boxes", "ib_status_string", "ib_last_hip_error", "ib_version")
 
 
 class IbxError(RuntimeError):
@@ -589,6 +597,52 @@ def particle_levels(level: DeviceLevel, parts: Particles, delta: int):
     _check(_levels(C.byref(lc), C.byref(pc), int(delta), _ptr(lvl), C.byref(n), _ptr(ws),
                    int(ws.numel()), _stream()), "ib_particle_levels")
     return lvl, int(n.value)
+
+
+# ---------------------------------------------------------------- fluid steps
+
+class Fluid:
+    """Single-level periodic fluid steps on an n^3 grid (Sec. 3.1, Steps 1 and
+    3): velocity [3][n][n][n] cell-centred, pressure [n][n][n] on the nodes."""
+
+    def __init__(self, n: int, h: float, dtype=torch.float64, device=None):
+        self.n, self.h, self.dtype = int(n), float(h), dtype
+        nb = int(_fl_ws(self.n, _prec_of(dtype)))
+        if nb == 0:
+            raise IbxError(IB_EUNSUPPORTED, "ib_fluid_workspace")
+        self._ws = torch.empty(nb, dtype=torch.uint8, device=_dev(device))
+
+    def predict(self, u, p, rho: float, mu: float, dt: float, grav, out=None):
+        """Eq. (31): u~* from u^n and p^{n-1/2}."""
+        out = torch.empty_like(u) if out is None else out
+        g3 = (C.c_double * 3)(*[float(v) for v in grav])
+        _check(_fl_predict(self.n, self.h, _prec_of(u.dtype), float(rho), float(mu), float(dt),
+                           C.cast(g3, C.c_void_p), _ptr(u), _ptr(p), _ptr(out), _ptr(self._ws),
+                           int(self._ws.numel()), _stream()), "ib_fluid_predict")
+        return out
+
+    def project(self, ustar, p_old, rho: float, dt: float, u_out=None, p_out=None):
+        """Eqs. (ns_lp1)-(ns_lp3): (u^{n+1}, p^{n+1/2})."""
+        u_out = torch.empty_like(ustar) if u_out is None else u_out
+        p_out = torch.empty_like(p_old) if p_out is None else p_out
+        _check(_fl_project(self.n, self.h, _prec_of(ustar.dtype), float(rho), float(dt),
+                           _ptr(ustar), _ptr(p_old), _ptr(u_out), _ptr(p_out), _ptr(self._ws),
+                           int(self._ws.numel()), _stream()), "ib_fluid_project")
+        return u_out, p_out
+
+
+def field_to_boxes(level: DeviceLevel, glob: torch.Tensor, boxed: torch.Tensor) -> torch.Tensor:
+    lc = level.c
+    _check(_to_boxes(C.byref(lc), _prec_of(glob.dtype), _ptr(glob), _ptr(boxed), _stream()),
+           "ib_field_to_boxes")
+    return boxed
+
+
+def field_from_boxes(level: DeviceLevel, boxed: torch.Tensor, glob: torch.Tensor) -> torch.Tensor:
+    lc = level.c
+    _check(_from_boxes(C.byref(lc), _prec_of(boxed.dtype), _ptr(boxed), _ptr(glob), _stream()),
+           "ib_field_from_boxes")
+    return glob
 
 
 def version() -> int:

@@ -86,16 +86,16 @@ def test_count_markers_rejects_bad_arguments(lib, np_, h, d):
 
 
 def test_build_entry_calls_both_builders(monkeypatch):
-    """build() compiles the library and the oracle (stand-ins record the calls)."""
+    """build() compiles the library and the oracle (stand-ins record the calls)
+    and reaches the library's builder without importing the package first."""
     import importlib
 
-    # import_module returns the submodules themselves (the oracle package
-    # re-exports a function of the same name)
-    ob = importlib.import_module("oracle.build")
-    lb = importlib.import_module("paper_2408_14140_amd.build")
+    import __graft_entry__ as ge
+    ge = importlib.reload(ge)
+    assert ge._library_builder().__module__ == "_libibx_build"
+    ob = importlib.import_module("oracle.build")   # the submodule, not the re-exported function
     calls = []
     monkeypatch.setattr(ob, "build", lambda *a, **k: calls.append("oracle"))
-    monkeypatch.setattr(lb, "build", lambda *a, **k: calls.append("library"))
-    import __graft_entry__ as ge
-    importlib.reload(ge).build()
+    monkeypatch.setattr(ge, "_library_builder", lambda: (lambda: calls.append("library")))
+    ge.build()
     assert sorted(calls) == ["library", "oracle"]

@@ -1,0 +1,167 @@
+"""GPU parity of the single-level periodic fluid steps (Sec. 3.1, Step 1 =
+Eq. (31), Step 3 = Eqs. (ns_lp1)-(ns_lp3)) against the FP64 NumPy oracle,
+on small grids and at the 256^3 size, the layout moves between the global
+and the box layout, and one whole time step (predictor, multidirect loop,
+projection) chained on the GPU against the same chain in the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import Case, announce, gpu_device, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return gpu_device()
+
+
+def _kappa(n):
+    """Spread of the kept eigenvalues of D G: the largest is 4/h^2, the
+    smallest 4/h^2 sin^2(pi/n) (the lowest mode, and the modes one step from
+    the null checkerboards).  Rounding of D V is amplified by up to this
+    factor in p, and by its square root in G p; u = dt (V - G p / rho) takes
+    no amplification in its well-determined part."""
+    return 1.0 / np.sin(np.pi / n) ** 2
+
+
+def _inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    u = W.fourier_field(rng, (n, n, n), h, (0.0, 0.0, 0.0), 8, 4)
+    u = u + 0.05 * rng.normal(size=u.shape)           # not divergence-free
+    p = rng.normal(size=(n, n, n))
+    return u, p, h
+
+
+@pytest.mark.parametrize("n,dtype", [(8, "f64"), (32, "f64"), (64, "f64"), (8, "f32"),
+                                     (32, "f32"), (64, "f32"), (256, "f32")])
+def test_predict_and_project_match_oracle(dev, n, dtype):
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    from oracle import fluid as FL
+    announce(f"fluid steps n={n} {dtype}")
+    u, p, h = _inputs(n, 40 + n)
+    rho, mu, dt, g = 1.2, 0.03, 0.5 * h, (0.0, -9.81, 0.5)
+    ref_s = FL.predict(u, p, h, rho, mu, dt, g)
+    ref_u, ref_p = FL.project(ref_s, p, h, rho, dt)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    tol = TOL64 if dtype == "f64" else TOL32
+    fl = ibx.Fluid(n, h, tdt, dev)
+    tu = torch.as_tensor(u, device=dev).to(tdt)
+    tp = torch.as_tensor(p, device=dev).to(tdt)
+    s = fl.predict(tu, tp, rho, mu, dt, g)
+    # the projection is checked on the oracle's own u~* so that the two
+    # steps are pinned separately
+    u1, p1 = fl.project(torch.as_tensor(ref_s, device=dev).to(tdt), tp, rho, dt)
+    torch.cuda.synchronize()
+    assert rel(s.cpu().numpy(), ref_s) <= tol
+    assert rel(u1.cpu().numpy(), ref_u) <= tol
+    kap = _kappa(n)
+    gp = FL.grad_nodes(p1.double().cpu().numpy(), h)
+    assert rel(gp, FL.grad_nodes(ref_p, h)) <= tol * np.sqrt(kap)
+    assert rel(p1.cpu().numpy(), ref_p) <= tol * kap
+    div = FL.div_nodes(u1.double().cpu().numpy(), h)
+    scale = np.abs(FL.div_nodes(ref_s / dt + FL.grad_nodes(p, h) / rho, h)).max() * dt
+    assert np.abs(div).max() <= (1e-4 if dtype == "f32" else 1e-11) * scale
+
+
+def test_in_place_aliasing(dev):
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    announce("fluid in place")
+    n = 32
+    u, p, h = _inputs(n, 7)
+    fl = ibx.Fluid(n, h, torch.float64, dev)
+    tu = torch.as_tensor(u, device=dev)
+    tp = torch.as_tensor(p, device=dev)
+    s = fl.predict(tu, tp, 1.0, 0.01, 0.5 * h, (0, 0, 0))
+    u1, p1 = fl.project(s, tp, 1.0, 0.5 * h)
+    a = tu.clone()
+    fl.predict(a, tp, 1.0, 0.01, 0.5 * h, (0, 0, 0), out=a)
+    b = tp.clone()
+    fl.project(a, b, 1.0, 0.5 * h, u_out=a, p_out=b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, u1) and torch.equal(b, p1)
+
+
+def test_rejects_unsupported_sizes(dev):
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    for n in (4, 48):
+        with pytest.raises(ibx.IbxError):
+            ibx.Fluid(n, 1.0 / n, torch.float64, dev)
+
+
+def test_layout_round_trip(dev):
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    announce("field layout round trip")
+    wl = W.config(3, 0, with_field=False)            # partial coverage of 256^3
+    lev = wl.level
+    rng = np.random.default_rng(5)
+    n = lev.n[0]
+    glob = rng.normal(size=(3, n, n, n)).astype(np.float32)
+    dl = ibx.device_level(lev, dev)
+    tg = torch.as_tensor(glob, device=dev)
+    boxed = torch.full((lev.nbox, 3) + (lev.box + 2 * lev.ngrow,) * 3, float("nan"),
+                       dtype=torch.float32, device=dev)
+    ibx.field_to_boxes(dl, tg, boxed)
+    back = torch.zeros_like(tg)
+    ibx.field_from_boxes(dl, boxed, back)
+    torch.cuda.synchronize()
+    ref = W.to_boxes(glob, lev, fill=np.nan, dtype=np.float32)
+    assert np.array_equal(boxed.cpu().numpy(), ref, equal_nan=True)
+    mask = np.broadcast_to(lev.covered_mask(), glob.shape)
+    bk = back.cpu().numpy()
+    assert np.array_equal(bk[mask], glob[mask]) and np.all(bk[~mask] == 0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_whole_time_step(dev, dtype):
+    """u^n, p^{n-1/2} -> Step 1 -> Step 2 (multidirect loop, in place on the
+    box layout) -> Step 3, against the oracle's predictor, loop and
+    projection on the global grid."""
+    import torch
+
+    import oracle as O
+    import paper_2408_14140_amd as ibx
+    from gpu_common import small_workload
+    from oracle import fluid as FL
+    announce(f"whole time step {dtype}")
+    wl = small_workload(32, 16, 4, 3, 5)            # every box covered
+    lev = wl.level
+    n, h = lev.n[0], lev.h
+    c = Case(wl, dev)
+    rng = np.random.default_rng(9)
+    p = rng.normal(size=(n, n, n))
+    rho, mu, g = 1.0, 0.02, (0.0, 0.0, -1.0)
+    s = FL.predict(wl.u0, p, h, rho, mu, wl.dt, g)
+    ib = O.multidirect(c.g, wl.delta, wl.ns, wl.dt, c.m, wl.xc, wl.up, wl.om, s)
+    ref_u, ref_p = FL.project(ib["ustar"], p, h, rho, wl.dt)
+
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    tol = TOL64 if dtype == "f64" else TOL32
+    fl = ibx.Fluid(n, h, tdt, dev)
+    u = torch.as_tensor(wl.u0, device=dev).to(tdt)
+    tp = torch.as_tensor(p, device=dev).to(tdt)
+    boxed = torch.zeros((lev.nbox, 3) + (lev.box + 2 * lev.ngrow,) * 3, dtype=tdt, device=dev)
+    b = ibx.bucket(c.dl, c.dm, wl.delta)
+    plan = ibx.Plan(wl.delta, tdt, ibx.IB_PATH_BATCHED)
+    fl.predict(u, tp, rho, mu, wl.dt, g, out=u)
+    ibx.field_to_boxes(c.dl, u, boxed)
+    _, f, F = plan.multidirect_force(c.dl, c.parts, c.dm, b, wl.ns, wl.dt, boxed, ustar=boxed)
+    ibx.field_from_boxes(c.dl, boxed, u)
+    u1, p1 = fl.project(u, tp, rho, wl.dt)
+    torch.cuda.synchronize()
+    assert rel(F.cpu().numpy(), ib["F"]) <= tol
+    assert rel(u1.cpu().numpy(), ref_u) <= tol
+    assert rel(p1.cpu().numpy(), ref_p) <= tol * _kappa(n)
