@@ -134,6 +134,8 @@ def run():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--bucket-width", type=int, default=0)
     ap.add_argument("--spread-wgs", type=int, default=0)
+    ap.add_argument("--no-fluid", action="store_true",
+                    help="skip the fluid steps and the whole time step")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the particle-by-particle (level by level) loop")
     ap.add_argument("--no-autotune", action="store_true",
@@ -252,6 +254,39 @@ def run():
     }
     log(f"particle step {json.dumps(particle_ms)}")
 
+    # the fluid steps around the loop on the same 256^3 grid (FP32), and one
+    # whole time step: Step 1, Step 2 (markers, bucketing, loop, sums), Step 3,
+    # Step 4 (rigid update, marker advection)
+    fluid_ms = None
+    if not args.no_fluid:
+        nf = lev.n[0]
+        fl = ibx.Fluid(nf, lev.h, torch.float32, dev)
+        ug = torch.as_tensor(wl.u0, device=dev).float()
+        pg = torch.zeros((nf, nf, nf), dtype=torch.float32, device=dev)
+        usg = torch.empty_like(ug)
+        ung = torch.empty_like(ug)
+        png = torch.empty_like(pg)
+        grav = (0.0, 0.0, -9.81)
+
+        def whole_step():
+            fl.predict(ug, pg, 1.0, 1e-3, dt, grav, out=usg)
+            ibx.field_to_boxes(dl, usg, u32)
+            step()
+            ibx.field_from_boxes(dl, u32, usg)
+            fl.project(usg, pg, 1.0, dt, u_out=ung, p_out=png)
+            ibx.rigid_update(parts, rho_p, red, red1, 1.0, grav, dt)
+            ibx.advect_markers(m, parts.xc, xc1, parts.om, om1, dt, out=madv)
+
+        fluid_ms = {
+            "predict": timed(captured(lambda: fl.predict(ug, pg, 1.0, 1e-3, dt, grav, out=usg)),
+                             args.steps),
+            "project": timed(captured(lambda: fl.project(usg, pg, 1.0, dt, u_out=ung, p_out=png)),
+                             args.steps),
+            "time_step": timed(captured(whole_step), args.steps),
+        }
+        log(f"fluid {json.dumps(fluid_ms)}")
+        del fl, ug, pg, usg, ung, png
+
     # per-kernel breakdown over the same number of loops, events on the launch stream
     plan.profile(True)
     for _ in range(args.steps):
@@ -317,6 +352,7 @@ def run():
         "loop_ms": ms_loop,
         "step_parts_ms": parts_ms,
         "particle_step_ms": particle_ms,
+        "fluid_256_fp32_ms": fluid_ms,
         "loop_marker_iters_per_s": N * ns / (ms_loop * 1e-3),
         "loop_model_gbs": bmodel / (ms_loop * 1e-3) / 1e9,
         "loop_model_bytes": bmodel,

@@ -104,6 +104,69 @@ k_fft_lines(Cx<T>* __restrict__ data, int n, int logn, int axis, const Cx<T>* __
     }
 }
 
+// Lines along y or z, 2^lx of them side by side (consecutive x) per
+// workgroup, so that every load and store moves 2^lx consecutive elements:
+// LDS holds [n][2^lx] (element j of line xi at j * 2^lx + xi).
+template <typename T, bool INV>
+__global__ void __launch_bounds__(256)
+k_fft_cols(Cx<T>* __restrict__ data, int n, int logn, int lx, int axis,
+           const Cx<T>* __restrict__ W, T scale)
+{
+    extern __shared__ unsigned char smem[];
+    const int X = 1 << lx;
+    Cx<T>* a = reinterpret_cast<Cx<T>*>(smem);
+    Cx<T>* b = a + (size_t)n * X;
+    Cx<T>* w = b + (size_t)n * X;
+    const int t = threadIdx.x;
+    const int64_t nn = (int64_t)n * n;
+    const int groups_x = n >> lx;
+    const int64_t x0 = (int64_t)(blockIdx.x % groups_x) << lx;
+    const int64_t other = blockIdx.x / groups_x;
+    const int64_t stride = axis == 1 ? n : nn;
+    const int64_t base = x0 + (axis == 1 ? other * nn : other * n);
+    const int half = n >> 1;
+    const int tot = n << lx;
+    for (int idx = t; idx < tot; idx += blockDim.x) {
+        const int j = idx >> lx, xi = idx & (X - 1);
+        a[idx] = data[base + xi + j * stride];
+    }
+    for (int q = t; q < half; q += blockDim.x)
+        w[q] = W[q];
+    __syncthreads();
+    Cx<T>* src = a;
+    Cx<T>* dst = b;
+    for (int s = 0; s < logn; ++s) {
+        const int ns = 1 << s;
+        for (int idx = t; idx < (half << lx); idx += blockDim.x) {
+            const int i = idx >> lx, xi = idx & (X - 1);
+            const int k = i & (ns - 1), jb = i >> s;
+            const Cx<T> u = src[(i << lx) + xi], v = src[((i + half) << lx) + xi];
+            Cx<T> tw = w[k << (logn - 1 - s)];
+            if (INV)
+                tw.y = -tw.y;
+            Cx<T> vt;
+            vt.x = tw.x * v.x - tw.y * v.y;
+            vt.y = tw.x * v.y + tw.y * v.x;
+            const int o = (jb << (s + 1)) + k;
+            dst[(o << lx) + xi].x = u.x + vt.x;
+            dst[(o << lx) + xi].y = u.y + vt.y;
+            dst[((o + ns) << lx) + xi].x = u.x - vt.x;
+            dst[((o + ns) << lx) + xi].y = u.y - vt.y;
+        }
+        __syncthreads();
+        Cx<T>* tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    for (int idx = t; idx < tot; idx += blockDim.x) {
+        const int j = idx >> lx, xi = idx & (X - 1);
+        Cx<T> v = src[idx];
+        v.x *= scale;
+        v.y *= scale;
+        data[base + xi + j * stride] = v;
+    }
+}
+
 template <typename T>
 static void fft3(Cx<T>* data, int n, int logn, const Cx<T>* W, bool inv, hipStream_t st)
 {
@@ -111,11 +174,23 @@ static void fft3(Cx<T>* data, int n, int logn, const Cx<T>* W, bool inv, hipStre
     const int threads = n / 2 < 64 ? 64 : (n / 2 > 512 ? 512 : n / 2);
     const size_t lds = sizeof(Cx<T>) * (2 * (size_t)n + n / 2);
     const T scale = inv ? (T)(1.0 / (double)n) : (T)1;
-    for (int axis = 0; axis < 3; ++axis) {
+    if (inv)
+        k_fft_lines<T, true><<<lines, threads, lds, st>>>(data, n, logn, 0, W, scale);
+    else
+        k_fft_lines<T, false><<<lines, threads, lds, st>>>(data, n, logn, 0, W, scale);
+    // y and z: as many side-by-side lines as keep the two LDS planes and the
+    // twiddles within 64 KiB (at most 16, at most n)
+    int lx = 0;
+    while (lx < 4 && (2 << lx) <= n &&
+           (2 * (size_t)n * (2u << lx) + n / 2) * sizeof(Cx<T>) <= 65536)
+        ++lx;
+    const size_t ldsc = sizeof(Cx<T>) * (2 * ((size_t)n << lx) + n / 2);
+    const unsigned groups = (unsigned)(((int64_t)n * n) >> lx);
+    for (int axis = 1; axis < 3; ++axis) {
         if (inv)
-            k_fft_lines<T, true><<<lines, threads, lds, st>>>(data, n, logn, axis, W, scale);
+            k_fft_cols<T, true><<<groups, 256, ldsc, st>>>(data, n, logn, lx, axis, W, scale);
         else
-            k_fft_lines<T, false><<<lines, threads, lds, st>>>(data, n, logn, axis, W, scale);
+            k_fft_cols<T, false><<<groups, 256, ldsc, st>>>(data, n, logn, lx, axis, W, scale);
     }
 }
 
