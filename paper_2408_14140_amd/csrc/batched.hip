@@ -337,10 +337,89 @@ k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, co
 }
 
 template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+
+// The same for an even ghost width, two neighbouring x cells per thread (every
+// pair starts on an even element of the box layout and of the tile slots):
+// one workgroup per (box, row of tiles in y, pair of z planes).
+template <typename T, bool F_ACC>
+__global__ void __launch_bounds__(256)
+k_finalize_pairs(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, const T* u0,
+                 T* ustar, T* __restrict__ f, double dt, int use_g)
+{
+    using V2 = typename Pair<T>::type;
+    __shared__ int tslot[64];                 // G slot of each tile along the row
+    const int B = g.box;
+    const int nty = B / TILE, ntx = B / TILE, npx = B / 2;
+    const int per_box = nty * (B / 2);
+    const int64_t items = (int64_t)g.nbox * per_box;
+    const T tdt = (T)dt;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int bid = (int)(it / per_box);
+        const int rem = (int)(it - (int64_t)bid * per_box);
+        const int ty = rem / (B / 2), lz0 = 2 * (rem - ty * (B / 2));
+        const int bx0 = g.box_lo[3 * bid], by0 = g.box_lo[3 * bid + 1], bz0 = g.box_lo[3 * bid + 2];
+        const int cz0 = bz0 + lz0, cyt = (by0 >> 3) + ty;
+        for (int k = threadIdx.x; k < ntx; k += blockDim.x)
+            tslot[k] = use_g ? slot[(bx0 >> 3) + k + g.nt[0] * (cyt + g.nt[1] * (cz0 >> 3))] : -1;
+        __syncthreads();
+        for (int q = threadIdx.x; q < 2 * TILE * npx; q += blockDim.x) {
+            const int px = q % npx, r = q / npx;
+            const int yy = r & (TILE - 1), pz = r >> 3;
+            const int lx = 2 * px, ly = ty * TILE + yy, lz = lz0 + pz;
+            const int s = tslot[lx >> 3];
+            const int64_t off = (int64_t)bid * g.bstride +
+                                ((int64_t)(lz + g.ngrow) * g.ext + (ly + g.ngrow)) * g.ext +
+                                (lx + g.ngrow);
+            const int64_t go =
+                (int64_t)s * 3 * TILE_CELLS + (lx & 7) + TILE * (yy + TILE * ((cz0 + pz) & 7));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                V2 v = {T(0), T(0)};
+                if (s >= 0)
+                    v = *reinterpret_cast<const V2*>(G + go + c * TILE_CELLS);
+                const int64_t o = off + c * g.cstride;
+                if (f && !F_ACC) {
+                    __builtin_nontemporal_store(v, reinterpret_cast<V2*>(f + o));
+                } else if (f && s >= 0) {
+                    V2 w = *reinterpret_cast<const V2*>(f + o);
+                    *reinterpret_cast<V2*>(f + o) = w + v;
+                }
+                if (s >= 0) {
+                    const V2 a = *reinterpret_cast<const V2*>(u0 + o);
+                    __builtin_nontemporal_store(a + tdt * v, reinterpret_cast<V2*>(ustar + o));
+                } else if (ustar != u0) {
+                    const V2 a = *reinterpret_cast<const V2*>(u0 + o);
+                    __builtin_nontemporal_store(a, reinterpret_cast<V2*>(ustar + o));
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
 static void launch_finalize(unsigned grid, hipStream_t st, const Grid& g, const int32_t* slot,
                             const T* G, const T* u0, T* ustar, T* f, double dt, int use_g,
                             int f_acc)
 {
+    if ((g.ngrow & 1) == 0) {
+        const int64_t items = (int64_t)g.nbox * (g.box / TILE) * (g.box / 2);
+        const unsigned gp = (unsigned)(items < 65535 ? (items > 0 ? items : 1) : 65535);
+        if (f_acc)
+            k_finalize_pairs<T, true><<<gp, 256, 0, st>>>(g, slot, G, u0, ustar, f, dt, use_g);
+        else
+            k_finalize_pairs<T, false><<<gp, 256, 0, st>>>(g, slot, G, u0, ustar, f, dt, use_g);
+        return;
+    }
     if (f_acc)
         k_finalize<T, true><<<grid, 256, 0, st>>>(g, slot, G, u0, ustar, f, dt, use_g);
     else
