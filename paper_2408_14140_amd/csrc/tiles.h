@@ -388,30 +388,39 @@ __device__ inline int wave_exclusive_sum(int v)
 // (r even) or r W + W - 1 - w (r odd) of the slab.
 //
 // Sources are staged 64 at a time as structure-of-arrays in LDS: the weight
-// of every tile x cell, y row and z row (zero outside the stencil) and
-// F dV/h^3.  Sixteen ballots give, per tile row y and per tile row z, the
-// 64-bit set of staged sources whose stencil covers it; a lane's own set is
-// the AND of its two, and the lane visits exactly those sources in list
-// order.  The staging arrays share LDS with the transpose buffer.
+// of every tile x cell (zero outside the stencil), the P weights along y and
+// along z with the stencil's first row, and F dV/h^3.  Sixteen ballots give,
+// per tile row y and per tile row z, the 64-bit set of staged sources whose
+// stencil covers it; a lane's own set is the AND of its two, and the lane
+// visits exactly those sources in list order.  Each lane holds one (y, z) row
+// of the tile and stores it straight to the slot (rows are contiguous there).
+// LDS stays near 5.9 KB so that 24 or more workgroups fit on a CU.
+// (FP32: registers capped so that 6 waves fit per SIMD, the residency that the
+// latency-bound visit chain wants; no spills at that cap.)
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8)))
 k_spread_tiles(const int32_t* __restrict__ order, const int32_t* __restrict__ active,
                const int32_t* __restrict__ nactive,
                const int32_t* __restrict__ src_offs, const int32_t* __restrict__ src_idx,
                Grid g, MarkerData<T> s, T* __restrict__ G)
 {
-    constexpr int NW = 3 * TILE + 3;                       // staged values per source
-    constexpr int NBUF = NW * 64 > 3 * TILE_CELLS ? NW * 64 : 3 * TILE_CELLS;
+    constexpr int NW = TILE + 2 * P + 3;                   // staged values per source
+    constexpr int NBUF = NW * 64;
+    constexpr int MAXP = NBUF / (3 * TILE) < 64 ? NBUF / (3 * TILE) : 64;   // phase-B pieces
     __shared__ T buf[NBUF];
+    __shared__ int32_t sb[64];          // stencil's first row: (by + 8) | (bz + 8) << 8
     T* const sx = buf;                  // [TILE][64] x weight of tile cell x
-    T* const sy = buf + TILE * 64;      // [TILE][64] y weight of tile row y
-    T* const sz = buf + 2 * TILE * 64;  // [TILE][64] z weight of tile row z
-    T* const sf = buf + 3 * TILE * 64;  // [3][64]    F dV / h^3
+    T* const sy = buf + TILE * 64;      // [P][64]    y weights
+    T* const sz = sy + P * 64;          // [P][64]    z weights
+    T* const sf = sz + P * 64;          // [3][64]    F dV / h^3
     __shared__ uint64_t rest[64];       // sources of each row left after phase A
-    __shared__ int32_t piece[64];       // phase-B slot -> row | piece << 8
+    __shared__ int32_t piece[MAXP];     // phase-B slot -> row | piece << 8
     // add source k's contribution to the 8 cells of row (y, z)
     auto visit = [&](T (&a)[TILE][3], int y, int z, int k) {
-        const T wyz = sy[y * 64 + k] * sz[z * 64 + k];
+        const int bb = sb[k];
+        const int dy = y + 8 - (bb & 255), dz = z + 8 - (bb >> 8);
+        const T wyz = sy[dy * 64 + k] * sz[dz * 64 + k];
         const T c0 = sf[k] * wyz, c1 = sf[64 + k] * wyz, c2 = sf[128 + k] * wyz;
 #pragma unroll
         for (int x = 0; x < TILE; ++x) {
@@ -437,11 +446,11 @@ k_spread_tiles(const int32_t* __restrict__ order, const int32_t* __restrict__ ac
         tile_coords(g, t, lo);
         T acc[TILE][3];
 #pragma unroll
-        for (int x = 0; x < TILE; ++x)
-            acc[x][0] = acc[x][1] = acc[x][2] = T(0);
+        for (int xx = 0; xx < TILE; ++xx)
+            acc[xx][0] = acc[xx][1] = acc[xx][2] = T(0);
         const int s0 = src_offs[t], s1 = src_offs[t + 1];
-        for (int sb = s0; sb < s1; sb += 64) {
-            const int sidx = sb + lane;
+        for (int sbat = s0; sbat < s1; sbat += 64) {
+            const int sidx = sbat + lane;
             int by = 64, bz = 64;       // no row for lanes past the list
             if (sidx < s1) {
                 const int64_t i = src_idx[sidx];
@@ -458,15 +467,19 @@ k_spread_tiles(const int32_t* __restrict__ order, const int32_t* __restrict__ ac
                 by = b[1];
                 bz = b[2];
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax)
+                for (int xx = 0; xx < TILE; ++xx) {
+                    T wv = T(0);
 #pragma unroll
-                    for (int x = 0; x < TILE; ++x) {
-                        T wv = T(0);
+                    for (int o = 0; o < P; ++o)
+                        wv = (xx - b[0] == o) ? gm.w[0][o] : wv;
+                    sx[xx * 64 + lane] = wv;
+                }
 #pragma unroll
-                        for (int o = 0; o < P; ++o)
-                            wv = (x - b[ax] == o) ? gm.w[ax][o] : wv;
-                        buf[(ax * TILE + x) * 64 + lane] = wv;
-                    }
+                for (int o = 0; o < P; ++o) {
+                    sy[o * 64 + lane] = gm.w[1][o];
+                    sz[o * 64 + lane] = gm.w[2][o];
+                }
+                sb[lane] = (by + 8) | ((bz + 8) << 8);
                 sf[0 * 64 + lane] = Fv.x * gm.rs;
                 sf[1 * 64 + lane] = Fv.y * gm.rs;
                 sf[2 * 64 + lane] = Fv.z * gm.rs;
@@ -482,7 +495,7 @@ k_spread_tiles(const int32_t* __restrict__ order, const int32_t* __restrict__ ac
             __syncthreads();
             // Phase A: every lane visits up to K sources of its own row.
             // Phase B: what is left of the heavier rows is cut into pieces of
-            // K sources dealt out to all 64 lanes; the owners then add the
+            // K sources dealt out to the lanes; the owners then add the
             // pieces in order.  K is the smallest cap whose pieces fit.
             uint64_t M = my & mz;
             const int n = __popcll(M);
@@ -493,14 +506,14 @@ k_spread_tiles(const int32_t* __restrict__ order, const int32_t* __restrict__ ac
                 while (lo_k < hi_k) {
                     const int mid = (lo_k + hi_k) >> 1;
                     const int pieces = wave_sum(n > mid ? small_div(n - 1, mid) : 0);
-                    if (pieces <= 64)
+                    if (pieces <= MAXP)
                         hi_k = mid;
                     else
                         lo_k = mid + 1;
                 }
                 K = lo_k;
             }
-            for (int t = 0; t < K && M; ++t) {
+            for (int tt = 0; tt < K && M; ++tt) {
                 const int k = __builtin_ctzll(M);
                 M &= M - 1;
                 visit(acc, ly, lz, k);
@@ -515,14 +528,14 @@ k_spread_tiles(const int32_t* __restrict__ order, const int32_t* __restrict__ ac
                 __syncthreads();
                 T pacc[TILE][3];
 #pragma unroll
-                for (int x = 0; x < TILE; ++x)
-                    pacc[x][0] = pacc[x][1] = pacc[x][2] = T(0);
+                for (int xx = 0; xx < TILE; ++xx)
+                    pacc[xx][0] = pacc[xx][1] = pacc[xx][2] = T(0);
                 if (lane < NP) {
                     const int pr = piece[lane] & 255, pq = piece[lane] >> 8;
                     uint64_t m = rest[pr];
                     for (int q = 0; q < pq * K; ++q)
                         m &= m - 1;
-                    for (int t = 0; t < K && m; ++t) {
+                    for (int tt = 0; tt < K && m; ++tt) {
                         const int k = __builtin_ctzll(m);
                         m &= m - 1;
                         visit(pacc, pr & 7, pr >> 3, k);
@@ -532,39 +545,38 @@ k_spread_tiles(const int32_t* __restrict__ order, const int32_t* __restrict__ ac
                 // the staged sources are no longer needed: pieces reuse them
                 if (lane < NP) {
 #pragma unroll
-                    for (int x = 0; x < TILE; ++x)
+                    for (int xx = 0; xx < TILE; ++xx)
 #pragma unroll
                         for (int c = 0; c < 3; ++c)
-                            buf[lane * 3 * TILE + 3 * x + c] = pacc[x][c];
+                            buf[lane * 3 * TILE + 3 * xx + c] = pacc[xx][c];
                 }
                 __syncthreads();
                 for (int q = 0; q < np; ++q) {
                     const T* pp = buf + (ps + q) * 3 * TILE;
 #pragma unroll
-                    for (int x = 0; x < TILE; ++x)
+                    for (int xx = 0; xx < TILE; ++xx)
 #pragma unroll
                         for (int c = 0; c < 3; ++c)
-                            acc[x][c] += pp[3 * x + c];
+                            acc[xx][c] += pp[3 * xx + c];
                 }
             }
             __syncthreads();
         }
-        // transpose the tile through LDS, then coalesced stores
-        T* const tr = buf;              // [3][TILE_CELLS]
-        const int cell0 = TILE * ly + TILE * TILE * lz;
+        // the lane's row is 8 consecutive cells of each component in the slot
+        T* gs = G + (int64_t)a * 3 * TILE_CELLS + TILE * lane;
 #pragma unroll
-        for (int x = 0; x < TILE; ++x) {
-            tr[0 * TILE_CELLS + cell0 + x] = acc[x][0];
-            tr[1 * TILE_CELLS + cell0 + x] = acc[x][1];
-            tr[2 * TILE_CELLS + cell0 + x] = acc[x][2];
+        for (int c = 0; c < 3; ++c) {
+            typename Vec4<T>::type v0, v1;
+            v0.x = acc[0][c];
+            v0.y = acc[1][c];
+            v0.z = acc[2][c];
+            v0.w = acc[3][c];
+            v1.x = acc[4][c];
+            v1.y = acc[5][c];
+            v1.z = acc[6][c];
+            v1.w = acc[7][c];
+            *reinterpret_cast<typename Vec4<T>::type*>(gs + c * TILE_CELLS) = v0;
+            *reinterpret_cast<typename Vec4<T>::type*>(gs + c * TILE_CELLS + 4) = v1;
         }
-        __syncthreads();
-        T* gs = G + (int64_t)a * 3 * TILE_CELLS;
-        for (int q = lane; q < TILE_CELLS; q += 64) {
-            gs[q] = tr[q];
-            gs[q + TILE_CELLS] = tr[TILE_CELLS + q];
-            gs[q + 2 * TILE_CELLS] = tr[2 * TILE_CELLS + q];
-        }
-        __syncthreads();
     }
 }
