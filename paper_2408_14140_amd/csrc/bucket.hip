@@ -169,30 +169,13 @@ k_radix_rowscan(int32_t* hist, int nblocks, int32_t* rowtot)
         rowtot[blockIdx.x] = carry;
 }
 
-// digit_off[d] = number of elements with a smaller digit.
-__global__ void __launch_bounds__(256) k_radix_digits(const int32_t* rowtot, int32_t* digit_off)
-{
-    __shared__ int32_t ts[256];
-    const int t = threadIdx.x;
-    const int32_t v = rowtot[t];
-    ts[t] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int32_t x = t >= off ? ts[t - off] : 0;
-        __syncthreads();
-        ts[t] += x;
-        __syncthreads();
-    }
-    digit_off[t] = ts[t] - v;
-}
-
 // Stable scatter: elements keep their input order within each digit.  Ranks
 // inside a wave come from ballot matching on the 8 digit bits; ranks across
 // the block's waves and rounds from per-digit counters in LDS.
 __global__ void __launch_bounds__(RS_THREADS)
 k_radix_scatter(const int32_t* kin, const int32_t* vin, int32_t* kout, int32_t* vout,
                 int64_t n_max, const int32_t* n_dev, int shift, const int32_t* hist_scan,
-                const int32_t* digit_off, int nblocks)
+                const int32_t* rowtot, int nblocks)
 {
     __shared__ int32_t run[256];
     __shared__ int32_t wc[RS_WAVES][256];
@@ -201,7 +184,19 @@ k_radix_scatter(const int32_t* kin, const int32_t* vin, int32_t* kout, int32_t* 
     const int64_t n = live_count(n_max, n_dev);
     if ((int64_t)blockIdx.x * RS_TILE >= n)
         return;                             // whole block past the live count
-    run[t] = digit_off[t] + hist_scan[(int64_t)t * nblocks + blockIdx.x];
+    // digit offsets: exclusive scan of the digit totals, in every block
+    const int32_t tot = rowtot[t];
+    run[t] = tot;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int32_t xv = t >= off ? run[t - off] : 0;
+        __syncthreads();
+        run[t] += xv;
+        __syncthreads();
+    }
+    const int32_t doff = run[t] - tot;
+    __syncthreads();
+    run[t] = doff + hist_scan[(int64_t)t * nblocks + blockIdx.x];
 #pragma unroll
     for (int w = 0; w < RS_WAVES; ++w)
         wc[w][t] = 0;
@@ -259,7 +254,7 @@ static int64_t rs_blocks(int64_t n_max) { return (n_max + RS_TILE - 1) / RS_TILE
 size_t radix_workspace(int64_t n_max)
 {
     int64_t nb = rs_blocks(n_max > 0 ? n_max : 1);
-    return align_up(sizeof(int32_t) * 256 * nb) + 2 * align_up(sizeof(int32_t) * 256);
+    return align_up(sizeof(int32_t) * 256 * nb) + align_up(sizeof(int32_t) * 256);
 }
 
 void radix_sort_pairs(int32_t* keys, int32_t* vals, int32_t* tk, int32_t* tv, int64_t n_max,
@@ -270,16 +265,14 @@ void radix_sort_pairs(int32_t* keys, int32_t* vals, int32_t* tk, int32_t* tv, in
     const int64_t nb = rs_blocks(n_max);
     int32_t* hist = (int32_t*)ws;
     int32_t* rowtot = (int32_t*)((char*)ws + align_up(sizeof(int32_t) * 256 * nb));
-    int32_t* digit_off = rowtot + align_up(sizeof(int32_t) * 256) / sizeof(int32_t);
     int32_t *ka = keys, *va = vals, *kb = tk, *vb = tv;
     const int passes = (bits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         k_radix_hist<<<(unsigned)nb, RS_THREADS, 0, st>>>(ka, n_max, n_dev, shift, hist, (int)nb);
         k_radix_rowscan<<<256, RS_THREADS, 0, st>>>(hist, (int)nb, rowtot);
-        k_radix_digits<<<1, 256, 0, st>>>(rowtot, digit_off);
         k_radix_scatter<<<(unsigned)nb, RS_THREADS, 0, st>>>(ka, va, kb, vb, n_max, n_dev, shift,
-                                                             hist, digit_off, (int)nb);
+                                                             hist, rowtot, (int)nb);
         int32_t* t0 = ka; ka = kb; kb = t0;
         t0 = va; va = vb; vb = t0;
     }
@@ -356,35 +349,42 @@ __global__ void k_bucket_keys(Grid g, int64_t nl, const double* __restrict__ x,
         return;
     const double X[3] = {x[l], y[l], z[l]};
     int c[3], b[3];
-    int bad = 0;
+    int bad = 0, tcount = 1;
     int bx[3][2], nbx[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double s = grid_coord(g, a, X[a]);
         const int fl = (int)floor(s);
         b[a] = stencil_base<P>(s);
+        // first and last stencil cell on this axis (wrapped, or clipped to a
+        // bounded axis): the P consecutive cells lie in at most two boxes and
+        // two tiles, those of these two cells
+        int q0, q1;
         if (g.periodic[a]) {
             c[a] = wrapi(fl, g.n[a]);
+            q0 = wrapi(b[a], g.n[a]);
+            q1 = q0 + P - 1;
+            if (q1 >= g.n[a])
+                q1 -= g.n[a];
         } else {
             c[a] = fl;
             if (fl < 0 || fl >= g.n[a]) {
                 bad = 1;
                 c[a] = fl < 0 ? 0 : g.n[a] - 1;
             }
-        }
-        // boxes touched by the stencil cells b .. b+P-1 on this axis (at most 2)
-        nbx[a] = 0;
-        for (int o = 0; o < P; ++o) {
-            int q = b[a] + o;
-            if (g.periodic[a])
-                q = wrapi(q, g.n[a]);
-            else if (q < 0 || q >= g.n[a]) {
+            q0 = max(b[a], 0);
+            q1 = min(b[a] + P - 1, g.n[a] - 1);
+            if (b[a] < 0 || b[a] + P - 1 >= g.n[a])
                 bad = 1;
-                continue;
-            }
-            const int bq = q / g.box;
-            if (nbx[a] == 0 || (bx[a][nbx[a] - 1] != bq && (nbx[a] < 2)))
-                bx[a][nbx[a]++] = bq;
+        }
+        if (g.periodic[a] || q0 <= q1) {
+            bx[a][0] = q0 / g.box;
+            bx[a][1] = q1 / g.box;
+            nbx[a] = bx[a][1] != bx[a][0] ? 2 : 1;
+            tcount *= (q1 >> 3) != (q0 >> 3) ? 2 : 1;
+        } else {
+            nbx[a] = 0;
+            tcount = 0;
         }
     }
     for (int k = 0; k < nbx[2] && !bad; ++k)
@@ -396,13 +396,8 @@ __global__ void k_bucket_keys(Grid g, int64_t nl, const double* __restrict__ x,
     const int t = c[0] / TILE + g.nt[0] * (c[1] / TILE + g.nt[1] * (c[2] / TILE));
     tileid[l] = t;
     int key = t;
-    if (kb > 0) {
-        int tl[2], cnt = 1;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            cnt *= axis_tiles<P>(g, a, b[a], tl);
-        key |= cnt << kb;
-    }
+    if (kb > 0)
+        key |= tcount << kb;
     keys[l] = key;
     vals[l] = (int32_t)l;
     base[3 * l + 0] = b[0];
