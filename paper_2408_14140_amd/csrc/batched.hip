@@ -123,7 +123,13 @@ k_prep(Grid g, int64_t nl, const double* __restrict__ x, const double* __restric
         T w[P];
         const int b = axis_weights<T, P>(sa, w);
         const int fl = (int)floor(sa);
-        const int c = g.periodic[a] ? wrapi(fl, g.n[a]) : fl;
+        int c = fl;
+        if (g.periodic[a]) {
+            // markers sit at most a period outside: one add or subtract, else the modulo
+            c = c < 0 ? c + g.n[a] : (c >= g.n[a] ? c - g.n[a] : c);
+            if ((unsigned)c >= (unsigned)g.n[a])
+                c = wrapi(fl, g.n[a]);
+        }
         r.rb[a] = c + (b - fl);
 #pragma unroll
         for (int o = 0; o < 4; ++o)
@@ -160,10 +166,14 @@ __device__ inline int slab_of(int a, int n_act)
     return a / per;
 }
 
+// (block 0 also clears the cost histogram that k_cost_hist fills next)
 __global__ void k_tile_counts(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
                               const int32_t* __restrict__ src_offs, int32_t* item_cnt,
-                              int32_t* act)
+                              int32_t* act, int32_t* __restrict__ hist)
 {
+    if (blockIdx.x == 0)
+        for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
+            hist[b] = 0;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T)
         return;
@@ -494,7 +504,7 @@ static BatchedWs<T> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, s
     w.G = cv.take<T>((size_t)3 * TILE_CELLS * (max_active > 0 ? max_active : 1));
     w.nb_u = cv.take<int64_t>(27 * w.max_items);
     w.nb_g = cv.take<int64_t>(27 * w.max_items);
-    w.scan = cv.take<char>(scan_workspace(T_));
+    w.scan = cv.take<char>(scan2_workspace(T_));
     *need = cv.used;
     return w;
 }
@@ -551,10 +561,10 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
                                      p->up, p->om, w.s);
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_LISTS);
-    k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt, w.act);
-    scan_exclusive(w.item_cnt, w.item_offs, T_, w.nitems, w.scan, st);
-    scan_exclusive(w.act, w.act_offs, T_, w.nactive, w.scan, st);
-    k_zero<int32_t><<<NXCD, 256, 0, st>>>(NXCD * COST_BINS, w.hist);
+    k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt, w.act,
+                                      w.hist);
+    scan_exclusive2(w.item_cnt, w.item_offs, w.act, w.act_offs, T_, w.nitems, w.nactive, w.scan,
+                    st);
     k_cost_hist<<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.hist);
     k_bin_scan<<<NXCD, COST_BINS, 0, st>>>(w.hist, w.nactive, w.cur);
     k_fill_lists<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs,

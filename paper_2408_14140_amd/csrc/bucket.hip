@@ -95,6 +95,102 @@ void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* total, 
     k_scan_add<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(out, n, sums);
 }
 
+// Two independent scans of the same length in one pass per level: block b
+// of the first kernel scans tile b of array 0 (b < nb) or tile b - nb of
+// array 1.
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_scan_tile2(const int32_t* in0, int32_t* out0, const int32_t* in1, int32_t* out1, int64_t n,
+             int32_t* sums)
+{
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    const bool second = blockIdx.x >= nb;
+    const int64_t blk = second ? blockIdx.x - nb : blockIdx.x;
+    const int32_t* in = second ? in1 : in0;
+    int32_t* out = second ? out1 : out0;
+    __shared__ int32_t ts[SCAN_THREADS];
+    const int t = threadIdx.x;
+    const int64_t base = blk * SCAN_TILE + (int64_t)t * SCAN_ITEMS;
+    int32_t v[SCAN_ITEMS];
+    int32_t tsum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        tsum += v[k];
+    }
+    ts[t] = tsum;
+    __syncthreads();
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+        int32_t x = (t >= off) ? ts[t - off] : 0;
+        __syncthreads();
+        ts[t] += x;
+        __syncthreads();
+    }
+    int32_t run = ts[t] - tsum;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n)
+            out[base + k] = run;
+        run += v[k];
+    }
+    if (t == SCAN_THREADS - 1)
+        sums[blockIdx.x] = ts[t];
+}
+
+// Adds the scanned tile sums back (sums holds both arrays' tiles, nb each);
+// blocks 2 nb and 2 nb + 1 ... are not used: the totals come from the last
+// tile of each array.
+__global__ void k_scan_add2(int32_t* out0, int32_t* out1, int64_t n, const int32_t* sums_scan,
+                            const int32_t* sums, int32_t* total0, int32_t* total1)
+{
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    const bool second = blockIdx.x >= nb;
+    const int64_t blk = second ? blockIdx.x - nb : blockIdx.x;
+    int32_t* out = second ? out1 : out0;
+    // exclusive prefix of this array's tiles = scan of all tiles minus the
+    // first array's total for the second array
+    const int32_t first_total = sums_scan[nb - 1] + sums[nb - 1];
+    const int32_t add = sums_scan[blockIdx.x] - (second ? first_total : 0);
+    const int64_t base = blk * SCAN_TILE;
+    for (int k = threadIdx.x; k < SCAN_TILE; k += blockDim.x)
+        if (base + k < n)
+            out[base + k] += add;
+    if (threadIdx.x == 0 && blk == nb - 1) {
+        const int32_t tot = sums_scan[blockIdx.x] + sums[blockIdx.x] - (second ? first_total : 0);
+        if (second) {
+            if (total1)
+                *total1 = tot;
+        } else if (total0) {
+            *total0 = tot;
+        }
+    }
+}
+
+size_t scan2_workspace(int64_t n)
+{
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    return 2 * align_up(sizeof(int32_t) * 2 * (nb > 0 ? nb : 1)) + scan_workspace(2 * nb);
+}
+
+void scan_exclusive2(const int32_t* in0, int32_t* out0, const int32_t* in1, int32_t* out1,
+                     int64_t n, int32_t* total0, int32_t* total1, void* ws, hipStream_t st)
+{
+    if (n <= 0) {
+        if (total0)
+            k_set1<<<1, 1, 0, st>>>(total0, 0);
+        if (total1)
+            k_set1<<<1, 1, 0, st>>>(total1, 0);
+        return;
+    }
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    int32_t* sums = (int32_t*)ws;
+    int32_t* sscan = (int32_t*)((char*)ws + align_up(sizeof(int32_t) * 2 * nb));
+    void* rest = (char*)ws + 2 * align_up(sizeof(int32_t) * 2 * nb);
+    k_scan_tile2<<<(unsigned)(2 * nb), SCAN_THREADS, 0, st>>>(in0, out0, in1, out1, n, sums);
+    scan_exclusive(sums, sscan, 2 * nb, nullptr, rest, st, 0);
+    k_scan_add2<<<(unsigned)(2 * nb), SCAN_THREADS, 0, st>>>(out0, out1, n, sscan, sums, total0,
+                                                             total1);
+}
+
 // ------------------------------------------------------------------ radix sort
 
 constexpr int RS_THREADS = 256;

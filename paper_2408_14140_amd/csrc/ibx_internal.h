@@ -183,6 +183,12 @@ size_t scan_workspace(int64_t n);
 void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* total, void* ws,
                     hipStream_t st, int shift = 0);
 
+// Exclusive scans of two int32 arrays of the same length (outputs may alias
+// inputs); totals (device, nullable).  Workspace bytes from scan2_workspace(n).
+size_t scan2_workspace(int64_t n);
+void scan_exclusive2(const int32_t* in0, int32_t* out0, const int32_t* in1, int32_t* out1,
+                     int64_t n, int32_t* total0, int32_t* total1, void* ws, hipStream_t st);
+
 // Stable LSD radix sort of (key, val) int32 pairs on the low `bits` bits of
 // the key.  n_dev (device, nullable) holds the live count <= n_max.  Result
 // is left in (keys, vals); (tk, tv) are scratch of n_max entries.

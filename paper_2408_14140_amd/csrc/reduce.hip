@@ -20,7 +20,7 @@ namespace ibx {
 
 constexpr int RD_THREADS = 256;
 constexpr int RD_WAVES = RD_THREADS / 64;
-constexpr int RD_SLABS = 8;
+constexpr int RD_SLABS = 4;
 constexpr int RD_QCAP = 512;               // per-wavefront queue capacity (cells)
 constexpr int RD_TAB = 256;                // bounding-box cells per axis held in LDS tables
 
