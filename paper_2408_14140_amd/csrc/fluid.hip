@@ -229,7 +229,7 @@ __device__ inline T grad_node(const T* __restrict__ p, const Idx& I, int i, int 
     return (T(0.25) * hi - T(0.25) * lo) * inv_h;
 }
 
-// rhs of Eq. (31) for every cell, as complex numbers: r[c][cell]
+// rhs of Eq. (31) for every cell, paired into two complex planes
 template <typename T>
 __global__ void k_predict_rhs(int n, T h, T rho, T a, T dt, T g0, T g1, T g2,
                               const T* __restrict__ u, const T* __restrict__ p,
@@ -268,17 +268,24 @@ __global__ void k_predict_rhs(int n, T h, T rho, T a, T dt, T g0, T g1, T g2,
             lap[c] += (up[c] - T(2) * uc[c] + um[c]) * inv_h2;
         }
     }
+    T rv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const T gp = grad_node(p, I, i, j, k, c, inv_h);
-        Cx<T> v;
-        v.x = uc[c] - dt * conv[c] - (dt / rho) * gp + a * lap[c] + dt * g[c];
-        v.y = T(0);
-        r[c * N + q] = v;
+        rv[c] = uc[c] - dt * conv[c] - (dt / rho) * gp + a * lap[c] + dt * g[c];
     }
+    // the solve's operator is real, so two real fields share one complex
+    // transform: plane 0 holds x + i y, plane 1 holds z
+    Cx<T> v0, v1;
+    v0.x = rv[0];
+    v0.y = rv[1];
+    v1.x = rv[2];
+    v1.y = T(0);
+    r[q] = v0;
+    r[N + q] = v1;
 }
 
-// r^[c][k] /= 1 - a lam(k), lam the 7-point eigenvalue of mode k
+// r^[c][k] /= 1 - a lam(k) on both planes, lam the 7-point eigenvalue of mode k
 template <typename T>
 __global__ void k_helmholtz_scale(int n, double h, double a, Cx<T>* __restrict__ r)
 {
@@ -293,12 +300,25 @@ __global__ void k_helmholtz_scale(int n, double h, double a, Cx<T>* __restrict__
         lam += (2.0 * cospi(2.0 * (double)kk[d] / (double)n) - 2.0) / (h * h);
     const T f = (T)(1.0 / (1.0 - a * lam));
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 2; ++c) {
         Cx<T> v = r[c * N + q];
         v.x *= f;
         v.y *= f;
         r[c * N + q] = v;
     }
+}
+
+// the three velocity components back from the two planes
+template <typename T>
+__global__ void k_unpair(int64_t N, const Cx<T>* __restrict__ r, T* __restrict__ out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N)
+        return;
+    const Cx<T> v0 = r[q], v1 = r[N + q];
+    out[q] = v0.x;
+    out[N + q] = v0.y;
+    out[2 * N + q] = v1.x;
 }
 
 template <typename T>
@@ -471,7 +491,7 @@ static int log2_exact(int32_t n)
 
 template <typename T>
 struct FluidWs {
-    Cx<T>* r;      // [3][N] complex
+    Cx<T>* r;      // [2][N] complex
     T* V;          // [3][N]
     Cx<T>* W;      // [n/2] twiddles
 };
@@ -482,7 +502,7 @@ static FluidWs<T> carve_fluid(int32_t n, void* ws, size_t bytes, size_t* need)
     Carver cv(ws, bytes);
     const size_t N = (size_t)n * n * n;
     FluidWs<T> w;
-    w.r = cv.take<Cx<T>>(3 * N);
+    w.r = cv.take<Cx<T>>(2 * N);
     w.V = cv.take<T>(3 * N);
     w.W = cv.take<Cx<T>>(n / 2 > 0 ? n / 2 : 1);
     *need = cv.used;
@@ -505,12 +525,12 @@ static int predict_t(int32_t n, double h, double rho, double mu, double dt, cons
     k_twiddles<T><<<(unsigned)((n / 2 + 255) / 256), 256, 0, st>>>(n, w.W);
     k_predict_rhs<T><<<gc, 256, 0, st>>>(n, (T)h, (T)rho, (T)a, (T)dt, (T)grav[0], (T)grav[1],
                                          (T)grav[2], u, p, w.r);
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 2; ++c)
         fft3<T>(w.r + c * N, n, logn, w.W, false, st);
     k_helmholtz_scale<T><<<gc, 256, 0, st>>>(n, h, a, w.r);
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 2; ++c)
         fft3<T>(w.r + c * N, n, logn, w.W, true, st);
-    k_real_part<T><<<(unsigned)((3 * N + 255) / 256), 256, 0, st>>>(3 * N, w.r, ustar);
+    k_unpair<T><<<gc, 256, 0, st>>>(N, w.r, ustar);
     return launch_status();
 }
 
