@@ -512,20 +512,21 @@ static BatchedWs<T> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, s
 template <typename T, int P, int MODE>
 static void launch_interp(const BatchedCfg& cfg, hipStream_t st, const Grid& g, int64_t nl,
                           double dt, const Item* items, const int32_t* nitems, const T* u0,
-                          const T* G, const int64_t* nbase, const MarkerData<T>& s, double* e2)
+                          const T* G, const int64_t* nbase, const MarkerData<T>& s, double* e2,
+                          T* Fout = nullptr, const int32_t* perm = nullptr)
 {
     if (cfg.bw == 64)
         k_interp_tiles<T, P, MODE, 64>
             <<<resident_grid<k_interp_tiles<T, P, MODE, 64>, 64>(cfg.ncu, 0), 64, 0, st>>>(
-                g, nl, dt, items, nitems, u0, G, nbase, s, e2);
+                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm);
     else if (cfg.bw == 128)
         k_interp_tiles<T, P, MODE, 128>
             <<<resident_grid<k_interp_tiles<T, P, MODE, 128>, 128>(cfg.ncu, 0), 128, 0, st>>>(
-                g, nl, dt, items, nitems, u0, G, nbase, s, e2);
+                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm);
     else
         k_interp_tiles<T, P, MODE, 256>
             <<<resident_grid<k_interp_tiles<T, P, MODE, 256>, 256>(cfg.ncu, 0), 256, 0, st>>>(
-                g, nl, dt, items, nitems, u0, G, nbase, s, e2);
+                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm);
 }
 
 #define IBX_PROF_BEGIN(k) \
@@ -578,7 +579,9 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     IBX_PROF_END();
     double* e2 = resid ? w.e2 : nullptr;
     IBX_PROF_BEGIN(PK_INTERP_U0);
-    launch_interp<T, P, 0>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_u, w.s, e2);
+    // the last interpolation of the loop also writes F in marker order
+    launch_interp<T, P, 0>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_u, w.s, e2,
+                           ns == 1 ? F : nullptr, b->perm);
     IBX_PROF_END();
     if (resid)
         sum_to(w.e2, nl, w.part, resid + 0, true, st);
@@ -597,7 +600,8 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
                 w.sorder, w.active, w.nactive, b->src_offs, b->src_idx, g, w.s, w.G);
         IBX_PROF_END();
         IBX_PROF_BEGIN(PK_INTERP_G);
-        launch_interp<T, P, 1>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_g, w.s, e2);
+        launch_interp<T, P, 1>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_g, w.s, e2,
+                               mi == ns ? F : nullptr, b->perm);
         IBX_PROF_END();
         if (resid)
             sum_to(w.e2, nl, w.part, resid + (mi - 1), true, st);
@@ -620,9 +624,6 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         IBX_PROF_END();
         sum_to(w.e2, nl, w.part, resid + ns, true, st);
     }
-    IBX_PROF_BEGIN(PK_UNSORT);
-    k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.f4, F);
-    IBX_PROF_END();
     return launch_status();
 }
 

@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(BW)
 k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                const int32_t* __restrict__ nitems, const T* __restrict__ u0,
                const T* __restrict__ G, const int64_t* __restrict__ nbase, MarkerData<T> s,
-               double* __restrict__ e2)
+               double* __restrict__ e2, T* __restrict__ Fout, const int32_t* __restrict__ perm)
 {
     constexpr int gh = Halo<P>::g, R = Halo<P>::R;
     // LDS holds the halo as rows [c][jz][jy] of pitch RP = 12 with halo x
@@ -317,17 +317,22 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                 }
             }
             if (MODE == 0) {
-                typename Vec4<T>::type o;
-                o.x = nf[0];
-                o.y = nf[1];
-                o.z = nf[2];
-                o.w = T(0);
-                s.f4[i] = o;
+                fv.x = nf[0];
+                fv.y = nf[1];
+                fv.z = nf[2];
+                fv.w = T(0);
+                s.f4[i] = fv;
             } else if (MODE == 1) {
                 fv.x += nf[0];
                 fv.y += nf[1];
                 fv.z += nf[2];
                 s.f4[i] = fv;
+            }
+            if (MODE != 2 && Fout) {            // the last F, straight to marker order
+                const int64_t l = perm[i];
+                Fout[3 * l + 0] = fv.x;
+                Fout[3 * l + 1] = fv.y;
+                Fout[3 * l + 2] = fv.z;
             }
             if (e2)
                 e2[i] = (double)rs * h3 * err;
