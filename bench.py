@@ -52,13 +52,14 @@ def model_bytes(kind, s, P, N, S, A, C, ncov):
 
     N markers, S source-list entries, A active tiles (512 cells each), C
     support cells, ncov cells of the covered boxes, s field bytes.  Marker
-    records: stencil base 12 B, weights 3P*s, dV/h^3 s, U^d / D / F 3s each.
-    The loop runs in place (u* overwrites u0)."""
-    rec = 12 + 3 * P * s
+    records: packed stencil base 8 B, the three offsets from the stencil's
+    first cell and dV/h^3 4s (the weights are formed from the offsets);
+    U^d / D / F 3s each.  The loop runs in place (u* overwrites u0)."""
+    rec = 8 + 4 * s
     if kind == "interp_u0":
         return 3 * s * C + N * (rec + 3 * s + 6 * s)
     if kind in ("spread", "spread_final"):
-        return N * (rec + s + 3 * s) + 4 * S + 3 * s * 512 * A
+        return N * (rec + 3 * s) + 4 * S + 3 * s * 512 * A
     if kind == "interp_g":
         return 3 * s * 512 * A + N * (rec + 3 * s + 3 * s + 3 * s)
     if kind == "fill":

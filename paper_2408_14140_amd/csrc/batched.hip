@@ -64,17 +64,59 @@ struct Vec4<double> {
     using type = double4;
 };
 
-// Stencil record of one marker (sorted order).
-template <typename T>
-struct alignas(sizeof(T) == 4 ? 64 : 128) Geo {
-    T w[3][4];        // kernel weights per axis (first P used)
-    T rs;             // dV / h^3
-    int32_t rb[3];    // stencil base, owning-tile frame: wrapped owning cell + (b - floor(s))
-};
+// Stencil record of one marker (sorted order), read by every work item
+// that the marker touches: geo = (r_x, r_y, r_z, dV/h^3) with r_a the offset
+// s_a - b_a - 1/2 of the grid coordinate from the stencil's first cell
+// centre (the weights follow from it, axis_weights_r), and the stencil base
+// in the owning-tile frame (wrapped owning cell + (b - floor(s))) packed in
+// 21-bit fields, each biased by RB_BIAS.
+constexpr int RB_BITS = 21, RB_BIAS = 4;
+constexpr int64_t RB_MASK = (int64_t(1) << RB_BITS) - 1;
+
+__device__ inline void unpack_rb(int64_t v, int* rb)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        rb[a] = (int)((v >> (RB_BITS * a)) & RB_MASK) - RB_BIAS;
+}
+
+// The P weights of one axis from r = s - b - 1/2.  With d = r - 1 the
+// distances to the P stencil points are 1 + d, |d|, 1 - d (and 2 - d), each
+// on a fixed branch of the kernel, and all branches share one square root.
+// P = 4: r in [1, 2), phi = (3 - 2|x| + q)/8 or (5 - 2|x| - q')/8 with
+// q^2 = 1 + 4d - 4d^2; P = 3: r in [1/2, 3/2), q^2 = 1 - 3d^2.
+__device__ inline float root(float x)
+{
+    return __builtin_amdgcn_sqrtf(x);   // the hardware square root (1 ulp), x in [1/4, 2]
+}
+
+__device__ inline double root(double x)
+{
+    return sqrt(x);
+}
+
+template <typename T, int P>
+__device__ inline void axis_weights_r(T r, T* w)
+{
+    const T d = r - T(1);
+    if (P == 4) {
+        const T q = root(T(1) + T(4) * d * (T(1) - d));
+        w[0] = (T(3) - T(2) * d - q) * T(0.125);
+        w[1] = (T(3) - T(2) * d + q) * T(0.125);
+        w[2] = (T(1) + T(2) * d + q) * T(0.125);
+        w[3] = (T(1) + T(2) * d - q) * T(0.125);
+    } else {
+        const T q = root(T(1) - T(3) * d * d);
+        w[0] = (T(2) - T(3) * d - q) * T(1.0 / 6.0);
+        w[1] = (T(1) + q) * T(1.0 / 3.0);
+        w[P - 1] = (T(2) + T(3) * d - q) * T(1.0 / 6.0);
+    }
+}
 
 template <typename T>
 struct MarkerData {
-    Geo<T>* geo;                      // [n]
+    typename Vec4<T>::type* geo;      // [n] (r_x, r_y, r_z, dV/h^3)
+    int64_t* rb;                      // [n] packed stencil base
     typename Vec4<T>::type* f4;       // [n] F^m (x, y, z, 0)
     T* ud;                            // [3][n] U^d
     T* d;                             // [3][n] D = (U^d - J u0)/dt
@@ -116,12 +158,13 @@ k_prep(Grid g, int64_t nl, const double* __restrict__ x, const double* __restric
         return;
     const int64_t l = perm[i];
     const double X[3] = {x[l], y[l], z[l]};
-    Geo<T> r;
+    T r[3];
+    int64_t pk = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double sa = grid_coord(g, a, X[a]);
-        T w[P];
-        const int b = axis_weights<T, P>(sa, w);
+        const int b = stencil_base<P>(sa);
+        r[a] = (T)(sa - (double)b - 0.5);
         const int fl = (int)floor(sa);
         int c = fl;
         if (g.periodic[a]) {
@@ -130,14 +173,16 @@ k_prep(Grid g, int64_t nl, const double* __restrict__ x, const double* __restric
             if ((unsigned)c >= (unsigned)g.n[a])
                 c = wrapi(fl, g.n[a]);
         }
-        r.rb[a] = c + (b - fl);
-#pragma unroll
-        for (int o = 0; o < 4; ++o)
-            r.w[a][o] = o < P ? w[o] : T(0);
+        pk |= (int64_t)(c + (b - fl) + RB_BIAS) << (RB_BITS * a);
     }
     const int p = pid[l];
-    r.rs = (T)(dv[p] * g.inv_h3);
-    s.geo[i] = r;
+    typename Vec4<T>::type q;
+    q.x = r[0];
+    q.y = r[1];
+    q.z = r[2];
+    q.w = (T)(dv[p] * g.inv_h3);
+    s.geo[i] = q;
+    s.rb[i] = pk;
     const double R0 = X[0] - xc[3 * p], R1 = X[1] - xc[3 * p + 1], R2 = X[2] - xc[3 * p + 2];
     const double w0 = om[3 * p], w1 = om[3 * p + 1], w2 = om[3 * p + 2];
     s.ud[0 * nl + i] = (T)(up[3 * p + 0] + (w1 * R2 - w2 * R1));
@@ -233,7 +278,7 @@ k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
              const int32_t* __restrict__ src_offs, const int32_t* __restrict__ item_offs,
              const int32_t* __restrict__ act_offs, const int32_t* __restrict__ nactive,
              Item* items, int32_t* active, int32_t* slot, int32_t* __restrict__ cur,
-             int32_t* __restrict__ sorder)
+             int4* __restrict__ sent)
 {
     __shared__ int32_t lc[NXCD * COST_BINS];
     __shared__ int32_t base[NXCD * COST_BINS];
@@ -242,7 +287,7 @@ k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
     __syncthreads();
     const int n_act = *nactive;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int bin = -1, rank = 0;
+    int bin = -1, rank = 0, s0 = 0, s1 = 0;
     if (t < T) {
         const int start = tile_offs[t];
         const int cnt = tile_offs[t + 1] - start;
@@ -255,7 +300,9 @@ k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
             it.pad = 0;
             items[io + k] = it;
         }
-        const int c = src_offs[t + 1] - src_offs[t];
+        s0 = src_offs[t];
+        s1 = src_offs[t + 1];
+        const int c = s1 - s0;
         if (c > 0) {
             const int a = act_offs[t];
             active[a] = (int32_t)t;
@@ -272,7 +319,7 @@ k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
             base[b] = atomicAdd(&cur[b], lc[b]);
     __syncthreads();
     if (bin >= 0)
-        sorder[base[bin] + rank] = act_offs[t];
+        sent[base[bin] + rank] = make_int4(act_offs[t], (int)t, s0, s1);
 }
 
 
@@ -421,7 +468,11 @@ static void launch_finalize(unsigned grid, hipStream_t st, const Grid& g, const 
                             const T* G, const T* u0, T* ustar, T* f, double dt, int use_g,
                             int f_acc)
 {
-    if ((g.ngrow & 1) == 0) {
+    // pairs of cells: rows start on even elements when ngrow is even, and the
+    // pair loads and stores need the fields aligned to two elements
+    const uintptr_t am = 2 * sizeof(T) - 1;
+    if ((g.ngrow & 1) == 0 && !((uintptr_t)u0 & am) && !((uintptr_t)ustar & am) &&
+        !((uintptr_t)f & am)) {
         const int64_t items = (int64_t)g.nbox * (g.box / TILE) * (g.box / 2);
         const unsigned gp = (unsigned)(items < 65535 ? (items > 0 ? items : 1) : 65535);
         if (f_acc)
@@ -467,7 +518,8 @@ struct BatchedWs {
     double* part;
     Item* items;
     int32_t *item_cnt, *item_offs, *act, *act_offs, *active, *slot, *nitems, *nactive;
-    int32_t *hist, *cur, *sorder;   // spreading order by decreasing cost
+    int32_t *hist, *cur;
+    int4* sent;     // spreading order by decreasing cost: (slot, tile, sources begin, end)
     T* G;
     void* scan;
     int64_t max_items;
@@ -481,7 +533,8 @@ static BatchedWs<T> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, s
     Carver cv(ws, bytes);
     BatchedWs<T> w;
     const int64_t T_ = g.ntiles;
-    w.s.geo = cv.take<Geo<T>>(nl);
+    w.s.geo = cv.take<typename Vec4<T>::type>(nl);
+    w.s.rb = cv.take<int64_t>(nl);
     w.s.f4 = cv.take<typename Vec4<T>::type>(nl);
     w.s.ud = cv.take<T>(3 * nl);
     w.s.d = cv.take<T>(3 * nl);
@@ -495,7 +548,7 @@ static BatchedWs<T> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, s
     w.act_offs = cv.take<int32_t>(T_);
     w.hist = cv.take<int32_t>(NXCD * COST_BINS);
     w.cur = cv.take<int32_t>(NXCD * COST_BINS);
-    w.sorder = cv.take<int32_t>(T_);
+    w.sent = cv.take<int4>(T_);
     w.active = cv.take<int32_t>(T_);
     w.slot = cv.take<int32_t>(T_);
     w.nitems = cv.take<int32_t>(1);
@@ -570,7 +623,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     k_bin_scan<<<NXCD, COST_BINS, 0, st>>>(w.hist, w.nactive, w.cur);
     k_fill_lists<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs,
                                      w.act_offs, w.nactive, w.items, w.active, w.slot, w.cur,
-                                     w.sorder);
+                                     w.sent);
     {
         const int64_t nth = 27 * w.max_items;
         k_item_bases<<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(g, w.items, w.nitems, w.slot,
@@ -597,7 +650,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         IBX_PROF_BEGIN(PK_SPREAD);
         k_spread_tiles<T, P>
             <<<resident_grid<k_spread_tiles<T, P>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
-                w.sorder, w.active, w.nactive, b->src_offs, b->src_idx, g, w.s, w.G);
+                w.sent, w.nactive, b->src_idx, g, w.s, w.G);
         IBX_PROF_END();
         IBX_PROF_BEGIN(PK_INTERP_G);
         launch_interp<T, P, 1>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_g, w.s, e2,
@@ -612,7 +665,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     IBX_PROF_BEGIN(PK_SPREAD_FINAL);
     k_spread_tiles<T, P>
         <<<resident_grid<k_spread_tiles<T, P>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
-            w.sorder, w.active, w.nactive, b->src_offs, b->src_idx, g, w.s, w.G);
+            w.sent, w.nactive, b->src_idx, g, w.s, w.G);
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_FILL);
     launch_finalize<T>(gfin, st, g, w.slot, w.G, u0, ustar, f, dt, 1, f_acc);
@@ -642,9 +695,11 @@ int batched_multidirect(const Grid& g, int P, ib_prec prec, const BatchedCfg& cf
                         double dt, const void* u0, void* ustar, void* f, void* F, double* resid,
                         void* Fhist, void* ws, size_t ws_bytes, hipStream_t st, int f_acc)
 {
-    // a stencil must never reach the same tile from both sides of a periodic axis
-    if (g.n[0] < 2 * TILE || g.n[1] < 2 * TILE || g.n[2] < 2 * TILE)
-        return IB_EUNSUPPORTED;
+    // a stencil must never reach the same tile from both sides of a periodic
+    // axis; every stencil base (>= -2, < n) fits a packed field
+    for (int a = 0; a < 3; ++a)
+        if (g.n[a] < 2 * TILE || g.n[a] > (int)RB_MASK - RB_BIAS)
+            return IB_EUNSUPPORTED;
     // the finalize step holds one box row of tile slots in LDS
     if (g.box > 64 * TILE)
         return IB_EUNSUPPORTED;

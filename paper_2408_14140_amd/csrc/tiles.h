@@ -139,15 +139,16 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
         typename Vec4<T>::type fv;
         fv.x = fv.y = fv.z = fv.w = T(0);
         if (mine) {
-            const Geo<T> gm = s.geo[i];
+            const typename Vec4<T>::type gq = s.geo[i];
+            int rb[3];
+            unpack_rb(s.rb[i], rb);
+            axis_weights_r<T, P>(gq.x, w[0]);
+            axis_weights_r<T, P>(gq.y, w[1]);
+            axis_weights_r<T, P>(gq.z, w[2]);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                lb[a] = gm.rb[a] - lo[a] + gh;
-#pragma unroll
-                for (int o = 0; o < P; ++o)
-                    w[a][o] = gm.w[a][o];
-            }
-            rs = gm.rs;
+            for (int a = 0; a < 3; ++a)
+                lb[a] = rb[a] - lo[a] + gh;
+            rs = gq.w;
             if (sub == 0) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -387,7 +388,7 @@ __device__ inline int wave_exclusive_sum(int v)
 }
 
 // One wavefront per workgroup; the tile is stored to its G slot.  The
-// workgroups of XCD x (ids = x mod 8) take the entries of slab x of `order`
+// workgroups of XCD x (ids = x mod 8) take the entries of slab x of `sent`
 // (the x-th of 8 equal cuts, each by decreasing cost) dealt in a snake: with
 // W workgroups on the XCD, round r gives its w-th workgroup entry r W + w
 // (r even) or r W + W - 1 - w (r odd) of the slab.
@@ -405,10 +406,9 @@ __device__ inline int wave_exclusive_sum(int v)
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8)))
-k_spread_tiles(const int32_t* __restrict__ order, const int32_t* __restrict__ active,
-               const int32_t* __restrict__ nactive,
-               const int32_t* __restrict__ src_offs, const int32_t* __restrict__ src_idx,
-               Grid g, MarkerData<T> s, T* __restrict__ G)
+k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactive,
+               const int32_t* __restrict__ src_idx, Grid g, MarkerData<T> s,
+               T* __restrict__ G)
 {
     constexpr int NW = TILE + 2 * P + 3;                   // staged values per source
     constexpr int NBUF = NW * 64;
@@ -445,26 +445,32 @@ k_spread_tiles(const int32_t* __restrict__ order, const int32_t* __restrict__ ac
         const int idx = x * per + r * nwg + ((r & 1) ? nwg - 1 - wg : wg);
         if (idx >= s_end)
             break;
-        const int a = order[idx];
-        const int t = active[a];
+        const int4 ent = sent[idx];     // (slot, tile, first source, end of sources)
+        const int a = ent.x;
         int lo[3];
-        tile_coords(g, t, lo);
+        tile_coords(g, ent.y, lo);
         T acc[TILE][3];
 #pragma unroll
         for (int xx = 0; xx < TILE; ++xx)
             acc[xx][0] = acc[xx][1] = acc[xx][2] = T(0);
-        const int s0 = src_offs[t], s1 = src_offs[t + 1];
+        const int s0 = ent.z, s1 = ent.w;
         for (int sbat = s0; sbat < s1; sbat += 64) {
             const int sidx = sbat + lane;
             int by = 64, bz = 64;       // no row for lanes past the list
             if (sidx < s1) {
                 const int64_t i = src_idx[sidx];
-                const Geo<T> gm = s.geo[i];
+                const typename Vec4<T>::type gq = s.geo[i];
                 const typename Vec4<T>::type Fv = s.f4[i];
+                int rb[3];
+                unpack_rb(s.rb[i], rb);
+                T gw[3][P];
+                axis_weights_r<T, P>(gq.x, gw[0]);
+                axis_weights_r<T, P>(gq.y, gw[1]);
+                axis_weights_r<T, P>(gq.z, gw[2]);
                 int b[3];
 #pragma unroll
                 for (int ax = 0; ax < 3; ++ax) {
-                    int v = gm.rb[ax] - lo[ax];
+                    int v = rb[ax] - lo[ax];
                     if (v < -(P - 1)) v += g.n[ax];
                     else if (v > TILE - 1) v -= g.n[ax];
                     b[ax] = v;
@@ -476,18 +482,18 @@ k_spread_tiles(const int32_t* __restrict__ order, const int32_t* __restrict__ ac
                     T wv = T(0);
 #pragma unroll
                     for (int o = 0; o < P; ++o)
-                        wv = (xx - b[0] == o) ? gm.w[0][o] : wv;
+                        wv = (xx - b[0] == o) ? gw[0][o] : wv;
                     sx[xx * 64 + lane] = wv;
                 }
 #pragma unroll
                 for (int o = 0; o < P; ++o) {
-                    sy[o * 64 + lane] = gm.w[1][o];
-                    sz[o * 64 + lane] = gm.w[2][o];
+                    sy[o * 64 + lane] = gw[1][o];
+                    sz[o * 64 + lane] = gw[2][o];
                 }
                 sb[lane] = (by + 8) | ((bz + 8) << 8);
-                sf[0 * 64 + lane] = Fv.x * gm.rs;
-                sf[1 * 64 + lane] = Fv.y * gm.rs;
-                sf[2 * 64 + lane] = Fv.z * gm.rs;
+                sf[0 * 64 + lane] = Fv.x * gq.w;
+                sf[1 * 64 + lane] = Fv.y * gq.w;
+                sf[2 * 64 + lane] = Fv.z * gq.w;
             }
             uint64_t my = 0, mz = 0;
 #pragma unroll
