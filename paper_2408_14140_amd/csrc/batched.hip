@@ -100,16 +100,18 @@ __device__ inline void axis_weights_r(T r, T* w)
 {
     const T d = r - T(1);
     if (P == 4) {
-        const T q = root(T(1) + T(4) * d * (T(1) - d));
-        w[0] = (T(3) - T(2) * d - q) * T(0.125);
-        w[1] = (T(3) - T(2) * d + q) * T(0.125);
-        w[2] = (T(1) + T(2) * d + q) * T(0.125);
-        w[3] = (T(1) + T(2) * d - q) * T(0.125);
+        const T q = root(T(1) + T(4) * d * (T(1) - d)) * T(0.125);
+        const T a = T(0.375) - T(0.25) * d, b = T(0.125) + T(0.25) * d;
+        w[0] = a - q;
+        w[1] = a + q;
+        w[2] = b + q;
+        w[3] = b - q;
     } else {
         const T q = root(T(1) - T(3) * d * d);
-        w[0] = (T(2) - T(3) * d - q) * T(1.0 / 6.0);
-        w[1] = (T(1) + q) * T(1.0 / 3.0);
-        w[P - 1] = (T(2) + T(3) * d - q) * T(1.0 / 6.0);
+        const T q6 = q * T(1.0 / 6.0);
+        w[0] = T(1.0 / 3.0) - T(0.5) * d - q6;
+        w[1] = T(1.0 / 3.0) + T(1.0 / 3.0) * q;
+        w[P - 1] = T(1.0 / 3.0) + T(0.5) * d - q6;
     }
 }
 

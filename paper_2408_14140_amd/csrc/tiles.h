@@ -414,7 +414,8 @@ k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactiv
     constexpr int NBUF = NW * 64;
     constexpr int MAXP = NBUF / (3 * TILE) < 64 ? NBUF / (3 * TILE) : 64;   // phase-B pieces
     __shared__ T buf[NBUF];
-    __shared__ int32_t sb[64];          // stencil's first row: (by + 8) | (bz + 8) << 8
+    __shared__ int2 sb[64];             // k - 64 by, k - 64 bz: tile row r (covered by the
+                                        // stencil) reads sy[64 r + .x], sz[64 r + .y]
     T* const sx = buf;                  // [TILE][64] x weight of tile cell x
     T* const sy = buf + TILE * 64;      // [P][64]    y weights
     T* const sz = sy + P * 64;          // [P][64]    z weights
@@ -423,9 +424,8 @@ k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactiv
     __shared__ int32_t piece[MAXP];     // phase-B slot -> row | piece << 8
     // add source k's contribution to the 8 cells of row (y, z)
     auto visit = [&](T (&a)[TILE][3], int y, int z, int k) {
-        const int bb = sb[k];
-        const int dy = y + 8 - (bb & 255), dz = z + 8 - (bb >> 8);
-        const T wyz = sy[dy * 64 + k] * sz[dz * 64 + k];
+        const int2 bb = sb[k];
+        const T wyz = sy[y * 64 + bb.x] * sz[z * 64 + bb.y];
         const T c0 = sf[k] * wyz, c1 = sf[64 + k] * wyz, c2 = sf[128 + k] * wyz;
 #pragma unroll
         for (int x = 0; x < TILE; ++x) {
@@ -477,20 +477,20 @@ k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactiv
                 }
                 by = b[1];
                 bz = b[2];
+                // x weights: zeros, then the P weights at the stencil's offset
 #pragma unroll
-                for (int xx = 0; xx < TILE; ++xx) {
-                    T wv = T(0);
+                for (int xx = 0; xx < TILE; ++xx)
+                    sx[xx * 64 + lane] = T(0);
 #pragma unroll
-                    for (int o = 0; o < P; ++o)
-                        wv = (xx - b[0] == o) ? gw[0][o] : wv;
-                    sx[xx * 64 + lane] = wv;
-                }
+                for (int o = 0; o < P; ++o)
+                    if ((unsigned)(b[0] + o) < (unsigned)TILE)
+                        sx[(b[0] + o) * 64 + lane] = gw[0][o];
 #pragma unroll
                 for (int o = 0; o < P; ++o) {
                     sy[o * 64 + lane] = gw[1][o];
                     sz[o * 64 + lane] = gw[2][o];
                 }
-                sb[lane] = (by + 8) | ((bz + 8) << 8);
+                sb[lane] = make_int2(lane - 64 * by, lane - 64 * bz);
                 sf[0 * 64 + lane] = Fv.x * gq.w;
                 sf[1 * 64 + lane] = Fv.y * gq.w;
                 sf[2 * 64 + lane] = Fv.z * gq.w;
@@ -511,18 +511,14 @@ k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactiv
             uint64_t M = my & mz;
             const int n = __popcll(M);
             const int nmax = wave_max(n);
+            // 64 K + MAXP K >= the batch's visits bounds K from below; the
+            // cap rarely lies more than a few steps above that bound, so it
+            // is searched upwards from there.
             int K = nmax;
             if (nmax > 1) {
-                int lo_k = 1, hi_k = nmax;
-                while (lo_k < hi_k) {
-                    const int mid = (lo_k + hi_k) >> 1;
-                    const int pieces = wave_sum(n > mid ? small_div(n - 1, mid) : 0);
-                    if (pieces <= MAXP)
-                        hi_k = mid;
-                    else
-                        lo_k = mid + 1;
-                }
-                K = lo_k;
+                K = max(1, (wave_sum(n) + 63 + MAXP) / (64 + MAXP));
+                while (K < nmax && wave_sum(n > K ? small_div(n - 1, K) : 0) > MAXP)
+                    ++K;
             }
             for (int tt = 0; tt < K && M; ++tt) {
                 const int k = __builtin_ctzll(M);
