@@ -114,8 +114,8 @@ def main():
     if "--gpus" in sys.argv:
         i = sys.argv.index("--gpus")
         if i + 1 < len(sys.argv) and sys.argv[i + 1] != "1":
-            print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-                  "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+            print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+                  "(the measured figure is one GPU's share of the workload)", file=sys.stderr)
             sys.exit(2)
     import torch
     torch.cuda.set_device(0)
@@ -329,7 +329,8 @@ def run():
     copy_gbs = copy_probe(1024, 10)
     log(f"cold loop {ms_cold:.3f} ms, copy {copy_gbs:.0f} GB/s")
 
-    # SURVEY-style loop byte model: per iteration u0 on C + 60 B per marker, plus final writes
+    # byte model of the literal loop: per iteration u0 read on the support C and
+    # 60 B per marker, plus the final writes of u* and f on C
     bmodel = ns * (3 * 4 * C + N * 60) + 6 * 4 * C
     out = {
         "metric": "marker-iters/s of the multidirect IB step (FP32 batched)",
