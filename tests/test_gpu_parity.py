@@ -301,3 +301,64 @@ def test_autotune_keeps_parity(dev, dtype):
     with pytest.raises(ibx.IbxError):
         ibx.Plan(wl.delta, tdt, ibx.IB_PATH_PLAIN).autotune(c.dl, c.parts, c.dm, b, wl.ns,
                                                              wl.dt, u0)
+
+
+def test_batched_rejects_unsupported_levels(dev):
+    """The batched path needs at least 16 cells per axis and a stencil base
+    that fits its 21-bit packed field (n <= 2^21 - 5 per axis); beyond either
+    it returns IB_EUNSUPPORTED before any kernel runs."""
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    announce("batched path rejects unsupported levels")
+    for n, box in (((32, 32, 8), 8), ((1 << 21, 16, 16), 16)):
+        h = 1.0 / 16
+        nb = [v // box for v in n]
+        cov = np.zeros((nb[2], nb[1], nb[0]), dtype=bool)
+        cov[0, 0, 0] = True
+        lev = W.make_level(n, h, box=box, ngrow=2, covered=cov)
+        dl = ibx.device_level(lev, dev)
+        xc = np.array([[0.5 * box * h + 0.01 * h, 0.5 * box * h, 0.5 * box * h - 0.02 * h]])
+        d = np.array([0.3 * box * h])
+        parts = ibx.particles(xc, d, np.zeros((1, 3)), np.zeros((1, 3)), dev)
+        m = ibx.build_markers(dl, parts)
+        b = ibx.bucket(dl, m, 4)
+        plan = ibx.Plan(4, torch.float32, ibx.IB_PATH_BATCHED)
+        u0 = torch.zeros((lev.nbox, 3) + (box + 4,) * 3, dtype=torch.float32, device=dev)
+        with pytest.raises(ibx.IbxError) as e:
+            plan.multidirect_force(dl, parts, m, b, 2, 0.5 * h, u0)
+        assert e.value.status == ibx.IB_EUNSUPPORTED
+
+
+def test_batched_misaligned_fields(dev):
+    """Fields that start one element past an 8-byte boundary take the
+    single-cell finalize instead of the pair one: the results are the same
+    bit for bit."""
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    announce("batched path, misaligned field pointers")
+    wl = small_workload(32, 16, 4, 3, 2)
+    c = Case(wl, dev)
+    b = ibx.bucket(c.dl, c.dm, wl.delta)
+    plan = ibx.Plan(wl.delta, torch.float32, ibx.IB_PATH_BATCHED)
+    u0 = c.u0_boxes(torch.float32)
+
+    def shifted(t):
+        base = torch.full((t.numel() + 1,), float("nan"), dtype=t.dtype, device=dev)
+        v = base[1:].view(t.shape)
+        v.copy_(t)
+        assert v.data_ptr() % 8 == 4
+        return v
+
+    outs = []
+    for mis in (False, True):
+        src = shifted(u0) if mis else u0.clone()
+        ustar = shifted(torch.zeros_like(u0)) if mis else torch.zeros_like(u0)
+        f = shifted(torch.zeros_like(u0)) if mis else torch.zeros_like(u0)
+        _, _, F = plan.multidirect_force(c.dl, c.parts, c.dm, b, wl.ns, wl.dt, src, ustar=ustar,
+                                         f=f)
+        torch.cuda.synchronize()
+        outs.append((ustar.cpu().numpy(), f.cpu().numpy(), F.cpu().numpy()))
+    for a, bb in zip(outs[0], outs[1]):
+        assert np.array_equal(a, bb, equal_nan=True)
