@@ -272,14 +272,15 @@ k_bin_scan(const int32_t* __restrict__ hist, const int32_t* __restrict__ nactive
     cur[x * COST_BINS + COST_BINS - 1 - b] = x * per + v[b] - h[COST_BINS - 1 - b];
 }
 
-// Work lists: interpolation items in tile order, active tiles and their slots
-// in tile order, and the spreading order (cur[x][b] holds the first free
-// position of bin b of slab x).
+// Work lists: interpolation items in tile order, the G slot of every tile
+// (-1 when its source list is empty), and the spreading entries (slot, tile,
+// source range) in spreading order (cur[x][b] holds the first free position
+// of bin b of slab x).
 __global__ void __launch_bounds__(256)
 k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
              const int32_t* __restrict__ src_offs, const int32_t* __restrict__ item_offs,
              const int32_t* __restrict__ act_offs, const int32_t* __restrict__ nactive,
-             Item* items, int32_t* active, int32_t* slot, int32_t* __restrict__ cur,
+             Item* items, int32_t* slot, int32_t* __restrict__ cur,
              int4* __restrict__ sent)
 {
     __shared__ int32_t lc[NXCD * COST_BINS];
@@ -307,7 +308,6 @@ k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
         const int c = s1 - s0;
         if (c > 0) {
             const int a = act_offs[t];
-            active[a] = (int32_t)t;
             slot[t] = a;
             bin = slab_of(a, n_act) * COST_BINS + min(c, COST_BINS - 1);
             rank = atomicAdd(&lc[bin], 1);
@@ -519,7 +519,7 @@ struct BatchedWs {
     double* e2;
     double* part;
     Item* items;
-    int32_t *item_cnt, *item_offs, *act, *act_offs, *active, *slot, *nitems, *nactive;
+    int32_t *item_cnt, *item_offs, *act, *act_offs, *slot, *nitems, *nactive;
     int32_t *hist, *cur;
     int4* sent;     // spreading order by decreasing cost: (slot, tile, sources begin, end)
     T* G;
@@ -551,7 +551,6 @@ static BatchedWs<T> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, s
     w.hist = cv.take<int32_t>(NXCD * COST_BINS);
     w.cur = cv.take<int32_t>(NXCD * COST_BINS);
     w.sent = cv.take<int4>(T_);
-    w.active = cv.take<int32_t>(T_);
     w.slot = cv.take<int32_t>(T_);
     w.nitems = cv.take<int32_t>(1);
     w.nactive = cv.take<int32_t>(1);
@@ -624,7 +623,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     k_cost_hist<<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.hist);
     k_bin_scan<<<NXCD, COST_BINS, 0, st>>>(w.hist, w.nactive, w.cur);
     k_fill_lists<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs,
-                                     w.act_offs, w.nactive, w.items, w.active, w.slot, w.cur,
+                                     w.act_offs, w.nactive, w.items, w.slot, w.cur,
                                      w.sent);
     {
         const int64_t nth = 27 * w.max_items;
