@@ -19,8 +19,8 @@
 // to K sources of its own row, then the rest of the heavier rows is dealt out
 // in pieces of K to all lanes and added back by the row's owner in order.  No
 // atomics: each cell's sum is formed in a fixed order, so the result is
-// reproducible bit for bit.  The tile is then transposed through LDS so the
-// global stores are coalesced.
+// reproducible bit for bit.  Each lane then stores its row (8 consecutive
+// cells per component in the tile's slot) straight from registers.
 #pragma once
 
 // XCD-aware static work split.  Workgroups are dispatched to the 8 XCDs of
