@@ -430,15 +430,81 @@ __device__ inline int axis_tiles(const Grid& g, int a, int b, int* tl)
     return nt;
 }
 
+// Source lists by direction.  With at least 3 tiles on every axis the 27
+// tiles around an owning tile are distinct.  The source list of tile t is
+// then the concatenation, over its 27 neighbours t' in increasing index
+// order, of the markers owned by t' whose stencil touches t, each run in
+// sorted-position order: the same ascending list that a stable sort of the
+// (tile, position) pairs gives.  Each marker's directions are found with its
+// key, each owning tile counts its markers per direction, the runs are
+// placed by one scan over the tiles, and each owning tile writes its runs
+// with ballot ranks.
+constexpr int NDIR = 27;
+
+__device__ inline void tile_xyz(const Grid& g, int64_t t, int* c)
+{
+    const int ti = (int)t;          // tile indices fit 31 bits (cells do)
+    c[0] = ti % g.nt[0];
+    c[1] = (ti / g.nt[0]) % g.nt[1];
+    c[2] = ti / (g.nt[0] * g.nt[1]);
+}
+
+// The tile at tc + s (d): s = +1 gives the tile that a run from tc in
+// direction d reaches, s = -1 the owner of the run that tc receives from
+// direction d.  -1 past a bounded edge.
+__device__ inline int64_t dir_tile(const Grid& g, const int* tc, int d, int s)
+{
+    const int dd[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+    int oc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int v = tc[a] + s * dd[a];
+        if (v < 0 || v >= g.nt[a]) {
+            if (!g.periodic[a])
+                return -1;
+            v = v < 0 ? v + g.nt[a] : v - g.nt[a];
+        }
+        oc[a] = v;
+    }
+    return oc[0] + (int64_t)g.nt[0] * (oc[1] + (int64_t)g.nt[1] * oc[2]);
+}
+
+// The 27-bit direction set (bit (dx + 1) + 3 (dy + 1) + 9 (dz + 1)) of a
+// direction code.
+__device__ inline uint32_t dir_set(int code)
+{
+    uint32_t ax[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int k = (code >> (2 * a)) & 3;
+        ax[a] = k == 1 ? 3u : k == 2 ? 6u : 2u;     // {-1, 0}, {0, +1}, {0}
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+                if ((ax[2] >> dz) & (ax[1] >> dy) & (ax[0] >> dx) & 1)
+                    r |= 1u << (dx + 3 * dy + 9 * dz);
+    return r;
+}
+
 // Per marker: owning cell c = floor(s) (wrapped on periodic axes), its tile,
 // the unwrapped stencil base, and whether all stencil cells are covered.  The
 // sort key is the tile; with kb > 0 the number of tiles the stencil touches
-// rides above the sorted digits, at bit kb.
+// rides above the sorted digits, at bit kb.  dmask (nullable) receives the
+// directions of the touched tiles from the owning one (dir_set of the
+// direction code: per axis the owning tile's layer alone, with the layer
+// below, or with the layer above -- the owning cell is always in the stencil,
+// and with 3 or more tiles on the axis the P cells reach one neighbour layer
+// at most).
 template <int P>
 __global__ void k_bucket_keys(Grid g, int64_t nl, const double* __restrict__ x,
                               const double* __restrict__ y, const double* __restrict__ z,
                               int32_t* cell, int32_t* tileid, int32_t* base, int32_t* keys,
-                              int32_t* vals, int32_t* flag, int kb)
+                              int32_t* vals, int32_t* flag, int kb, uint32_t* dmask)
 {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= nl)
@@ -447,6 +513,7 @@ __global__ void k_bucket_keys(Grid g, int64_t nl, const double* __restrict__ x,
     int c[3], b[3];
     int bad = 0, tcount = 1;
     int bx[3][2], nbx[3];
+    int code = 0;                   // direction code, 2 bits per axis
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double s = grid_coord(g, a, X[a]);
@@ -478,6 +545,12 @@ __global__ void k_bucket_keys(Grid g, int64_t nl, const double* __restrict__ x,
             bx[a][1] = q1 / g.box;
             nbx[a] = bx[a][1] != bx[a][0] ? 2 : 1;
             tcount *= (q1 >> 3) != (q0 >> 3) ? 2 : 1;
+            // the P cells span at most two tiles, those of q0 and q1
+            const int ot = c[a] / TILE;
+            if ((q0 >> 3) != ot)
+                code |= 1 << (2 * a);
+            else if ((q1 >> 3) != ot)
+                code |= 2 << (2 * a);
         } else {
             nbx[a] = 0;
             tcount = 0;
@@ -494,6 +567,8 @@ __global__ void k_bucket_keys(Grid g, int64_t nl, const double* __restrict__ x,
     int key = t;
     if (kb > 0)
         key |= tcount << kb;
+    if (dmask)
+        dmask[l] = dir_set(code);
     keys[l] = key;
     vals[l] = (int32_t)l;
     base[3 * l + 0] = b[0];
@@ -548,6 +623,125 @@ __global__ void k_src_emit(Grid g, int64_t nl, const int32_t* perm, const int32_
         npairs[0] = (int32_t)(pos < cap ? pos : cap);
 }
 
+// cnt[t'][d]: markers owned by tile t' whose stencil touches tile t' + d;
+// tot[t' + d] += that count.  One wavefront per owning tile.
+__global__ void __launch_bounds__(64)
+k_dir_counts(Grid g, int64_t T, const int32_t* __restrict__ tile_offs,
+             const int32_t* __restrict__ perm, const uint32_t* __restrict__ dmask,
+             int32_t* __restrict__ cnt, int32_t* __restrict__ tot)
+{
+    const int lane = threadIdx.x;
+    for (int64_t t = blockIdx.x; t < T; t += gridDim.x) {
+        const int s0 = tile_offs[t], s1 = tile_offs[t + 1];
+        int mine = 0;                  // lane d < 27: count of direction d
+        for (int i0 = s0; i0 < s1; i0 += 64) {
+            const int i = i0 + lane;
+            const uint32_t m = i < s1 ? dmask[perm[i]] : 0u;
+            for (int d = 0; d < NDIR; ++d) {
+                const int c = __popcll(__ballot((m >> d) & 1));
+                if (lane == d)
+                    mine += c;
+            }
+        }
+        if (lane < NDIR) {
+            cnt[t * NDIR + lane] = mine;
+            if (mine) {
+                int tc[3];
+                tile_xyz(g, t, tc);
+                atomicAdd(&tot[dir_tile(g, tc, lane, 1)], mine);
+            }
+        }
+    }
+}
+
+__global__ void k_zero_i32(int64_t n, int32_t* __restrict__ a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        a[i] = 0;
+}
+
+// In place: cnt[t'][d] becomes the first position of that run in src_idx
+// (the runs of tile t follow src_offs[t] in increasing owner index); every
+// entry belongs to exactly one receiving tile.  One wavefront per receiving
+// tile (four per workgroup), lane d for direction d; the wavefront of t = T
+// clamps the total to the capacity
+// and raises flag[1] on overflow.  src_offs[t] is clamped likewise.
+__global__ void __launch_bounds__(256)
+k_dir_offsets(Grid g, int64_t T, int32_t* __restrict__ cnt, int32_t* __restrict__ src_offs,
+              int64_t cap, int32_t* __restrict__ flag)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t > T)
+        return;
+    const int o = src_offs[t];
+    if (t == T) {
+        if (lane == 0 && o > cap) {
+            flag[1] = 1;
+            src_offs[T] = (int32_t)cap;
+        }
+        return;
+    }
+    int tc[3];
+    tile_xyz(g, t, tc);
+    int own = -1, c = 0;
+    if (lane < NDIR) {
+        const int64_t ow = dir_tile(g, tc, lane, -1);
+        if (ow >= 0) {
+            own = (int)ow;
+            c = cnt[ow * NDIR + lane];
+        }
+    }
+    int pos = o;
+    for (int e = 0; e < NDIR; ++e) {
+        const int oe = __builtin_amdgcn_readlane(own, e);
+        const int ce = __builtin_amdgcn_readlane(c, e);
+        pos += (unsigned)oe < (unsigned)own ? ce : 0;
+    }
+    if (own >= 0)
+        cnt[(int64_t)own * NDIR + lane] = pos;
+    if (lane == 0 && o > cap)
+        src_offs[t] = (int32_t)cap;
+}
+
+// Each owning tile writes its runs: marker i goes to position first + rank in
+// every run its stencil touches (rank = earlier markers of the tile in that
+// run).  Positions past the capacity are dropped (flag[1] is raised).
+__global__ void __launch_bounds__(64)
+k_dir_emit(Grid g, int64_t T, const int32_t* __restrict__ tile_offs,
+           const int32_t* __restrict__ perm, const uint32_t* __restrict__ dmask,
+           const int32_t* __restrict__ first, int32_t* __restrict__ src_idx, int64_t cap)
+{
+    const int lane = threadIdx.x;
+    for (int64_t t = blockIdx.x; t < T; t += gridDim.x) {
+        const int s0 = tile_offs[t], s1 = tile_offs[t + 1];
+        if (s0 == s1)
+            continue;
+        int next = lane < NDIR ? first[t * NDIR + lane] : 0;   // lane d: run d's next slot
+        for (int i0 = s0; i0 < s1; i0 += 64) {
+            const int i = i0 + lane;
+            const uint32_t m = i < s1 ? dmask[perm[i]] : 0u;
+            for (int d = 0; d < NDIR; ++d) {
+                const uint64_t bd = __ballot((m >> d) & 1);
+                if (!bd)
+                    continue;
+                const int start = __builtin_amdgcn_readlane(next, d);
+                if ((m >> d) & 1) {
+                    const int64_t pos =
+                        (int64_t)start +
+                        __builtin_amdgcn_mbcnt_hi((uint32_t)(bd >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bd, 0u));
+                    if (pos < cap)
+                        src_idx[pos] = i;
+                }
+                if (lane == d)
+                    next += __popcll(bd);
+            }
+        }
+    }
+}
+
 static int key_bits(int64_t T)
 {
     int bits = 0;
@@ -558,13 +752,26 @@ static int key_bits(int64_t T)
 
 struct BucketWs {
     int32_t *keys, *tk, *tv, *cnt, *total, *npairs, *keys2, *tk2, *tv2;
-    void *rs, *scan;
+    int32_t *dcnt, *dtot;   // [T][27] run counts, then run starts; [T] list lengths
+    uint32_t* dmask;        // [nl] directions of the tiles each marker's stencil touches
+    void *rs, *scan, *dscan;
 };
 
-static BucketWs carve_bucket_ws(void* ws, size_t bytes, int64_t nl, int64_t cap, size_t* need)
+// Source lists by direction need every axis to hold at least 3 tiles.
+static bool by_direction(const Grid& g)
+{
+    return g.nt[0] >= 3 && g.nt[1] >= 3 && g.nt[2] >= 3;
+}
+
+static BucketWs carve_bucket_ws(void* ws, size_t bytes, int64_t nl, int64_t cap, int64_t Tdir,
+                                size_t* need)
 {
     Carver cv(ws, bytes);
     BucketWs w;
+    w.dcnt = cv.take<int32_t>(NDIR * Tdir);
+    w.dtot = cv.take<int32_t>(Tdir);
+    w.dscan = cv.take<char>(scan_workspace(Tdir));
+    w.dmask = cv.take<uint32_t>(Tdir > 0 ? nl : 0);
     w.keys = cv.take<int32_t>(nl);
     w.tk = cv.take<int32_t>(nl);
     w.tv = cv.take<int32_t>(nl);
@@ -587,11 +794,12 @@ using namespace ibx;
 
 extern "C" size_t ib_bucket_workspace(const ib_level* lv, int64_t nl)
 {
-    (void)lv;
     size_t need = 0;
-    if (nl < 0)
+    if (nl < 0 || check_level(lv))
         return 0;
-    carve_bucket_ws(nullptr, 0, nl, 8 * (nl > 0 ? nl : 1), &need);
+    const Grid g = make_grid(lv);
+    carve_bucket_ws(nullptr, 0, nl, 8 * (nl > 0 ? nl : 1), by_direction(g) ? g.ntiles : 0,
+                    &need);
     return need;
 }
 
@@ -615,10 +823,11 @@ extern "C" int ib_bucket(const ib_level* lv, const ib_markers* m, ib_delta delta
     hipStream_t st = (hipStream_t)stream;
     size_t need = 0;
     const int64_t cap = b->src_cap < 8 * nl ? b->src_cap : 8 * nl;
-    BucketWs w = carve_bucket_ws(nullptr, 0, nl, cap, &need);
+    const bool dir = by_direction(g);
+    BucketWs w = carve_bucket_ws(nullptr, 0, nl, cap, dir ? T : 0, &need);
     if (!ws || ws_bytes < need)
         return IB_EWORKSPACE;
-    w = carve_bucket_ws(ws, ws_bytes, nl, cap, &need);
+    w = carve_bucket_ws(ws, ws_bytes, nl, cap, dir ? T : 0, &need);
 
     k_init_flags<<<1, 64, 0, st>>>(b->flag);
     if (nl == 0) {
@@ -632,12 +841,26 @@ extern "C" int ib_bucket(const ib_level* lv, const ib_markers* m, ib_delta delta
     const int kb = 8 * passes + 4 <= 31 ? 8 * passes : 0;   // 4 count bits above the digits
     if (delta == IB_DELTA3)
         k_bucket_keys<3><<<gb, 256, 0, st>>>(g, nl, m->x, m->y, m->z, b->cell, b->tileid,
-                                             b->base, w.keys, b->perm, b->flag, kb);
+                                             b->base, w.keys, b->perm, b->flag, kb,
+                                             dir ? w.dmask : nullptr);
     else
         k_bucket_keys<4><<<gb, 256, 0, st>>>(g, nl, m->x, m->y, m->z, b->cell, b->tileid,
-                                             b->base, w.keys, b->perm, b->flag, kb);
+                                             b->base, w.keys, b->perm, b->flag, kb,
+                                             dir ? w.dmask : nullptr);
     radix_sort_pairs(w.keys, b->perm, w.tk, w.tv, nl, nullptr, bits, w.rs, st);
     lower_bounds(w.keys, nl, nullptr, b->tile_offs, T, st, kb > 0 ? (1 << kb) - 1 : -1);
+
+    if (dir) {
+        const unsigned gw = (unsigned)(T < 16384 ? T : 16384);
+        k_zero_i32<<<(unsigned)((T + 255) / 256), 256, 0, st>>>(T, w.dtot);
+        k_dir_counts<<<gw, 64, 0, st>>>(g, T, b->tile_offs, b->perm, w.dmask, w.dcnt, w.dtot);
+        scan_exclusive(w.dtot, b->src_offs, T, b->src_offs + T, w.dscan, st);
+        k_dir_offsets<<<(unsigned)((T + 4) / 4), 256, 0, st>>>(g, T, w.dcnt, b->src_offs, cap,
+                                                              b->flag);
+        k_dir_emit<<<gw, 64, 0, st>>>(g, T, b->tile_offs, b->perm, w.dmask, w.dcnt, b->src_idx,
+                                      cap);
+        return launch_status();
+    }
 
     if (kb > 0) {
         scan_exclusive(w.keys, w.cnt, nl, nullptr, w.scan, st, kb);

@@ -53,7 +53,31 @@ def test_build_markers(dev, name, mk):
     assert ibx.count_markers(wl.d, wl.level.h).tolist() == O.count_markers(wl.d, wl.level.h).tolist()
 
 
-@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def _bucket_extra():
+    """Grids that take the other branches of the source-list construction: two
+    bounded axes (stencils within a few cells of both ends, and wrapping on
+    the periodic one), and a 16^3 grid with only two tiles per axis (the
+    sort-based construction)."""
+    h48 = 1.0 / 48
+    bounded = [[6.3 * h48, 2.1 * h48, 40.2 * h48], [24.5 * h48, 24.2 * h48, 7.0 * h48],
+               [41.0 * h48, 46.7 * h48, 24.3 * h48]]
+    h16 = 1.0 / 16
+    return [
+        ("bounded48_P4", lambda: W.make_workload("bounded48", 48, 16, 2, 4, 2,
+                                                 np.full(3, 8.0), centres=bounded, nmodes=8,
+                                                 K=4, cover_all=True, periodic=(0, 1, 0))),
+        ("bounded48_P3", lambda: W.make_workload("bounded48", 48, 16, 2, 3, 2,
+                                                 np.full(3, 8.0), centres=bounded, nmodes=8,
+                                                 K=4, cover_all=True, periodic=(0, 1, 0))),
+        ("two_tiles16_P4", lambda: W.make_workload("two16", 16, 16, 2, 4, 2, np.full(2, 5.0),
+                                                   centres=[[4 * h16, 4.2 * h16, 3.9 * h16],
+                                                            [12.1 * h16, 11 * h16, 10.3 * h16]],
+                                                   nmodes=8, K=4, cover_all=True)),
+    ]
+
+
+@pytest.mark.parametrize("name,mk", CASES + _bucket_extra(),
+                         ids=[c[0] for c in CASES + _bucket_extra()])
 def test_bucket_bit_exact(dev, name, mk):
     import torch
 
@@ -362,3 +386,27 @@ def test_batched_misaligned_fields(dev):
         outs.append((ustar.cpu().numpy(), f.cpu().numpy(), F.cpu().numpy()))
     for a, bb in zip(outs[0], outs[1]):
         assert np.array_equal(a, bb, equal_nan=True)
+
+
+@pytest.mark.parametrize("name,mk", [CASES[0], _bucket_extra()[2]],
+                         ids=[CASES[0][0], _bucket_extra()[2][0]])
+def test_bucket_source_list_overflow(dev, name, mk):
+    """A source-list capacity below the pair count raises flag[1]; the list
+    bounds stay within the capacity and non-decreasing, so consumers never
+    read past it."""
+    import torch
+
+    import oracle as O
+    import paper_2408_14140_amd as ibx
+    announce(f"bucket overflow {name}")
+    wl = mk()
+    c = Case(wl, dev)
+    ref = O.bucket(c.lev, wl.delta, c.m)
+    need = int(ref["src_offs"][-1])
+    cap = need // 2
+    b = ibx.bucket(c.dl, c.dm, wl.delta, src_cap=cap)
+    torch.cuda.synchronize()
+    assert int(b.flag[1].item()) == 1
+    so = b.src_offs.cpu().numpy()
+    assert so[0] == 0 and so[-1] == cap and np.all(np.diff(so) >= 0)
+    assert np.array_equal(b.tile_offs.cpu().numpy(), ref["tile_offs"])
