@@ -2,12 +2,15 @@
 // lists.  Integer work only; every output is deterministic.
 //
 // Pipeline (all on one stream, no host synchronization):
-//   keys    per marker: owning cell, tile, stencil base, coverage check
+//   keys    per marker: owning cell, tile, stencil base, coverage check, and
+//           the directions of the tiles its stencil touches
 //   sort    stable LSD radix sort of (tile, marker) -> perm
 //   offs    tile_offs[t] = lower bound of t in the sorted tiles
-//   pairs   per sorted position i, the (tile, i) pairs of every tile its
-//           stencil touches, emitted in i order, then stably sorted by tile
-//           -> src_idx / src_offs (each list ascending in i)
+//   lists   src_idx / src_offs (each list ascending in the sorted position):
+//           with 3 or more tiles on every axis, by direction (per owning
+//           tile, runs counted and written with ballots, placed by one scan);
+//           otherwise the (tile, i) pairs of every touched tile, emitted in
+//           i order and stably sorted by tile
 #include "ibx_internal.h"
 
 namespace ibx {
