@@ -139,6 +139,8 @@ int ib_desired_velocity(const ib_particles* p, const ib_markers* m, ib_prec prec
 /* make every later call return garbage for them.                          */
 /* ---------------------------------------------------------------------- */
 
+/* Device workspace of ib_bucket in bytes: grows with nl and with the level's
+ * tile count (0 for an invalid level or nl < 0). */
 size_t ib_bucket_workspace(const ib_level* lv, int64_t nl);
 int ib_bucket(const ib_level* lv, const ib_markers* m, ib_delta delta, const ib_buckets* b,
               void* ws, size_t ws_bytes, void* stream);
