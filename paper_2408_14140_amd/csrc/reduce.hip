@@ -11,8 +11,9 @@
 //
 // The volume integrals run on RD_SLABS workgroups per particle, each taking
 // the z planes of the particle's bounding box congruent to its slab index,
-// and write FP64 partial sums; a second kernel adds the Lagrangian sums and
-// the slab partials in a fixed order.  Every sum is formed by fixed-shape
+// and write FP64 partial sums; one more workgroup per particle forms the
+// Lagrangian sums beside them, and a second kernel adds the slab partials in
+// a fixed order.  Every sum is formed by fixed-shape
 // trees, so results are reproducible bit for bit.
 #include "paths.h"
 
@@ -58,20 +59,58 @@ __device__ inline void block_sums(double (&acc)[N], double (*red)[N])
     }
 }
 
+// Lagrangian sums of particle p -> part[p][RD_SLABS][6].
+template <typename T>
+__device__ void lagrangian_sums(int p, const double* __restrict__ xc,
+                                const int64_t* __restrict__ offs, const double* __restrict__ x,
+                                const double* __restrict__ y, const double* __restrict__ z,
+                                const double* __restrict__ dv, const T* __restrict__ F,
+                                double* __restrict__ part, double (*red)[6])
+{
+    const int t = threadIdx.x;
+    const double c[3] = {xc[3 * p], xc[3 * p + 1], xc[3 * p + 2]};
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double dvp = dv[p];
+    for (int64_t l = offs[p] + t; l < offs[p + 1]; l += RD_THREADS) {
+        const double F0 = (double)F[3 * l], F1 = (double)F[3 * l + 1], F2 = (double)F[3 * l + 2];
+        const double R0 = x[l] - c[0], R1 = y[l] - c[1], R2 = z[l] - c[2];
+        acc[0] += F0 * dvp;
+        acc[1] += F1 * dvp;
+        acc[2] += F2 * dvp;
+        acc[3] += (R1 * F2 - R2 * F1) * dvp;
+        acc[4] += (R2 * F0 - R0 * F2) * dvp;
+        acc[5] += (R0 * F1 - R1 * F0) * dvp;
+    }
+    block_sums<6>(acc, red);
+    if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            part[((int64_t)p * (RD_SLABS + 1) + RD_SLABS) * 6 + q] = acc[q];
+    }
+}
+
 // Volume integrals of particle blockIdx.x over the z planes kk = slab,
-// slab + RD_SLABS, ... of its bounding box -> part[p][slab][6].
+// slab + RD_SLABS, ... of its bounding box -> part[p][slab][6]; workgroup
+// slab = RD_SLABS forms the particle's Lagrangian sums instead.
 // Each wavefront classifies 64 cells per round with no global access:
 // interior cells (alpha = 1) and cells near the surface go, in cell order, to
 // two queues of its own in LDS, drained in bulk with independent loads.
 template <typename T>
 __global__ void __launch_bounds__(RD_THREADS)
 k_volume_partials(Grid g, const double* __restrict__ xc, const double* __restrict__ d,
-                  const T* __restrict__ u, double* __restrict__ part, int32_t* flag)
+                  const T* __restrict__ u, double* __restrict__ part, int32_t* flag,
+                  const int64_t* __restrict__ offs, const double* __restrict__ mx,
+                  const double* __restrict__ my, const double* __restrict__ mz,
+                  const double* __restrict__ dv, const T* __restrict__ F)
 {
     __shared__ double red[RD_WAVES][6];
     __shared__ int qin[RD_WAVES * RD_QCAP], qsurf[RD_WAVES * RD_QCAP];
     __shared__ int2 ptab[3][RD_TAB];       // per axis: (box index or -1, index in the extent)
     const int p = blockIdx.x, slab = blockIdx.y;
+    if (slab == RD_SLABS) {
+        lagrangian_sums<T>(p, xc, offs, mx, my, mz, dv, F, part, red);
+        return;
+    }
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const double c[3] = {xc[3 * p], xc[3 * p + 1], xc[3 * p + 2]};
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -241,48 +280,30 @@ k_volume_partials(Grid g, const double* __restrict__ xc, const double* __restric
     if (t == 0) {
 #pragma unroll
         for (int q = 0; q < 6; ++q)
-            part[((int64_t)p * RD_SLABS + slab) * 6 + q] = acc[q];
+            part[((int64_t)p * (RD_SLABS + 1) + slab) * 6 + q] = acc[q];
     }
 }
 
-// Lagrangian sums of particle blockIdx.x, then out[p] with the slab partials
-// of the volume integrals added in slab order.
-template <typename T>
-__global__ void __launch_bounds__(RD_THREADS)
-k_particle_sums(const double* __restrict__ xc, const int64_t* __restrict__ offs,
-                const double* __restrict__ x, const double* __restrict__ y,
-                const double* __restrict__ z, const double* __restrict__ dv,
-                const T* __restrict__ F, const double* __restrict__ part,
-                double* __restrict__ out)
+// out[p] = (Lagrangian sums, then the slab partials of the volume integrals
+// added in slab order); one thread per output value.
+__global__ void k_particle_out(int64_t np, const double* __restrict__ part,
+                               double* __restrict__ out)
 {
-    __shared__ double red[RD_WAVES][6];
-    const int p = blockIdx.x;
-    const int t = threadIdx.x;
-    const double c[3] = {xc[3 * p], xc[3 * p + 1], xc[3 * p + 2]};
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const double dvp = dv[p];
-    for (int64_t l = offs[p] + t; l < offs[p + 1]; l += RD_THREADS) {
-        const double F0 = (double)F[3 * l], F1 = (double)F[3 * l + 1], F2 = (double)F[3 * l + 2];
-        const double R0 = x[l] - c[0], R1 = y[l] - c[1], R2 = z[l] - c[2];
-        acc[0] += F0 * dvp;
-        acc[1] += F1 * dvp;
-        acc[2] += F2 * dvp;
-        acc[3] += (R1 * F2 - R2 * F1) * dvp;
-        acc[4] += (R2 * F0 - R0 * F2) * dvp;
-        acc[5] += (R0 * F1 - R1 * F0) * dvp;
-    }
-    block_sums<6>(acc, red);
-    if (t == 0) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q)
-            out[12 * (int64_t)p + q] = acc[q];
-    }
-    if (t >= 6 && t < 12) {
-        double v = 0.0;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 12 * np)
+        return;
+    const int64_t p = e / 12;
+    const int q = (int)(e - 12 * p);
+    const double* pp = part + p * (RD_SLABS + 1) * 6;
+    double v;
+    if (q < 6) {
+        v = pp[RD_SLABS * 6 + q];
+    } else {
+        v = 0.0;
         for (int sl = 0; sl < RD_SLABS; ++sl)
-            v += part[((int64_t)p * RD_SLABS + sl) * 6 + (t - 6)];
-        out[12 * (int64_t)p + t] = v;
+            v += pp[sl * 6 + (q - 6)];
     }
+    out[e] = v;
 }
 
 }  // namespace ibx
@@ -291,7 +312,7 @@ using namespace ibx;
 
 extern "C" size_t ib_reductions_workspace(int32_t np)
 {
-    return np > 0 ? (size_t)np * RD_SLABS * 6 * sizeof(double) : 0;
+    return np > 0 ? (size_t)np * (RD_SLABS + 1) * 6 * sizeof(double) : 0;
 }
 
 extern "C" int ib_particle_reductions(const ib_level* lv, const ib_particles* p,
@@ -314,17 +335,16 @@ extern "C" int ib_particle_reductions(const ib_level* lv, const ib_particles* p,
     Grid g = make_grid(lv);
     hipStream_t st = (hipStream_t)stream;
     double* part = (double*)ws;
-    const dim3 gv((unsigned)p->np, RD_SLABS);
-    if (prec == IB_F64) {
-        k_volume_partials<double><<<gv, RD_THREADS, 0, st>>>(g, p->xc, p->d, (const double*)u,
-                                                              part, flag);
-        k_particle_sums<double><<<(unsigned)p->np, RD_THREADS, 0, st>>>(
-            p->xc, m->offs, m->x, m->y, m->z, m->dv, (const double*)F, part, out);
-    } else {
-        k_volume_partials<float><<<gv, RD_THREADS, 0, st>>>(g, p->xc, p->d, (const float*)u,
-                                                             part, flag);
-        k_particle_sums<float><<<(unsigned)p->np, RD_THREADS, 0, st>>>(
-            p->xc, m->offs, m->x, m->y, m->z, m->dv, (const float*)F, part, out);
-    }
+    const dim3 gv((unsigned)p->np, RD_SLABS + 1);
+    if (prec == IB_F64)
+        k_volume_partials<double><<<gv, RD_THREADS, 0, st>>>(
+            g, p->xc, p->d, (const double*)u, part, flag, m->offs, m->x, m->y, m->z, m->dv,
+            (const double*)F);
+    else
+        k_volume_partials<float><<<gv, RD_THREADS, 0, st>>>(
+            g, p->xc, p->d, (const float*)u, part, flag, m->offs, m->x, m->y, m->z, m->dv,
+            (const float*)F);
+    const int64_t ne = 12 * (int64_t)p->np;
+    k_particle_out<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(p->np, part, out);
     return launch_status();
 }
