@@ -99,3 +99,14 @@ def test_build_entry_calls_both_builders(monkeypatch):
     monkeypatch.setattr(ge, "_library_builder", lambda: (lambda: calls.append("library")))
     ge.build()
     assert sorted(calls) == ["library", "oracle"]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The library has no multi-GPU path: bench.py --gpus N > 1 exits with a
+    message before touching a GPU."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
