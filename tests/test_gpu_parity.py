@@ -260,7 +260,19 @@ def test_box_tiling_invariance(dev):
         assert rel(F, outs[0][1]) <= 1e-14
 
 
-@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def _big_spheres():
+    """Two spheres far larger than the others here (bounding boxes of 64 and
+    75 cells per axis, thousands of near-surface cells per workgroup, so the
+    per-wavefront queues fill and drain many times), both wrapping across the
+    periodic boundaries."""
+    h = 1.0 / 96
+    xc = np.array([[48.9 * h] * 3, [10.3 * h, 88.6 * h, 47.2 * h]])
+    return W.make_workload("big_spheres96", 96, 32, 2, 4, 2, np.array([60.4, 72.0]),
+                           centres=xc, nmodes=8, K=4, cover_all=True)
+
+
+@pytest.mark.parametrize("name,mk", CASES + [("big_spheres96", _big_spheres)],
+                         ids=[c[0] for c in CASES] + ["big_spheres96"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_particle_reductions(dev, name, mk, dtype):
     import torch
