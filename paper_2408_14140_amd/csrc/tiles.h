@@ -387,6 +387,23 @@ __device__ inline int wave_exclusive_sum(int v)
     return s;
 }
 
+// m with its s lowest set bits cleared (s below the popcount of m): a binary
+// search for the position of the s-th set bit by halves, in constant time.
+__device__ inline uint64_t drop_low_bits(uint64_t m, int s)
+{
+    int p = 0;
+    uint64_t w = m;
+    int c = __popc((uint32_t)w);
+    if (s >= c) { s -= c; w >>= 32; p = 32; }
+    uint32_t v = (uint32_t)w;
+    c = __popc(v & 0xffffu); if (s >= c) { s -= c; v >>= 16; p += 16; }
+    c = __popc(v & 0xffu);   if (s >= c) { s -= c; v >>= 8;  p += 8; }
+    c = __popc(v & 0xfu);    if (s >= c) { s -= c; v >>= 4;  p += 4; }
+    c = __popc(v & 0x3u);    if (s >= c) { s -= c; v >>= 2;  p += 2; }
+    if (s >= (int)(v & 1u)) p += 1;
+    return m & (~0ull << p);
+}
+
 // One wavefront per workgroup; the tile is stored to its G slot.  The
 // workgroups of XCD x (ids = x mod 8) take the entries of slab x of `sent`
 // (the x-th of 8 equal cuts, each by decreasing cost) dealt in a snake: with
@@ -539,9 +556,7 @@ k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactiv
                     pacc[xx][0] = pacc[xx][1] = pacc[xx][2] = T(0);
                 if (lane < NP) {
                     const int pr = piece[lane] & 255, pq = piece[lane] >> 8;
-                    uint64_t m = rest[pr];
-                    for (int q = 0; q < pq * K; ++q)
-                        m &= m - 1;
+                    uint64_t m = drop_low_bits(rest[pr], pq * K);
                     for (int tt = 0; tt < K && m; ++tt) {
                         const int k = __builtin_ctzll(m);
                         m &= m - 1;
