@@ -21,8 +21,37 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 4;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 
+// Up to this many tiles, each workgroup of the add pass sums the tile totals
+// before its own tile itself, instead of a second scan over the totals (two
+// launches fewer; the sums grow with the square of the tile count).
+constexpr int64_t SCAN_FUSE = 64;
+
+// Sum of a[0 .. m) over the workgroup; every thread gets it.  Called by all
+// threads of the workgroup.
+__device__ int32_t group_sum(const int32_t* a, int64_t m)
+{
+    __shared__ int32_t part[SCAN_THREADS / 64];
+    int32_t s = 0;
+    for (int64_t k = threadIdx.x; k < m; k += SCAN_THREADS)
+        s += a[k];
+    for (int off = 32; off > 0; off >>= 1)
+        s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    int32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_THREADS / 64; ++w)
+        tot += part[w];
+    __syncthreads();
+    return tot;
+}
+
+// total (if not null) receives the sum of the whole input: launch it only
+// with one workgroup then.
 __global__ void __launch_bounds__(SCAN_THREADS)
-k_scan_tile(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, int shift)
+k_scan_tile(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, int shift,
+            int32_t* total)
 {
     __shared__ int32_t ts[SCAN_THREADS];
     const int t = threadIdx.x;
@@ -49,20 +78,27 @@ k_scan_tile(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, int shift
             out[base + k] = run;
         run += v[k];
     }
-    if (t == SCAN_THREADS - 1)
+    if (t == SCAN_THREADS - 1) {
         sums[blockIdx.x] = ts[t];
+        if (total)
+            *total = ts[t];
+    }
 }
 
-__global__ void k_scan_add(int32_t* out, int64_t n, const int32_t* sums)
+// sums: the scanned tile totals, or (fused) the tile totals themselves, whose
+// prefix each workgroup forms; the last workgroup then writes the total.
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_scan_add(int32_t* out, int64_t n, const int32_t* sums, bool fused, int32_t* total)
 {
-    const int32_t add = sums[blockIdx.x];
+    const int32_t add = fused ? group_sum(sums, blockIdx.x) : sums[blockIdx.x];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
     for (int k = threadIdx.x; k < SCAN_TILE; k += blockDim.x)
         if (base + k < n)
             out[base + k] += add;
+    if (fused && total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1)
+        *total = add + sums[blockIdx.x];
 }
 
-__global__ void k_copy1(int32_t* dst, const int32_t* src) { *dst = *src; }
 __global__ void k_set1(int32_t* dst, int32_t v) { *dst = v; }
 
 size_t scan_workspace(int64_t n)
@@ -88,14 +124,16 @@ void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* total, 
     }
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     int32_t* sums = (int32_t*)ws;
-    k_scan_tile<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, out, n, sums, shift);
-    if (nb == 1) {
-        if (total)
-            k_copy1<<<1, 1, 0, st>>>(total, sums);
+    k_scan_tile<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, out, n, sums, shift,
+                                                       nb == 1 ? total : nullptr);
+    if (nb == 1)
+        return;
+    if (nb <= SCAN_FUSE) {
+        k_scan_add<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(out, n, sums, true, total);
         return;
     }
     scan_exclusive(sums, sums, nb, total, (char*)ws + align_up(sizeof(int32_t) * nb), st, 0);
-    k_scan_add<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(out, n, sums);
+    k_scan_add<<<(unsigned)nb, SCAN_THREADS, 0, st>>>(out, n, sums, false, nullptr);
 }
 
 // Two independent scans of the same length in one pass per level: block b
@@ -141,9 +179,11 @@ k_scan_tile2(const int32_t* in0, int32_t* out0, const int32_t* in1, int32_t* out
 
 // Adds the scanned tile sums back (sums holds both arrays' tiles, nb each);
 // blocks 2 nb and 2 nb + 1 ... are not used: the totals come from the last
-// tile of each array.
-__global__ void k_scan_add2(int32_t* out0, int32_t* out1, int64_t n, const int32_t* sums_scan,
-                            const int32_t* sums, int32_t* total0, int32_t* total1)
+// tile of each array.  With sums_scan null, each workgroup forms the prefix
+// of the tile totals itself.
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_scan_add2(int32_t* out0, int32_t* out1, int64_t n, const int32_t* sums_scan,
+            const int32_t* sums, int32_t* total0, int32_t* total1)
 {
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     const bool second = blockIdx.x >= nb;
@@ -151,14 +191,15 @@ __global__ void k_scan_add2(int32_t* out0, int32_t* out1, int64_t n, const int32
     int32_t* out = second ? out1 : out0;
     // exclusive prefix of this array's tiles = scan of all tiles minus the
     // first array's total for the second array
-    const int32_t first_total = sums_scan[nb - 1] + sums[nb - 1];
-    const int32_t add = sums_scan[blockIdx.x] - (second ? first_total : 0);
+    const int32_t pre = sums_scan ? sums_scan[blockIdx.x] : group_sum(sums, blockIdx.x);
+    const int32_t first_total = sums_scan ? sums_scan[nb - 1] + sums[nb - 1] : group_sum(sums, nb);
+    const int32_t add = pre - (second ? first_total : 0);
     const int64_t base = blk * SCAN_TILE;
     for (int k = threadIdx.x; k < SCAN_TILE; k += blockDim.x)
         if (base + k < n)
             out[base + k] += add;
     if (threadIdx.x == 0 && blk == nb - 1) {
-        const int32_t tot = sums_scan[blockIdx.x] + sums[blockIdx.x] - (second ? first_total : 0);
+        const int32_t tot = pre + sums[blockIdx.x] - (second ? first_total : 0);
         if (second) {
             if (total1)
                 *total1 = tot;
@@ -189,9 +230,12 @@ void scan_exclusive2(const int32_t* in0, int32_t* out0, const int32_t* in1, int3
     int32_t* sscan = (int32_t*)((char*)ws + align_up(sizeof(int32_t) * 2 * nb));
     void* rest = (char*)ws + 2 * align_up(sizeof(int32_t) * 2 * nb);
     k_scan_tile2<<<(unsigned)(2 * nb), SCAN_THREADS, 0, st>>>(in0, out0, in1, out1, n, sums);
-    scan_exclusive(sums, sscan, 2 * nb, nullptr, rest, st, 0);
-    k_scan_add2<<<(unsigned)(2 * nb), SCAN_THREADS, 0, st>>>(out0, out1, n, sscan, sums, total0,
-                                                             total1);
+    const bool fused = 2 * nb <= SCAN_FUSE;
+    if (!fused)
+        scan_exclusive(sums, sscan, 2 * nb, nullptr, rest, st, 0);
+    k_scan_add2<<<(unsigned)(2 * nb), SCAN_THREADS, 0, st>>>(out0, out1, n,
+                                                             fused ? nullptr : sscan, sums,
+                                                             total0, total1);
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -409,10 +453,14 @@ void lower_bounds(const int32_t* keys, int64_t n_max, const int32_t* n_dev, int3
 
 // ------------------------------------------------------------------ bucket keys
 
-__global__ void k_init_flags(int32_t* flag)
+// Clears the two flags and a[0 .. n).
+__global__ void k_init_flags(int32_t* flag, int64_t n, int32_t* __restrict__ a)
 {
-    if (threadIdx.x < 2)
-        flag[threadIdx.x] = 0;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2)
+        flag[i] = 0;
+    if (i < n)
+        a[i] = 0;
 }
 
 // Tiles touched on one axis by the stencil cells b .. b+P-1 (1 or 2 tiles).
@@ -657,13 +705,6 @@ k_dir_counts(Grid g, int64_t T, const int32_t* __restrict__ tile_offs,
     }
 }
 
-__global__ void k_zero_i32(int64_t n, int32_t* __restrict__ a)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n)
-        a[i] = 0;
-}
-
 // In place: cnt[t'][d] becomes the first position of that run in src_idx
 // (the runs of tile t follow src_offs[t] in increasing owner index); every
 // entry belongs to exactly one receiving tile.  One wavefront per receiving
@@ -832,7 +873,8 @@ extern "C" int ib_bucket(const ib_level* lv, const ib_markers* m, ib_delta delta
         return IB_EWORKSPACE;
     w = carve_bucket_ws(ws, ws_bytes, nl, cap, dir ? T : 0, &need);
 
-    k_init_flags<<<1, 64, 0, st>>>(b->flag);
+    const int64_t nz = dir && nl > 0 ? T : 0;                // the list totals, when used
+    k_init_flags<<<(unsigned)(nz > 0 ? (nz + 255) / 256 : 1), 256, 0, st>>>(b->flag, nz, w.dtot);
     if (nl == 0) {
         lower_bounds(w.keys, 0, nullptr, b->tile_offs, T, st);
         lower_bounds(w.keys, 0, nullptr, b->src_offs, T, st);
@@ -855,7 +897,6 @@ extern "C" int ib_bucket(const ib_level* lv, const ib_markers* m, ib_delta delta
 
     if (dir) {
         const unsigned gw = (unsigned)(T < 16384 ? T : 16384);
-        k_zero_i32<<<(unsigned)((T + 255) / 256), 256, 0, st>>>(T, w.dtot);
         k_dir_counts<<<gw, 64, 0, st>>>(g, T, b->tile_offs, b->perm, w.dmask, w.dcnt, w.dtot);
         scan_exclusive(w.dtot, b->src_offs, T, b->src_offs + T, w.dscan, st);
         k_dir_offsets<<<(unsigned)((T + 4) / 4), 256, 0, st>>>(g, T, w.dcnt, b->src_offs, cap,
