@@ -710,10 +710,12 @@ k_dir_counts(Grid g, int64_t T, const int32_t* __restrict__ tile_offs,
 // entry belongs to exactly one receiving tile.  One wavefront per receiving
 // tile (four per workgroup), lane d for direction d; the wavefront of t = T
 // clamps the total to the capacity
-// and raises flag[1] on overflow.  src_offs[t] is clamped likewise.
+// and raises flag[1] on overflow.  src_offs[t] is clamped likewise.  A tile
+// that no stencil reaches (tot[t] = 0) has only empty runs, which the emit
+// pass never reads: their entries keep their (zero) counts.
 __global__ void __launch_bounds__(256)
 k_dir_offsets(Grid g, int64_t T, int32_t* __restrict__ cnt, int32_t* __restrict__ src_offs,
-              int64_t cap, int32_t* __restrict__ flag)
+              const int32_t* __restrict__ tot, int64_t cap, int32_t* __restrict__ flag)
 {
     const int lane = threadIdx.x & 63;
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -727,6 +729,10 @@ k_dir_offsets(Grid g, int64_t T, int32_t* __restrict__ cnt, int32_t* __restrict_
         }
         return;
     }
+    if (lane == 0 && o > cap)
+        src_offs[t] = (int32_t)cap;
+    if (tot[t] == 0)
+        return;
     int tc[3];
     tile_xyz(g, t, tc);
     int own = -1, c = 0;
@@ -745,8 +751,6 @@ k_dir_offsets(Grid g, int64_t T, int32_t* __restrict__ cnt, int32_t* __restrict_
     }
     if (own >= 0)
         cnt[(int64_t)own * NDIR + lane] = pos;
-    if (lane == 0 && o > cap)
-        src_offs[t] = (int32_t)cap;
 }
 
 // Each owning tile writes its runs: marker i goes to position first + rank in
@@ -899,8 +903,8 @@ extern "C" int ib_bucket(const ib_level* lv, const ib_markers* m, ib_delta delta
         const unsigned gw = (unsigned)(T < 16384 ? T : 16384);
         k_dir_counts<<<gw, 64, 0, st>>>(g, T, b->tile_offs, b->perm, w.dmask, w.dcnt, w.dtot);
         scan_exclusive(w.dtot, b->src_offs, T, b->src_offs + T, w.dscan, st);
-        k_dir_offsets<<<(unsigned)((T + 4) / 4), 256, 0, st>>>(g, T, w.dcnt, b->src_offs, cap,
-                                                              b->flag);
+        k_dir_offsets<<<(unsigned)((T + 4) / 4), 256, 0, st>>>(g, T, w.dcnt, b->src_offs,
+                                                              w.dtot, cap, b->flag);
         k_dir_emit<<<gw, 64, 0, st>>>(g, T, b->tile_offs, b->perm, w.dmask, w.dcnt, b->src_idx,
                                       cap);
         return launch_status();
