@@ -251,6 +251,108 @@ k_cost_hist(int64_t T, const int32_t* __restrict__ src_offs, const int32_t* __re
             atomicAdd(&hist[b], lh[b]);
 }
 
+// The two work-list scans for grids of at most SCAN_FUSE / 2 scan tiles, in
+// two launches.  Pass 1: workgroup b < nb scans the interpolation item counts
+// ceil(markers / bw) of scan tile b, workgroup nb + b the flags "source list
+// not empty" (the inputs are formed from the offsets on the fly); workgroup 0
+// also clears the cost histogram.
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_list_scan(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
+            const int32_t* __restrict__ src_offs, int32_t* __restrict__ item_offs,
+            int32_t* __restrict__ act_offs, int32_t* __restrict__ sums,
+            int32_t* __restrict__ hist)
+{
+    __shared__ int32_t ts[SCAN_THREADS];
+    if (blockIdx.x == 0)
+        for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
+            hist[b] = 0;
+    const int64_t nb = (T + SCAN_TILE - 1) / SCAN_TILE;
+    const bool second = blockIdx.x >= nb;
+    const int64_t blk = second ? blockIdx.x - nb : blockIdx.x;
+    int32_t* out = second ? act_offs : item_offs;
+    const int t = threadIdx.x;
+    const int64_t base = blk * SCAN_TILE + (int64_t)t * SCAN_ITEMS;
+    int32_t v[SCAN_ITEMS];
+    int32_t tsum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t i = base + k;
+        v[k] = 0;
+        if (i < T)
+            v[k] = second ? (src_offs[i + 1] > src_offs[i] ? 1 : 0)
+                          : (tile_offs[i + 1] - tile_offs[i] + bw - 1) / bw;
+        tsum += v[k];
+    }
+    ts[t] = tsum;
+    __syncthreads();
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+        const int32_t x = t >= off ? ts[t - off] : 0;
+        __syncthreads();
+        ts[t] += x;
+        __syncthreads();
+    }
+    int32_t run = ts[t] - tsum;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < T)
+            out[base + k] = run;
+        run += v[k];
+    }
+    if (t == SCAN_THREADS - 1)
+        sums[blockIdx.x] = ts[t];
+}
+
+// Pass 2: each workgroup adds the totals of the scan tiles before its own
+// (for the flags, less the item total), the last one of each array writes its
+// total (nitems, nactive), and the flag workgroups count their spreading
+// tiles into the cost histogram (as k_cost_hist does).
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_list_add(int64_t T, const int32_t* __restrict__ src_offs, int32_t* __restrict__ item_offs,
+           int32_t* __restrict__ act_offs, const int32_t* __restrict__ sums,
+           int32_t* __restrict__ nitems, int32_t* __restrict__ nactive,
+           int32_t* __restrict__ hist)
+{
+    __shared__ int32_t lh[NXCD * COST_BINS];
+    const int64_t nb = (T + SCAN_TILE - 1) / SCAN_TILE;
+    const bool second = blockIdx.x >= nb;
+    const int64_t blk = second ? blockIdx.x - nb : blockIdx.x;
+    int32_t* out = second ? act_offs : item_offs;
+    const int32_t pre = group_sum(sums, blockIdx.x);
+    const int32_t first_total = group_sum(sums, nb);
+    const int32_t n_act = group_sum(sums + nb, nb);
+    const int32_t add = pre - (second ? first_total : 0);
+    const int64_t base = blk * SCAN_TILE;
+    if (threadIdx.x == 0 && blk == nb - 1) {
+        if (second)
+            *nactive = n_act;
+        else
+            *nitems = first_total;
+    }
+    if (!second) {
+        for (int k = threadIdx.x; k < SCAN_TILE; k += blockDim.x)
+            if (base + k < T)
+                out[base + k] += add;
+        return;
+    }
+    for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
+        lh[b] = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < SCAN_TILE; k += blockDim.x) {
+        const int64_t i = base + k;
+        if (i < T) {
+            const int32_t a = out[i] + add;
+            out[i] = a;
+            const int c = src_offs[i + 1] - src_offs[i];
+            if (c > 0)
+                atomicAdd(&lh[slab_of(a, n_act) * COST_BINS + min(c, COST_BINS - 1)], 1);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
+        if (lh[b])
+            atomicAdd(&hist[b], lh[b]);
+}
+
 // cur[x][b] = first position of slab x plus its tiles in bins above b.
 __global__ void __launch_bounds__(COST_BINS)
 k_bin_scan(const int32_t* __restrict__ hist, const int32_t* __restrict__ nactive,
@@ -616,11 +718,20 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
                                      p->up, p->om, w.s);
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_LISTS);
-    k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt, w.act,
-                                      w.hist);
-    scan_exclusive2(w.item_cnt, w.item_offs, w.act, w.act_offs, T_, w.nitems, w.nactive, w.scan,
-                    st);
-    k_cost_hist<<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.hist);
+    const int64_t nbl = (T_ + SCAN_TILE - 1) / SCAN_TILE;
+    if (2 * nbl <= SCAN_FUSE) {
+        int32_t* sums = (int32_t*)w.scan;
+        k_list_scan<<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
+            T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs, w.act_offs, sums, w.hist);
+        k_list_add<<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
+            T_, b->src_offs, w.item_offs, w.act_offs, sums, w.nitems, w.nactive, w.hist);
+    } else {
+        k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt,
+                                          w.act, w.hist);
+        scan_exclusive2(w.item_cnt, w.item_offs, w.act, w.act_offs, T_, w.nitems, w.nactive,
+                        w.scan, st);
+        k_cost_hist<<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.hist);
+    }
     k_bin_scan<<<NXCD, COST_BINS, 0, st>>>(w.hist, w.nactive, w.cur);
     k_fill_lists<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs,
                                      w.act_offs, w.nactive, w.items, w.slot, w.cur,

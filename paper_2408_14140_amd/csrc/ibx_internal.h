@@ -169,6 +169,38 @@ __device__ inline int axis_weights_d(double s, T* w, T* dw)
     return b;
 }
 
+// ---------------------------------------------------------------- scans
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+// Up to this many tiles, each workgroup of the add pass sums the tile totals
+// before its own tile itself, instead of a second scan over the totals (two
+// launches fewer; the sums grow with the square of the tile count).
+constexpr int64_t SCAN_FUSE = 64;
+
+// Sum of a[0 .. m) over the workgroup; every thread gets it.  Called by all
+// threads of the workgroup.
+__device__ inline int32_t group_sum(const int32_t* a, int64_t m)
+{
+    __shared__ int32_t part[SCAN_THREADS / 64];
+    int32_t s = 0;
+    for (int64_t k = threadIdx.x; k < m; k += SCAN_THREADS)
+        s += a[k];
+    for (int off = 32; off > 0; off >>= 1)
+        s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    int32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_THREADS / 64; ++w)
+        tot += part[w];
+    __syncthreads();
+    return tot;
+}
+
 // ---------------------------------------------------------------- host side
 
 Grid make_grid(const ib_level* lv);
