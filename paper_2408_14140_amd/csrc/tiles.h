@@ -419,7 +419,8 @@ __device__ inline uint64_t drop_low_bits(uint64_t m, int s)
 // of the tile and stores it straight to the slot (rows are contiguous there).
 // LDS stays near 5.9 KB so that 24 or more workgroups fit on a CU.
 // (FP32: registers capped so that 6 waves fit per SIMD, the residency that the
-// latency-bound visit chain wants; no spills at that cap.)
+// latency-bound visit chain wants; at that cap the 4-point kernel spills two
+// registers, which costs less than the prefetch of the source indices saves.)
 template <typename T, int P>
 __global__ void __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8)))
@@ -458,11 +459,16 @@ k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactiv
     const int per = (n_act + NXCD - 1) / NXCD;
     const int x = blockIdx.x % NXCD, nwg = gridDim.x / NXCD, wg = blockIdx.x / NXCD;
     const int s_end = min(n_act, (x + 1) * per);
-    for (int r = 0;; ++r) {
-        const int idx = x * per + r * nwg + ((r & 1) ? nwg - 1 - wg : wg);
-        if (idx >= s_end)
-            break;
-        const int4 ent = sent[idx];     // (slot, tile, first source, end of sources)
+    auto entry = [&](int r) { return x * per + r * nwg + ((r & 1) ? nwg - 1 - wg : wg); };
+    // The source indices of each batch are loaded one batch ahead (the next
+    // tile's first batch after a tile's last), so the visits hide that load.
+    int idx = entry(0);
+    int4 ent = idx < s_end ? sent[idx] : make_int4(0, 0, 0, 0);
+    int pf = idx < s_end && ent.z + lane < ent.w ? src_idx[ent.z + lane] : 0;
+    for (int r = 0; idx < s_end; ++r) {
+        // (slot, tile, first source, end of sources) of this and the next tile
+        const int nidx = entry(r + 1);
+        const int4 nent = nidx < s_end ? sent[nidx] : make_int4(0, 0, 0, 0);
         const int a = ent.x;
         int lo[3];
         tile_coords(g, ent.y, lo);
@@ -473,9 +479,13 @@ k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactiv
         const int s0 = ent.z, s1 = ent.w;
         for (int sbat = s0; sbat < s1; sbat += 64) {
             const int sidx = sbat + lane;
+            const int cur = pf;
+            const bool more = sbat + 64 < s1;
+            const int n0 = more ? sbat + 64 : nent.z, n1 = more ? s1 : nent.w;
+            pf = n0 + lane < n1 ? src_idx[n0 + lane] : 0;
             int by = 64, bz = 64;       // no row for lanes past the list
             if (sidx < s1) {
-                const int64_t i = src_idx[sidx];
+                const int64_t i = cur;
                 const typename Vec4<T>::type gq = s.geo[i];
                 const typename Vec4<T>::type Fv = s.f4[i];
                 int rb[3];
@@ -600,5 +610,7 @@ k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactiv
             *reinterpret_cast<typename Vec4<T>::type*>(gs + c * TILE_CELLS) = v0;
             *reinterpret_cast<typename Vec4<T>::type*>(gs + c * TILE_CELLS + 4) = v1;
         }
+        idx = nidx;
+        ent = nent;
     }
 }
