@@ -115,10 +115,15 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     const T* src = MODE == 0 ? u0 : G;
     const bool paired = true;   // tile slots: rows start on multiples of 8 elements
     const Slab sl = xcd_slab(n_items);
+    // the neighbour offsets of each item are loaded one item ahead, so the
+    // staging and compute of an item hide the next one's load
+    int64_t pnb = sl.begin < sl.end && tid < 27 ? nbase[(int64_t)sl.begin * 27 + tid] : 0;
     for (int it = sl.begin; it < sl.end; it += sl.stride) {
         if (tid < 27)
-            nb[tid] = nbase[(int64_t)it * 27 + tid];
+            nb[tid] = pnb;
         __syncthreads();
+        if (tid < 27 && it + sl.stride < sl.end)
+            pnb = nbase[(int64_t)(it + sl.stride) * 27 + tid];
         const Item item = items[it];
         int lo[3];
         tile_coords(g, item.tile, lo);
