@@ -12,9 +12,10 @@ import os
 
 import numpy as np
 
-from .build import LIB, build
+from .build import LIB, LIB_OMP, build
 
 _lib = None
+_lib_omp = None
 
 _d = C.c_double
 _i32 = C.c_int32
@@ -27,13 +28,38 @@ class Grid(C.Structure):
                 ("periodic", C.c_int32 * 3)]
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB):
-        build()
-    lib = C.CDLL(LIB)
+def _load(threads: int = 0):
+    """The single-threaded oracle, or with threads > 0 the OpenMP build of the
+    same source set to that many threads (identical results)."""
+    global _lib, _lib_omp
+    if threads > 0:
+        if _lib_omp is None:
+            if not os.path.exists(LIB_OMP):
+                build()
+            _lib_omp = _setup(C.CDLL(LIB_OMP))
+        _lib_omp.ibo_threads(int(threads))
+        return _lib_omp
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        _lib = _setup(C.CDLL(LIB))
+    return _lib
+
+
+def threads_available() -> int:
+    """Threads the OpenMP build runs with by default (OMP_NUM_THREADS, else the
+    host's cores)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(LIB_OMP):
+            build()
+        _lib_omp = _setup(C.CDLL(LIB_OMP))
+    return int(_lib_omp.ibo_threads(0))
+
+
+def _setup(lib):
+    lib.ibo_threads.restype = C.c_int
+    lib.ibo_threads.argtypes = [C.c_int]
     lib.ibo_phi.restype = _d
     lib.ibo_phi.argtypes = [C.c_int, _d]
     lib.ibo_dphi.restype = _d
@@ -70,7 +96,6 @@ def _load():
     lib.ibo_advect_markers.argtypes = [_i64, _p, _p, _p, _p, _p, _p, _p, _p, _d, _p, _p, _p]
     lib.ibo_collision_forces.restype = None
     lib.ibo_collision_forces.argtypes = [_i32, _p, _p, _p, _d, _d, _d, _p, _p]
-    _lib = lib
     return lib
 
 
@@ -180,8 +205,8 @@ def desired_velocity(m: Markers, xc, up, om) -> np.ndarray:
     return Ud
 
 
-def interp(g: Grid, P: int, m: Markers, u) -> np.ndarray:
-    lib = _load()
+def interp(g: Grid, P: int, m: Markers, u, threads: int = 0) -> np.ndarray:
+    lib = _load(threads)
     u = _f64(u)
     U = np.zeros((m.nl, 3))
     rc = lib.ibo_interp(C.byref(g), int(P), m.nl, _ptr(m.x), _ptr(m.y), _ptr(m.z), _ptr(u),
@@ -191,8 +216,8 @@ def interp(g: Grid, P: int, m: Markers, u) -> np.ndarray:
     return U
 
 
-def spread(g: Grid, P: int, m: Markers, F) -> np.ndarray:
-    lib = _load()
+def spread(g: Grid, P: int, m: Markers, F, threads: int = 0) -> np.ndarray:
+    lib = _load(threads)
     F = _f64(F)
     f = np.zeros((3, g.n[2], g.n[1], g.n[0]))
     rc = lib.ibo_spread(C.byref(g), int(P), m.nl, _ptr(m.x), _ptr(m.y), _ptr(m.z),
@@ -203,8 +228,10 @@ def spread(g: Grid, P: int, m: Markers, F) -> np.ndarray:
 
 
 def multidirect(g: Grid, P: int, ns: int, dt: float, m: Markers, xc, up, om, u0,
-                order: str = "jacobi", history: bool = False, residuals: bool = True) -> dict:
-    lib = _load()
+                order: str = "jacobi", history: bool = False, residuals: bool = True,
+                threads: int = 0) -> dict:
+    """Algorithm 1; threads > 0 runs the OpenMP build (same bits)."""
+    lib = _load(threads)
     xc, up, om, u0 = _f64(xc), _f64(up), _f64(om), _f64(u0)
     ustar = np.zeros_like(u0)
     f = np.zeros_like(u0)

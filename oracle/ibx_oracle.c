@@ -8,10 +8,16 @@
  * loaded solely by the test-suite, the smoke check and the CPU-baseline leg
  * of the benchmark.  It shares no code, header or table with the GPU library.
  *
- * Everything is single-threaded FP64 over a global cell-centred grid
- * u[c][z][y][x] (x fastest) of n[0] x n[1] x n[2] cells of size h starting at
- * lo.  Loops follow the paper's equations term by term; nothing is blocked,
- * fused or reordered.
+ * Everything is FP64 over a global cell-centred grid u[c][z][y][x] (x
+ * fastest) of n[0] x n[1] x n[2] cells of size h starting at lo.  Loops
+ * follow the paper's equations term by term; nothing is blocked, fused or
+ * reordered.  The default build (liboracle.so) is single-threaded.  The same
+ * source compiled with OpenMP (liboracle_omp.so) splits the loops of
+ * Algorithm 1 without changing any sum's order: interpolation and the
+ * velocity correction are independent per marker and per cell; spreading
+ * gives each thread a slab of z planes, and every thread visits all markers
+ * in index order and adds only into its own planes, so each cell receives
+ * its contributions in the serial order.  Both builds give identical bits.
  *
  * Readings of points the paper leaves open (kept identical in the GPU library
  * by its own code):
@@ -36,6 +42,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define IBO_PI 3.14159265358979323846
 
@@ -122,6 +131,33 @@ static int64_t wrap(int64_t i, int32_t n)
 {
     int64_t m = i % n;
     return m < 0 ? m + n : m;
+}
+
+/* Threads of the loops below: sets the count (OpenMP build) and returns it;
+ * always 1 in the single-threaded build. */
+int ibo_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+/* z planes [z0, z1) owned by the calling thread inside a parallel region
+ * (the whole grid outside one, or in the single-threaded build). */
+static void thread_slab(const ibo_grid* g, int64_t* z0, int64_t* z1)
+{
+#ifdef _OPENMP
+    int64_t t = omp_get_thread_num(), nt = omp_get_num_threads();
+#else
+    int64_t t = 0, nt = 1;
+#endif
+    *z0 = (int64_t)g->n[2] * t / nt;
+    *z1 = (int64_t)g->n[2] * (t + 1) / nt;
 }
 
 /* Grid coordinate s = (X - lo)/h of one axis (cell i spans [i, i+1)). */
@@ -364,10 +400,12 @@ static int interp_one(const ibo_grid* g, int P, double X, double Y, double Z,
 int ibo_interp(const ibo_grid* g, int P, int64_t nl, const double* x, const double* y,
                const double* z, const double* u, double* U)
 {
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t l = 0; l < nl; ++l)
         if (interp_one(g, P, x[l], y[l], z[l], u, U + 3 * l))
-            return -1;
-    return 0;
+            bad = 1;
+    return bad ? -1 : 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -376,8 +414,10 @@ int ibo_interp(const ibo_grid* g, int P, int64_t nl, const double* x, const doub
 /* f is zeroed first: f^m is built from scratch each iteration.            */
 /* ------------------------------------------------------------------------ */
 
+/* Adds marker l's contribution to the cells of f whose z plane lies in
+ * [z0, z1) (the calling thread's slab). */
 static int spread_add(const ibo_grid* g, int P, double X, double Y, double Z,
-                      const double V[3], double scale, double* f)
+                      const double V[3], double scale, double* f, int64_t z0, int64_t z1)
 {
     int64_t ci[3][4];
     double w[3][4];
@@ -386,7 +426,9 @@ static int spread_add(const ibo_grid* g, int P, double X, double Y, double Z,
         if (stencil_axis(g, P, a, P3[a], ci[a], w[a], NULL))
             return -1;
     int64_t N = cells_total(g);
-    for (int k = 0; k < P; ++k)
+    for (int k = 0; k < P; ++k) {
+        if (ci[2][k] < z0 || ci[2][k] >= z1)
+            continue;
         for (int j = 0; j < P; ++j)
             for (int i = 0; i < P; ++i) {
                 double wt = w[0][i] * w[1][j] * w[2][k] * scale;
@@ -394,20 +436,38 @@ static int spread_add(const ibo_grid* g, int P, double X, double Y, double Z,
                 for (int c = 0; c < 3; ++c)
                     f[c * N + q] += V[c] * wt;
             }
+    }
     return 0;
+}
+
+/* f = sum over markers [l0, l1) of F_l dV_l delta_h, from zero.  Each thread
+ * owns a slab of z planes and visits every marker in index order. */
+static int spread_range(const ibo_grid* g, int P, int64_t l0, int64_t l1, const double* x,
+                        const double* y, const double* z, const int32_t* pid,
+                        const double* dv, const double* F, double* f)
+{
+    int64_t N = cells_total(g);
+    double h3 = g->h * g->h * g->h;
+    int bad = 0;
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < 3 * N; ++q)
+        f[q] = 0.0;
+#pragma omp parallel reduction(| : bad)
+    {
+        int64_t z0, z1;
+        thread_slab(g, &z0, &z1);
+        for (int64_t l = l0; l < l1; ++l)
+            if (spread_add(g, P, x[l], y[l], z[l], F + 3 * l, dv[pid[l]] / h3, f, z0, z1))
+                bad = 1;
+    }
+    return bad ? -1 : 0;
 }
 
 int ibo_spread(const ibo_grid* g, int P, int64_t nl, const double* x, const double* y,
                const double* z, const int32_t* pid, const double* dv, const double* F,
                double* f)
 {
-    int64_t N = cells_total(g);
-    double h3 = g->h * g->h * g->h;
-    memset(f, 0, sizeof(double) * (size_t)(3 * N));
-    for (int64_t l = 0; l < nl; ++l)
-        if (spread_add(g, P, x[l], y[l], z[l], F + 3 * l, dv[pid[l]] / h3, f))
-            return -1;
-    return 0;
+    return spread_range(g, P, 0, nl, x, y, z, pid, dv, F, f);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -424,15 +484,23 @@ static double residual(const ibo_grid* g, int P, int64_t l0, int64_t l1, const d
                        const double* y, const double* z, const int32_t* pid,
                        const double* dv, const double* Ud, const double* u)
 {
-    double acc = 0.0;
+    /* the errors are formed per marker (in parallel), then summed in index order */
+    int64_t n = l1 - l0;
+    double* e = (double*)malloc(sizeof(double) * (size_t)(3 * (n > 0 ? n : 1)));
+#pragma omp parallel for schedule(static)
     for (int64_t l = l0; l < l1; ++l) {
         double U[3];
         interp_one(g, P, x[l], y[l], z[l], u, U);
-        for (int c = 0; c < 3; ++c) {
-            double e = Ud[3 * l + c] - U[c];
-            acc += dv[pid[l]] * e * e;
-        }
+        for (int c = 0; c < 3; ++c)
+            e[3 * (l - l0) + c] = Ud[3 * l + c] - U[c];
     }
+    double acc = 0.0;
+    for (int64_t l = l0; l < l1; ++l)
+        for (int c = 0; c < 3; ++c) {
+            double ec = e[3 * (l - l0) + c];
+            acc += dv[pid[l]] * ec * ec;
+        }
+    free(e);
     return sqrt(acc);
 }
 
@@ -445,31 +513,37 @@ static int multidirect_range(const ibo_grid* g, int P, int ns, double dt, int64_
                              double* Fhist, int64_t nl, double* resid)
 {
     int64_t N = cells_total(g);
-    double h3 = g->h * g->h * g->h;
-    memcpy(ucur, ustart, sizeof(double) * (size_t)(3 * N));
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < 3 * N; ++q)
+        ucur[q] = ustart[q];
     for (int64_t l = l0; l < l1; ++l)
         F[3 * l] = F[3 * l + 1] = F[3 * l + 2] = 0.0;
     if (resid)
         resid[0] = residual(g, P, l0, l1, x, y, z, pid, dv, Ud, ucur);
     for (int m = 1; m <= ns; ++m) {
         /* interpolate u^(m-1) and update the Lagrangian force */
+        int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
         for (int64_t l = l0; l < l1; ++l) {
             double U[3];
-            if (interp_one(g, P, x[l], y[l], z[l], ucur, U))
-                return -1;
+            if (interp_one(g, P, x[l], y[l], z[l], ucur, U)) {
+                bad = 1;
+                continue;
+            }
             for (int c = 0; c < 3; ++c)
                 F[3 * l + c] = F[3 * l + c] + (Ud[3 * l + c] - U[c]) / dt;
         }
+        if (bad)
+            return -1;
         if (Fhist)
             for (int64_t l = l0; l < l1; ++l)
                 for (int c = 0; c < 3; ++c)
                     Fhist[((int64_t)(m - 1) * nl + l) * 3 + c] = F[3 * l + c];
         /* spread F^m from scratch */
-        memset(fpart, 0, sizeof(double) * (size_t)(3 * N));
-        for (int64_t l = l0; l < l1; ++l)
-            if (spread_add(g, P, x[l], y[l], z[l], F + 3 * l, dv[pid[l]] / h3, fpart))
-                return -1;
+        if (spread_range(g, P, l0, l1, x, y, z, pid, dv, F, fpart))
+            return -1;
         /* correct the velocity: u^(m) = u^(0) + dt f^m */
+#pragma omp parallel for schedule(static)
         for (int64_t q = 0; q < 3 * N; ++q)
             ucur[q] = ustart[q] + dt * fpart[q];
         if (resid)
@@ -712,7 +786,7 @@ int ibo_reverse(const ibo_grid* g, int P, int ns, double dt, int32_t np, const i
         }
         memset(au, 0, fb);
         for (int64_t l = 0; l < nl && rc == 0; ++l) {
-            rc |= spread_add(g, P, x[l], y[l], z[l], Ub + 3 * l, 1.0, au);
+            rc |= spread_add(g, P, x[l], y[l], z[l], Ub + 3 * l, 1.0, au, 0, g->n[2]);
             rc |= grad_pos(g, P, x[l], y[l], z[l], uprev, Ub + 3 * l, 1.0, gX + 3 * l);
         }
         memset(af, 0, fb);
