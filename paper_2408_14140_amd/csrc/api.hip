@@ -5,6 +5,25 @@
 
 #include "paths.h"
 
+// Launch sequence key: every argument that shapes the enqueued work -- each
+// field of the level, particles, markers and buckets that reaches a kernel
+// or the host-side launch set-up, the loop's scalars, every buffer and the
+// stream.  Zeroed first and filled field by field, so padding never differs.
+struct GraphKey {
+    int32_t n[3], periodic[3], box, ngrow, nbox, np, ns, pad;
+    double h, lo[3], dt;
+    const void* box_lo;
+    const void* box_lut;
+    const void* part[4];
+    int64_t nl;
+    const void* mark[6];
+    const void* buck[8];
+    int64_t src_cap;
+    const void* bufs[7];
+    size_t ws_bytes;
+    void* stream;
+};
+
 struct ib_plan {
     int P;
     ib_prec prec;
@@ -16,7 +35,7 @@ struct ib_plan {
     // launch sequence captured for one argument set
     hipGraph_t graph;
     hipGraphExec_t exec;
-    uint64_t key[24];
+    GraphKey key;
     int has_graph;
     ibx::Profiler* prof;
 };
@@ -245,39 +264,55 @@ static int check_common(const ib_plan* plan, const ib_level* lv, const ib_partic
     return IB_OK;
 }
 
-// Launch sequence key: every argument that shapes the enqueued work.
-static void make_key(uint64_t* k, const ib_level* lv, const ib_particles* p, const ib_markers* m,
-                     const ib_buckets* b, int32_t ns, double dt, const void* u0, void* ustar,
-                     void* f, void* F, double* resid, void* Fhist, void* ws, size_t ws_bytes,
-                     void* stream)
+static void make_key(GraphKey* k, const ib_level* lv, const ib_particles* p,
+                     const ib_markers* m, const ib_buckets* b, int32_t ns, double dt,
+                     const void* u0, void* ustar, void* f, void* F, double* resid, void* Fhist,
+                     void* ws, size_t ws_bytes, void* stream)
 {
-    memset(k, 0, sizeof(uint64_t) * 24);
-    uint64_t dtb;
-    memcpy(&dtb, &dt, 8);
-    k[0] = (uint64_t)lv->n[0] | ((uint64_t)lv->n[1] << 21) | ((uint64_t)lv->n[2] << 42);
-    k[1] = (uint64_t)(uintptr_t)lv->box_lut;
-    k[2] = (uint64_t)lv->nbox | ((uint64_t)lv->box << 32);
-    memcpy(&k[3], &lv->h, 8);
-    k[4] = (uint64_t)m->nl;
-    k[5] = (uint64_t)(uintptr_t)m->x ^ ((uint64_t)(uintptr_t)m->pid << 1);
-    k[6] = (uint64_t)(uintptr_t)p->xc ^ ((uint64_t)(uintptr_t)p->up << 1);
-    k[7] = (uint64_t)(uintptr_t)b->perm ^ ((uint64_t)(uintptr_t)b->src_idx << 1);
-    k[8] = (uint64_t)ns;
-    k[9] = dtb;
-    k[10] = (uint64_t)(uintptr_t)u0;
-    k[11] = (uint64_t)(uintptr_t)ustar;
-    k[12] = (uint64_t)(uintptr_t)f;
-    k[13] = (uint64_t)(uintptr_t)F;
-    k[14] = (uint64_t)(uintptr_t)resid;
-    k[15] = (uint64_t)(uintptr_t)Fhist;
-    k[16] = (uint64_t)(uintptr_t)ws;
-    k[17] = (uint64_t)ws_bytes;
-    k[18] = (uint64_t)(uintptr_t)stream;
-    k[19] = (uint64_t)(uintptr_t)m->y ^ ((uint64_t)(uintptr_t)m->z << 1);
-    k[20] = (uint64_t)(uintptr_t)m->dv ^ ((uint64_t)(uintptr_t)m->offs << 1);
-    k[21] = (uint64_t)(uintptr_t)p->om ^ ((uint64_t)(uintptr_t)p->d << 1);
-    k[22] = (uint64_t)(uintptr_t)b->tile_offs ^ ((uint64_t)(uintptr_t)b->src_offs << 1);
-    memcpy(&k[23], lv->lo, 8);
+    memset(k, 0, sizeof(*k));
+    for (int a = 0; a < 3; ++a) {
+        k->n[a] = lv->n[a];
+        k->periodic[a] = lv->periodic[a];
+        k->lo[a] = lv->lo[a];
+    }
+    k->box = lv->box;
+    k->ngrow = lv->ngrow;
+    k->nbox = lv->nbox;
+    k->h = lv->h;
+    k->box_lo = lv->box_lo;
+    k->box_lut = lv->box_lut;
+    k->np = p->np;
+    k->part[0] = p->xc;
+    k->part[1] = p->d;
+    k->part[2] = p->up;
+    k->part[3] = p->om;
+    k->nl = m->nl;
+    k->mark[0] = m->offs;
+    k->mark[1] = m->x;
+    k->mark[2] = m->y;
+    k->mark[3] = m->z;
+    k->mark[4] = m->pid;
+    k->mark[5] = m->dv;
+    k->buck[0] = b->cell;
+    k->buck[1] = b->tileid;
+    k->buck[2] = b->base;
+    k->buck[3] = b->perm;
+    k->buck[4] = b->tile_offs;
+    k->buck[5] = b->src_offs;
+    k->buck[6] = b->src_idx;
+    k->buck[7] = b->flag;
+    k->src_cap = b->src_cap;
+    k->ns = ns;
+    k->dt = dt;
+    k->bufs[0] = u0;
+    k->bufs[1] = ustar;
+    k->bufs[2] = f;
+    k->bufs[3] = F;
+    k->bufs[4] = resid;
+    k->bufs[5] = Fhist;
+    k->bufs[6] = ws;
+    k->ws_bytes = ws_bytes;
+    k->stream = stream;
 }
 
 extern "C" int ib_multidirect_force(ib_plan* plan, const ib_level* lv, const ib_particles* p,
@@ -310,9 +345,9 @@ extern "C" int ib_multidirect_force(ib_plan* plan, const ib_level* lv, const ib_
     if (!plan->use_graph || !stream || plan->prof || cap != hipStreamCaptureStatusNone)
         return batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0, ustar, f, F,
                                    resid, Fhist, ws, ws_bytes, st);
-    uint64_t key[24];
-    make_key(key, lv, p, m, b, ns, dt, u0, ustar, f, F, resid, Fhist, ws, ws_bytes, stream);
-    if (!plan->has_graph || memcmp(key, plan->key, sizeof(key)) != 0) {
+    GraphKey key;
+    make_key(&key, lv, p, m, b, ns, dt, u0, ustar, f, F, resid, Fhist, ws, ws_bytes, stream);
+    if (!plan->has_graph || memcmp(&key, &plan->key, sizeof(key)) != 0) {
         drop_graph(plan);
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
@@ -339,7 +374,7 @@ extern "C" int ib_multidirect_force(ib_plan* plan, const ib_level* lv, const ib_
         }
         plan->graph = graph;
         plan->exec = exec;
-        memcpy(plan->key, key, sizeof(key));
+        memcpy(&plan->key, &key, sizeof(key));
         plan->has_graph = 1;
     }
     hipError_t e = hipGraphLaunch(plan->exec, st);

@@ -69,3 +69,46 @@ def test_captured_step_replays_match_eager(dev, use_graph):
         torch.cuda.synchronize()
         for k, (a, e) in enumerate(zip(state(), ref)):
             assert same(a, e), (r, k)
+
+
+def test_plan_graph_keys_on_every_level_field(dev):
+    """A use_graph plan called with levels that differ only in lo[1] or lo[2]
+    (same buffers, same stream) must not replay the graph captured for
+    another level: each call equals an eager plan's bit for bit."""
+    import dataclasses
+
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    announce("graph key: levels differing only in lo")
+    wl = small_workload(32, 16, 4, 3, 5)
+    c = Case(wl, dev)
+    h = c.lev.h
+    levels = [c.dl,
+              dataclasses.replace(c.dl, lo=(c.dl.lo[0], c.dl.lo[1], c.dl.lo[2] + 0.37 * h)),
+              dataclasses.replace(c.dl, lo=(c.dl.lo[0], c.dl.lo[1] - 0.21 * h, c.dl.lo[2]))]
+    m = ibx.build_markers(c.dl, c.parts)
+    b = ibx.bucket(c.dl, m, wl.delta)
+    u0 = c.u0_boxes(torch.float32)
+    u, f = torch.empty_like(u0), torch.zeros_like(u0)
+    F = torch.zeros((m.nl, 3), dtype=torch.float32, device=dev)
+    graphed = ibx.Plan(wl.delta, torch.float32, ibx.IB_PATH_BATCHED, use_graph=True)
+    eager = ibx.Plan(wl.delta, torch.float32, ibx.IB_PATH_BATCHED, use_graph=False)
+    stream = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(stream):
+        for rep in range(2):
+            for k, lv in enumerate(levels):
+                ibx.bucket_into(lv, m, wl.delta, b)
+                res = []
+                for plan in (graphed, eager):
+                    u.copy_(u0)
+                    f.zero_()
+                    plan.multidirect_force(lv, c.parts, m, b, wl.ns, wl.dt, u, ustar=u, f=f, F=F)
+                    stream.synchronize()
+                    res.append((u.nan_to_num(0.0).clone(), f.clone(), F.clone()))
+                for a, e in zip(*res):
+                    assert torch.equal(a, e), (rep, k)
+                outs.append(res[1][2])
+    # the levels really differ
+    assert not torch.equal(outs[0], outs[1]) and not torch.equal(outs[0], outs[2])
