@@ -17,8 +17,11 @@
  *          a negative ib_status is returned synchronously and nothing runs.
  *          A failed kernel launch returns IB_EHIP (hipGetLastError text via
  *          ib_last_hip_error).  Conditions only the device can see (a marker
- *          stencil outside the covered boxes) are reported through device
- *          flag words that the caller reads after synchronizing.
+ *          stencil outside the covered boxes, a source-list overflow) are
+ *          reported through device flag words that the caller reads after
+ *          synchronizing; every call made with a flagged bucket set writes
+ *          NaN into all of its outputs (checked on the device, no host
+ *          synchronization), so a wrong result never looks valid.
  * Grid:    the finest AMR level: n[0] x n[1] x n[2] cells of edge h whose low
  *          corner is lo (Sec. 3.1: IB markers live on the finest level only).
  *          It is tiled into cubic boxes of `box` cells; only covered boxes
@@ -135,8 +138,10 @@ int ib_desired_velocity(const ib_particles* p, const ib_markers* m, ib_prec prec
 /* every tile the ascending list of sorted positions whose stencil cells   */
 /* touch it.  Not in the paper, which treats one particle at a time        */
 /* (Sec. 3.1); integer outputs are deterministic.  flag[0] counts markers   */
-/* whose stencil leaves the covered boxes or a bounded axis; such markers   */
-/* make every later call return garbage for them.                          */
+/* whose stencil leaves the covered boxes or a bounded axis, flag[1] is set */
+/* when src_idx overflows src_cap; ib_spread, ib_multidirect_force,        */
+/* ib_plan_autotune and ib_multidirect_backward called with such a set      */
+/* write NaN into every output.                                            */
 /* ---------------------------------------------------------------------- */
 
 /* Device workspace of ib_bucket in bytes: grows with nl and with the level's
@@ -149,7 +154,8 @@ int ib_bucket(const ib_level* lv, const ib_markers* m, ib_delta delta, const ib_
 /* a4  Velocity interpolation, Algorithm 1 first sub-step:                  */
 /*     U_l = sum_x u(x) delta_h(x - X_l) h^3.                               */
 /* u: field in the box layout; U: device [nl][3].  One thread per marker,   */
-/* FP64 or FP32 arithmetic as prec.                                         */
+/* FP64 or FP32 arithmetic as prec.  A marker whose stencil reaches a cell  */
+/* off a bounded axis or in an uncovered box gets U = NaN.                  */
 /* ---------------------------------------------------------------------- */
 int ib_interp(const ib_level* lv, const ib_markers* m, ib_delta delta, ib_prec prec,
               const void* u, void* U, void* stream);
@@ -159,7 +165,8 @@ int ib_interp(const ib_level* lv, const ib_markers* m, ib_delta delta, ib_prec p
 /*     f(x) = sum_l F_l delta_h(x - X_l) dV_l.                              */
 /* Writes f on every valid cell of every covered box (zero where no marker  */
 /* reaches).  Deterministic: each cell sums its tile's source list in       */
-/* order.  Needs the buckets of the same markers.                           */
+/* order.  Needs the buckets of the same markers; with a flagged bucket set */
+/* f is NaN on every valid cell.                                            */
 /* ---------------------------------------------------------------------- */
 int ib_spread(const ib_level* lv, const ib_markers* m, const ib_buckets* b, ib_delta delta,
               ib_prec prec, const void* F, void* f, void* stream);
@@ -174,6 +181,8 @@ int ib_spread(const ib_level* lv, const ib_markers* m, const ib_buckets* b, ib_d
 /*   resid (device double [ns+1] or NULL) receives                          */
 /*   sqrt(sum_l dV_l |U^d_l - (J u^(m))_l|^2), m = 0..ns.                     */
 /*   Fhist (device [ns][nl][3] or NULL) receives F^1..F^ns for the adjoint. */
+/*   With a flagged bucket set, ustar, f, F, resid and Fhist are all NaN    */
+/*   (ustar overwrites u0 when they alias).                                 */
 /* The plan fixes kernel width, precision and path (plain: one kernel per   */
 /* sub-step, straight from global memory; batched: tile-staged LDS kernels  */
 /* fed by the buckets, ustar may alias u0; needs at least 16 cells per axis */
@@ -248,7 +257,8 @@ int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_particles* p,
 /* the eight nodal values of phi_p = |x - X_p|/(D_p/2) - 1 (Sec. 4.1).       */
 /* Raw sums: the caller applies -rho_f and the time derivatives.  F and u   */
 /* in precision prec; out: device double [np][12].  flag (device int32 or   */
-/* NULL) is set to 1 when a particle's cells leave the covered boxes.  ws:   */
+/* NULL) is set to 1 when a particle's cells leave the covered boxes; such  */
+/* a particle gets NaN in all twelve of its sums.  ws:                      */
 /* device workspace of ib_reductions_workspace(np) bytes (partial sums).     */
 /* Deterministic: fixed-order tree reductions in FP64.                      */
 /* ---------------------------------------------------------------------- */
@@ -266,7 +276,7 @@ int ib_particle_reductions(const ib_level* lv, const ib_particles* p, const ib_m
 /* marker positions through phi').  Intermediate fields u^(m-1) are         */
 /* recomputed from u0 and Fhist, never stored.  ws sized by                 */
 /* ib_backward_workspace_bytes.  Runs on the plain kernels for either plan  */
-/* path.                                                                    */
+/* path.  With a flagged bucket set every gradient output is NaN.           */
 /* ---------------------------------------------------------------------- */
 size_t ib_backward_workspace_bytes(const ib_plan* plan, const ib_level* lv, int64_t nl);
 int ib_multidirect_backward(ib_plan* plan, const ib_level* lv, const ib_particles* p,
@@ -351,7 +361,8 @@ int ib_particle_levels(const ib_level* lv, const ib_particles* p, ib_delta delta
 /* else IB_EUNSUPPORTED).  Markers must be contiguous per particle as given */
 /* by m->offs (pid is not read).  flag (device int32 [2] or NULL) receives  */
 /* the OR of the per-level bucketing flags (ib_buckets.flag).  Batched plans */
-/* only (IB_EUNSUPPORTED otherwise); no graph replay, no residuals.  Reads  */
+/* only (IB_EUNSUPPORTED otherwise); no graph replay, no residuals.  When a */
+/* level's bucketing is flagged, ustar, f and F are all NaN.  Reads          */
 /* the level boundaries back once: synchronizes the stream (do not capture). */
 /* ws: device workspace of ib_sequential_workspace_bytes(plan, lv, np, nl,   */
 /* ns) bytes.  IB_EINVAL (after that synchronization, nothing else run) for */

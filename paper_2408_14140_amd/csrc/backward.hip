@@ -273,14 +273,28 @@ int multidirect_backward(const Grid& g, int P, ib_prec prec, const ib_particles*
                          const void* gF, void* gu0, double* gup, double* gom, double* gX,
                          void* ws, size_t ws_bytes, hipStream_t st)
 {
+    int rc;
     if (prec == IB_F64)
-        return run_backward<double>(g, P, p, m, b, ns, dt, (const double*)u0,
-                                    (const double*)Fhist, (const double*)gus, (const double*)gf,
-                                    (const double*)gF, (double*)gu0, gup, gom, gX, ws, ws_bytes,
-                                    st);
-    return run_backward<float>(g, P, p, m, b, ns, dt, (const float*)u0, (const float*)Fhist,
-                               (const float*)gus, (const float*)gf, (const float*)gF,
-                               (float*)gu0, gup, gom, gX, ws, ws_bytes, st);
+        rc = run_backward<double>(g, P, p, m, b, ns, dt, (const double*)u0,
+                                  (const double*)Fhist, (const double*)gus, (const double*)gf,
+                                  (const double*)gF, (double*)gu0, gup, gom, gX, ws, ws_bytes,
+                                  st);
+    else
+        rc = run_backward<float>(g, P, p, m, b, ns, dt, (const float*)u0, (const float*)Fhist,
+                                 (const float*)gus, (const float*)gf, (const float*)gF,
+                                 (float*)gu0, gup, gom, gX, ws, ws_bytes, st);
+    if (rc)
+        return rc;
+    PoisonSet ps;
+    ps.field[0] = gu0;
+    ps.dvec[0] = gup;
+    ps.ndvec[0] = 3 * (int64_t)p->np;
+    ps.dvec[1] = gom;
+    ps.ndvec[1] = 3 * (int64_t)p->np;
+    ps.dvec[2] = gX;
+    ps.ndvec[2] = 3 * m->nl;
+    poison_if_flagged(b->flag, g, prec, ps, st);
+    return launch_status();
 }
 
 }  // namespace ibx

@@ -690,6 +690,24 @@ static void launch_interp(const BatchedCfg& cfg, hipStream_t st, const Grid& g, 
 #define IBX_PROF_END() \
     if (cfg.prof) cfg.prof->end(st)
 
+// Every output set to NaN when the bucket set is flagged (checked on the
+// device at the end of the loop; nothing is read back).
+template <typename T>
+static void poison_outputs(const Grid& g, const ib_buckets* b, T* ustar, T* f, T* F,
+                           double* resid, T* Fhist, int64_t nl, int ns, hipStream_t st)
+{
+    PoisonSet ps;
+    ps.field[0] = ustar;
+    ps.field[1] = f;
+    ps.vec[0] = F;
+    ps.nvec[0] = 3 * nl;
+    ps.vec[1] = Fhist;
+    ps.nvec[1] = 3 * nl * ns;
+    ps.dvec[0] = resid;
+    ps.ndvec[0] = ns + 1;
+    poison_if_flagged(b->flag, g, sizeof(T) == 8 ? IB_F64 : IB_F32, ps, st);
+}
+
 template <typename T, int P>
 static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles* p,
                        const ib_markers* m, const ib_buckets* b, int ns, double dt,
@@ -711,6 +729,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         launch_finalize<T>(gfin, st, g, w.slot, w.G, u0, ustar, f, dt, 0, f_acc);
         if (resid)
             k_zero<double><<<1, 64, 0, st>>>(ns + 1, resid);
+        poison_outputs(g, b, ustar, f, F, resid, Fhist, nl, ns, st);
         return launch_status();
     }
     IBX_PROF_BEGIN(PK_PREP);
@@ -754,6 +773,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         // no iteration: ustar = u0, f = 0, F = 0
         launch_finalize<T>(gfin, st, g, w.slot, w.G, u0, ustar, f, dt, 0, f_acc);
         k_zero<T><<<gm, 256, 0, st>>>(3 * nl, F);
+        poison_outputs(g, b, ustar, f, F, resid, Fhist, nl, ns, st);
         return launch_status();
     }
     if (Fhist)
@@ -789,6 +809,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         IBX_PROF_END();
         sum_to(w.e2, nl, w.part, resid + ns, true, st);
     }
+    poison_outputs(g, b, ustar, f, F, resid, Fhist, nl, ns, st);
     return launch_status();
 }
 

@@ -136,6 +136,56 @@ void desired_velocity(const ib_particles* p, const ib_markers* m, ib_prec prec, 
                                                       p->up, p->om, (float*)Ud);
 }
 
+// ------------------------------------------------------------------ flagged buckets
+
+// Every output of a call made with a flagged bucket set (a stencil that leaves
+// the covered boxes or a bounded axis, or an overflowing source list) is set
+// to NaN, so a wrong result never looks like a valid one.  Every thread reads
+// the two flag words; with both clear the kernel does nothing.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_poison(const int32_t* __restrict__ flag, Grid g, PoisonSet ps)
+{
+    if ((flag[0] | flag[1]) == 0)
+        return;
+    const T nan = (T)__builtin_nan("");
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_box = (int64_t)g.box * g.box * g.box;
+    for (int k = 0; k < 2; ++k) {
+        T* fld = (T*)ps.field[k];
+        if (!fld)
+            continue;
+        for (int64_t q = t0; q < per_box * g.nbox; q += stride) {
+            const int64_t bid = q / per_box, r = q - bid * per_box;
+            const int lx = (int)(r % g.box) + g.ngrow;
+            const int ly = (int)((r / g.box) % g.box) + g.ngrow;
+            const int lz = (int)(r / ((int64_t)g.box * g.box)) + g.ngrow;
+            const int64_t off = bid * g.bstride + ((int64_t)lz * g.ext + ly) * g.ext + lx;
+            fld[off] = nan;
+            fld[off + g.cstride] = nan;
+            fld[off + 2 * g.cstride] = nan;
+        }
+    }
+    for (int k = 0; k < 2; ++k)
+        for (int64_t q = t0; ps.vec[k] && q < ps.nvec[k]; q += stride)
+            ((T*)ps.vec[k])[q] = nan;
+    for (int k = 0; k < 4; ++k)
+        for (int64_t q = t0; ps.dvec[k] && q < ps.ndvec[k]; q += stride)
+            ps.dvec[k][q] = __builtin_nan("");
+}
+
+void poison_if_flagged(const int32_t* flag, const Grid& g, ib_prec prec, const PoisonSet& ps,
+                       hipStream_t st)
+{
+    if (!flag)
+        return;
+    if (prec == IB_F64)
+        k_poison<double><<<512, 256, 0, st>>>(flag, g, ps);
+    else
+        k_poison<float><<<512, 256, 0, st>>>(flag, g, ps);
+}
+
 }  // namespace ibx
 
 using namespace ibx;

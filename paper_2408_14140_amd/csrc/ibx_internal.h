@@ -235,6 +235,20 @@ void lower_bounds(const int32_t* keys, int64_t n_max, const int32_t* n_dev, int3
 
 inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Outputs of a call set to NaN when its bucket set is flagged (flag[0] or
+// flag[1] nonzero on the device): up to two fields in the box layout (valid
+// cells only), two vectors in the field precision and four FP64 vectors.
+// Enqueue-only; no host synchronization.
+struct PoisonSet {
+    void* field[2] = {nullptr, nullptr};
+    void* vec[2] = {nullptr, nullptr};
+    int64_t nvec[2] = {0, 0};
+    double* dvec[4] = {nullptr, nullptr, nullptr, nullptr};
+    int64_t ndvec[4] = {0, 0, 0, 0};
+};
+void poison_if_flagged(const int32_t* flag, const Grid& g, ib_prec prec, const PoisonSet& ps,
+                       hipStream_t st);
+
 // Kernel classes timed by the optional per-plan profiler (see ib_plan_profile).
 enum ProfKind {
     PK_PREP = 0, PK_LISTS, PK_INTERP_U0, PK_SPREAD, PK_INTERP_G, PK_SPREAD_FINAL, PK_FILL,

@@ -37,19 +37,26 @@ k_interp_plain(Grid g, int64_t nl, const double* __restrict__ x, const double* _
             c[a][o] = resolve(g, a, b + o);
     }
     T acc0 = 0, acc1 = 0, acc2 = 0;
+    bool outside = false;     // a stencil cell off a bounded axis or in an uncovered box
     for (int k = 0; k < P; ++k)
         for (int j = 0; j < P; ++j)
             for (int i = 0; i < P; ++i) {
-                if ((c[0][i] | c[1][j] | c[2][k]) < 0)
+                if ((c[0][i] | c[1][j] | c[2][k]) < 0) {
+                    outside = true;
                     continue;
+                }
                 const int64_t off = cell_offset(g, c[0][i], c[1][j], c[2][k]);
-                if (off < 0)
+                if (off < 0) {
+                    outside = true;
                     continue;
+                }
                 const T wt = w[0][i] * w[1][j] * w[2][k];
                 acc0 += u[off] * wt;
                 acc1 += u[off + g.cstride] * wt;
                 acc2 += u[off + 2 * g.cstride] * wt;
             }
+    if (outside)
+        acc0 = acc1 = acc2 = (T)__builtin_nan("");
     U[3 * l + 0] = acc0;
     U[3 * l + 1] = acc1;
     U[3 * l + 2] = acc2;
@@ -374,6 +381,16 @@ static int plain_loop(const Grid& g, int P, const ib_particles* p, const ib_mark
             k_resid_only<T><<<gm, 256, 0, st>>>(nl, Ud, U, m->pid, m->dv, e2);
         sum_to(e2, nl, part, resid + ns, true, st);
     }
+    PoisonSet ps;
+    ps.field[0] = ustar;
+    ps.field[1] = f;
+    ps.vec[0] = F;
+    ps.nvec[0] = 3 * nl;
+    ps.vec[1] = Fhist;
+    ps.nvec[1] = 3 * nl * ns;
+    ps.dvec[0] = resid;
+    ps.ndvec[0] = ns + 1;
+    poison_if_flagged(b->flag, g, sizeof(T) == 8 ? IB_F64 : IB_F32, ps, st);
     return launch_status();
 }
 
@@ -418,6 +435,10 @@ extern "C" int ib_spread(const ib_level* lv, const ib_markers* m, const ib_bucke
         (m->nl > 0 && (!m->x || !m->y || !m->z || !m->pid || !m->dv || !F || !b->perm ||
                        !b->src_idx)))
         return IB_EINVAL;
-    plain_spread(make_grid(lv), (int)delta, prec, m, b, F, f, 1.0, 1, (hipStream_t)stream);
+    const Grid g = make_grid(lv);
+    plain_spread(g, (int)delta, prec, m, b, F, f, 1.0, 1, (hipStream_t)stream);
+    PoisonSet ps;
+    ps.field[0] = f;
+    poison_if_flagged(b->flag, g, prec, ps, (hipStream_t)stream);
     return launch_status();
 }

@@ -210,6 +210,8 @@ k_volume_partials(Grid g, const double* __restrict__ xc, const double* __restric
         if (id < 0) {
             if (flag)
                 atomicOr(flag, 1);
+            for (int q = 0; q < 6; ++q)
+                acc[q] = __builtin_nan("");
             return;
         }
         const int64_t off = (int64_t)id * g.bstride + ((int64_t)lzo * g.ext + lyo) * g.ext + lxo;
@@ -298,6 +300,12 @@ __global__ void k_particle_out(int64_t np, const double* __restrict__ part,
     double v;
     if (q < 6) {
         v = pp[RD_SLABS * 6 + q];
+        // a particle whose cells leave the covered boxes gets NaN in all 12
+        bool bad = false;
+        for (int sl = 0; sl < RD_SLABS; ++sl)
+            bad |= isnan(pp[sl * 6]);
+        if (bad)
+            v = __builtin_nan("");
     } else {
         v = 0.0;
         for (int sl = 0; sl < RD_SLABS; ++sl)

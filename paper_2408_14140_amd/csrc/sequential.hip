@@ -250,7 +250,7 @@ __global__ void k_or_flags(const int32_t* __restrict__ src, int32_t* __restrict_
 
 struct SeqWs {
     double *xc, *d, *up, *om, *dv;
-    int32_t *pord, *loffs, *err;
+    int32_t *pord, *loffs, *err, *anyflag;
     int64_t* noffs;
     double *x, *y, *z;
     int32_t *pid, *mmap;
@@ -275,6 +275,7 @@ static SeqWs carve_seq(const ib_level* lv, const Grid& g, ib_prec prec, int32_t 
     w.pord = cv.take<int32_t>(np);
     w.loffs = cv.take<int32_t>((size_t)np + 1);
     w.err = cv.take<int32_t>(1);
+    w.anyflag = cv.take<int32_t>(2);
     w.noffs = cv.take<int64_t>((size_t)np + 1);
     w.x = cv.take<double>(nl);
     w.y = cv.take<double>(nl);
@@ -333,6 +334,7 @@ int sequential_multidirect(const ib_level* lv, const Grid& g, int P, ib_prec pre
     SeqWs w = carve_seq(lv, g, prec, np, nl, cfg, ws, ws_bytes, &need);
     if (flag)
         k_fill_i32<<<1, 64, 0, st>>>(2, flag, 0);
+    k_fill_i32<<<1, 64, 0, st>>>(2, w.anyflag, 0);
     if (nl == 0) {
         // no marker: one empty loop writes ustar = u0 and f = 0
         ib_markers me = *m;
@@ -402,6 +404,7 @@ int sequential_multidirect(const ib_level* lv, const Grid& g, int P, ib_prec pre
             return rc;
         if (flag)
             k_or_flags<<<1, 64, 0, st>>>(w.b.flag, flag);
+        k_or_flags<<<1, 64, 0, st>>>(w.b.flag, w.anyflag);
         rc = batched_multidirect(g, P, prec, cfg, &pr, &mc, &w.b, ns, dt, uin, ustar, f,
                                  w.F + 3 * n0 * es, nullptr, nullptr, w.lws, w.lws_bytes, st,
                                  first ? 0 : 1);
@@ -415,6 +418,13 @@ int sequential_multidirect(const ib_level* lv, const Grid& g, int P, ib_prec pre
         k_scatter_F<double><<<gm, 256, 0, st>>>(nl, w.mmap, (const double*)w.F, (double*)F);
     else
         k_scatter_F<float><<<gm, 256, 0, st>>>(nl, w.mmap, (const float*)w.F, (float*)F);
+    // a flagged level leaves every output NaN, not only its own markers' F
+    PoisonSet ps;
+    ps.field[0] = ustar;
+    ps.field[1] = f;
+    ps.vec[0] = F;
+    ps.nvec[0] = 3 * nl;
+    poison_if_flagged(w.anyflag, g, prec, ps, st);
     return launch_status();
 }
 

@@ -20,6 +20,24 @@ def announce(msg):
     print(f"[gpu-case] {msg}", flush=True)
 
 
+def resid_bounds(g, P, m, xc, up, om, u0, ref_resid, tol, threads=0):
+    """Allowed |r_m(path) - r_m(oracle)| for the residuals of Algorithm 1.
+
+    r_m is the dV-norm of e_m = U^d - J u0 - dt J G^m (G^m = S F^m), a sum of
+    three marker vectors.  A path that forms each of them to relative accuracy
+    tol gets r_m within tol (|U^d| + |J u0| + dt |J G^m|) by the triangle
+    inequality, and dt J G^m = J u^(m) - J u0 with |J u^(m)| <= |U^d| + r_m, so
+    the bound is tol (2 |U^d| + 2 |J u0| + r_m), all norms in dV.  The norms
+    come from the oracle on the same inputs."""
+    import oracle as O
+    dv = m.dv[m.pid][:, None]
+    Ud = O.desired_velocity(m, xc, up, om)
+    Ju0 = O.interp(g, P, m, u0, threads=threads)
+    a = float(np.sqrt((dv * Ud * Ud).sum()))
+    b0 = float(np.sqrt((dv * Ju0 * Ju0).sum()))
+    return tol * (2 * a + 2 * b0 + np.asarray(ref_resid))
+
+
 @functools.lru_cache(maxsize=None)
 def small_workload(n=32, box=16, delta=4, ns=3, seed=1, cover_all=True, k=3):
     rng = np.random.default_rng(100 + seed)
