@@ -5,18 +5,28 @@
 * spheres1000_256 (922,600 markers, 256^3): the benchmarked configuration --
   markers built and bucketed on the GPU, FP32 batched loop in place on a side
   stream replayed from a captured hipGraph -- against the full oracle loop.
-* spheres20000_512 (17.5 M markers, 512^3): too large for the whole oracle
-  loop in a test, so: bucketing bit-exact against the oracle's; interpolation
-  on a sample of markers; the FP32 loop on particles whose supports touch no
-  other particle's, against the oracle run on a window around each of them
-  (the Jacobi iteration of such a particle does not see the others); and
-  force conservation (sum_x f h^3 = sum_l F_l dV_l) over the whole grid.
+  The same workload on the FP64 batched path, against the oracle at 1e-12.
+* spheres20000_512 (17.5 M markers, 512^3, 3-point kernel, clustered and
+  overlapping spheres): bucketing bit-exact against the oracle's, and the
+  autotuned FP32 batched loop in place against the whole oracle loop (its
+  OpenMP build, whose bits equal the single-threaded one's): F on every
+  marker, f and u* on every covered cell, the residuals, and force
+  conservation (sum_x f h^3 = sum_l F_l dV_l) over the whole grid.  On this
+  workload the iteration does not converge (the overlapping clumps put the
+  coupling operator's spectrum past 2; the oracle's residual grows from 1.47
+  to 9.35), which the comparison does not care about: both sides compute the
+  same five iterations.
+
+Residuals are held to the bound of gpu_common.resid_bounds (the error a path
+makes forming the three marker vectors whose difference the residual
+measures).
 """
 import numpy as np
 import pytest
 
 import workloads as W
-from gpu_common import Case, announce, gpu_device, rel
+import oracle as O
+from gpu_common import Case, announce, gpu_device, rel, resid_bounds
 
 pytestmark = pytest.mark.gpu
 
@@ -33,6 +43,19 @@ def dev():
 def cfg4():
     announce("generate spheres20000_512")
     return W.config(4, 0)
+
+
+@pytest.fixture(scope="module")
+def cfg3_ref():
+    """spheres1000_256 (seed 0) and the oracle's whole loop on it."""
+    announce("oracle loop on spheres1000_256")
+    wl = W.config(3, 0)
+    lev = wl.level
+    g = O.grid_of(lev)
+    mo = O.build_markers(wl.xc, wl.d, lev.h)
+    ref = O.multidirect(g, wl.delta, wl.ns, wl.dt, mo, wl.xc, wl.up, wl.om, wl.u0,
+                        threads=O.threads_available())
+    return wl, g, mo, ref
 
 
 @pytest.mark.parametrize("dtype,path", [("f64", 1), ("f64", 2), ("f32", 2)],
@@ -57,20 +80,17 @@ def test_spheres8_256_full_loop(dev, dtype, path):
     assert rel(F.cpu().numpy(), ref["F"]) <= tol
     assert c.field_rel(f, ref["f"]) <= tol
     assert c.field_rel(ustar, ref["ustar"]) <= tol
-    assert np.max(np.abs(r.cpu().numpy() - ref["resid"])) <= 10 * tol * ref["resid"][0]
+    bound = resid_bounds(c.g, wl.delta, c.m, wl.xc, wl.up, wl.om, wl.u0, ref["resid"], tol)
+    assert np.all(np.abs(r.cpu().numpy() - ref["resid"]) <= bound)
 
 
-def test_spheres1000_256_benchmark_configuration(dev):
+def test_spheres1000_256_benchmark_configuration(dev, cfg3_ref):
     import torch
 
-    import oracle as O
     import paper_2408_14140_amd as ibx
     announce("spheres1000_256 benchmark configuration")
-    wl = W.config(3, 0)
+    wl, g, mo, ref = cfg3_ref
     lev = wl.level
-    g = O.grid_of(lev)
-    mo = O.build_markers(wl.xc, wl.d, lev.h)
-    ref = O.multidirect(g, wl.delta, wl.ns, wl.dt, mo, wl.xc, wl.up, wl.om, wl.u0)
     bref = O.bucket(lev, wl.delta, mo)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -97,14 +117,46 @@ def test_spheres1000_256_benchmark_configuration(dev):
     assert np.array_equal(b.src_offs.cpu().numpy(), bref["src_offs"])
     mask = lev.covered_mask()
     mk = np.broadcast_to(mask, (3,) + mask.shape)
+    bound = resid_bounds(g, wl.delta, mo, wl.xc, wl.up, wl.om, wl.u0, ref["resid"], TOL32,
+                         threads=O.threads_available())
     for ustar, f, F, r in outs:
         assert rel(F.cpu().numpy(), ref["F"]) <= TOL32
         gf = W.from_boxes(f.double().cpu().numpy(), lev)
         gu = W.from_boxes(ustar.double().cpu().numpy(), lev)
         assert rel(gf[mk], ref["f"][mk]) <= TOL32
         assert rel(gu[mk], ref["ustar"][mk]) <= TOL32
-        assert np.max(np.abs(r.cpu().numpy() - ref["resid"])) <= 10 * TOL32 * ref["resid"][0]
+        assert np.all(np.abs(r.cpu().numpy() - ref["resid"]) <= bound)
     assert torch.equal(outs[0][2], outs[1][2])
+
+
+def test_spheres1000_256_fp64_batched(dev, cfg3_ref):
+    """The batched path in FP64 on the benchmark workload: the tile kernels,
+    the G recurrence and the finalize step against the oracle at 1e-12."""
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    announce("spheres1000_256 FP64 batched")
+    wl, g, mo, ref = cfg3_ref
+    lev = wl.level
+    dl = ibx.device_level(lev, dev)
+    parts = ibx.particles(wl.xc, wl.d, wl.up, wl.om, dev)
+    dm = ibx.markers_from(mo.x, mo.y, mo.z, mo.pid, mo.dv, mo.offs, dev)
+    b = ibx.bucket(dl, dm, wl.delta)
+    u = torch.as_tensor(W.to_boxes(wl.u0, lev, fill=np.nan), device=dev)
+    plan = ibx.Plan(wl.delta, torch.float64, ibx.IB_PATH_BATCHED)
+    r = torch.zeros(wl.ns + 1, dtype=torch.float64, device=dev)
+    ustar, f, F = plan.multidirect_force(dl, parts, dm, b, wl.ns, wl.dt, u, resid=r)
+    torch.cuda.synchronize()
+    mask = lev.covered_mask()
+    mk = np.broadcast_to(mask, (3,) + mask.shape)
+    assert rel(F.cpu().numpy(), ref["F"]) <= TOL64
+    gf = W.from_boxes(f.cpu().numpy(), lev)
+    gu = W.from_boxes(ustar.cpu().numpy(), lev)
+    assert rel(gf[mk], ref["f"][mk]) <= TOL64
+    assert rel(gu[mk], ref["ustar"][mk]) <= TOL64
+    bound = resid_bounds(g, wl.delta, mo, wl.xc, wl.up, wl.om, wl.u0, ref["resid"], TOL64,
+                         threads=O.threads_available())
+    assert np.all(np.abs(r.cpu().numpy() - ref["resid"]) <= bound)
 
 
 def test_spheres20000_512_bucketing_bit_exact(dev, cfg4):
@@ -128,66 +180,26 @@ def test_spheres20000_512_bucketing_bit_exact(dev, cfg4):
     assert np.array_equal(b.src_idx[:ns].cpu().numpy(), ref["src_idx"])
 
 
-def _isolated(wl, count, seed=0):
-    """Up to `count` particles whose dilated bounding sphere meets no other's."""
-    from scipy.spatial import cKDTree
-    h = wl.level.h
-    pad = (wl.delta + 2) * h
-    rmax = wl.d.max() + pad
-    tree = cKDTree(np.mod(wl.xc, 1.0), boxsize=1.0)
-    pairs = tree.query_pairs(rmax, output_type="ndarray")
-    dx = wl.xc[pairs[:, 0]] - wl.xc[pairs[:, 1]]
-    dx -= np.round(dx)
-    dist = np.sqrt((dx * dx).sum(axis=1))
-    clash = dist < 0.5 * (wl.d[pairs[:, 0]] + wl.d[pairs[:, 1]]) + pad
-    bad = np.zeros(wl.npart, bool)
-    bad[pairs[clash, 0]] = True
-    bad[pairs[clash, 1]] = True
-    good = np.nonzero(~bad)[0]
-    rng = np.random.default_rng(seed)
-    return rng.choice(good, size=min(count, good.size), replace=False)
-
-
-def _window(wl, p):
-    """Non-periodic local grid around particle p and its slice of u0."""
-    import oracle as O
-    lev = wl.level
-    h, n = lev.h, lev.n[0]
-    R = 0.5 * wl.d[p]
-    lo = np.floor((wl.xc[p] - R) / h).astype(int) - (wl.delta + 2)
-    hi = np.ceil((wl.xc[p] + R) / h).astype(int) + (wl.delta + 2)
-    idx = [np.arange(lo[a], hi[a]) % n for a in range(3)]
-    u = wl.u0[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]]
-    g = O.grid(tuple(int(v) for v in hi - lo), h, tuple(float(v) for v in lo * h),
-               periodic=(0, 0, 0))
-    return g, np.ascontiguousarray(u), lo, hi
-
-
-def test_spheres20000_512_sampled(dev, cfg4):
+def test_spheres20000_512_full_loop(dev, cfg4):
+    """The whole Algorithm 1 loop at scale: 17.5 M markers of clustered,
+    overlapping spheres, 3-point kernel, N_s = 5, against the oracle."""
     import torch
 
-    import oracle as O
     import paper_2408_14140_amd as ibx
-    announce("spheres20000_512 sampled loop")
     wl = cfg4
     lev = wl.level
     h = lev.h
+    g = O.grid_of(lev)
     mo = O.build_markers(wl.xc, wl.d, h)
+    nt = O.threads_available()
+    announce(f"spheres20000_512 oracle loop ({nt} threads)")
+    ref = O.multidirect(g, wl.delta, wl.ns, wl.dt, mo, wl.xc, wl.up, wl.om, wl.u0, threads=nt)
+    announce("spheres20000_512 GPU loop")
     dl = ibx.device_level(lev, dev)
     parts = ibx.particles(wl.xc, wl.d, wl.up, wl.om, dev)
     dm = ibx.markers_from(mo.x, mo.y, mo.z, mo.pid, mo.dv, mo.offs, dev)
     b = ibx.bucket(dl, dm, wl.delta)
     u = torch.as_tensor(W.to_boxes(wl.u0, lev, fill=np.nan, dtype=np.float32), device=dev)
-    # interpolation of u0 on a sample of markers
-    U = ibx.interp(dl, dm, wl.delta, u)
-    rng = np.random.default_rng(4)
-    pick = np.sort(rng.choice(mo.nl, size=50000, replace=False))
-    sub = O.Markers(mo.x[pick], mo.y[pick], mo.z[pick], mo.pid[pick], mo.dv,
-                    np.array([0, pick.size], np.int64))
-    Uref = O.interp(O.grid_of(lev), wl.delta, sub, wl.u0)
-    torch.cuda.synchronize()
-    assert rel(U.cpu().numpy()[pick], Uref) <= TOL32
-    # autotuned plan, in place, with residuals
     plan = ibx.Plan(wl.delta, torch.float32, ibx.IB_PATH_BATCHED)
     plan.autotune(dl, parts, dm, b, wl.ns, wl.dt, u)
     f = torch.zeros_like(u)
@@ -195,22 +207,24 @@ def test_spheres20000_512_sampled(dev, cfg4):
     ustar, f, F = plan.multidirect_force(dl, parts, dm, b, wl.ns, wl.dt, u, ustar=u, f=f,
                                          resid=r)
     torch.cuda.synchronize()
+    assert int(b.flag[0].item()) == 0 and int(b.flag[1].item()) == 0
     Fh = F.double().cpu().numpy()
+    assert rel(Fh, ref["F"]) <= TOL32
+    mask = lev.covered_mask()
+    mk = np.broadcast_to(mask, (3,) + mask.shape)
+    gf = W.from_boxes(f.double().cpu().numpy(), lev)
+    assert rel(gf[mk], ref["f"][mk]) <= TOL32
+    del gf
+    gu = W.from_boxes(ustar.double().cpu().numpy(), lev)
+    assert rel(gu[mk], ref["ustar"][mk]) <= TOL32
+    del gu
+    bound = resid_bounds(g, wl.delta, mo, wl.xc, wl.up, wl.om, wl.u0, ref["resid"], TOL32,
+                         threads=nt)
+    assert np.all(np.abs(r.cpu().numpy() - ref["resid"]) <= bound)
     # force conservation over the whole grid: sum_x f h^3 = sum_l F_l dV_l
-    g = lev.ngrow
-    fv = f[:, :, g:g + lev.box, g:g + lev.box, g:g + lev.box]
+    gw = lev.ngrow
+    fv = f[:, :, gw:gw + lev.box, gw:gw + lev.box, gw:gw + lev.box]
     lhs = fv.double().sum(dim=(0, 2, 3, 4)).cpu().numpy() * h ** 3
     rhs = (Fh * mo.dv[mo.pid][:, None]).sum(axis=0)
     scale = (np.abs(Fh) * mo.dv[mo.pid][:, None]).sum(axis=0)
     assert np.all(np.abs(lhs - rhs) <= TOL32 * scale)
-    # isolated particles against the oracle on a window around each
-    sel = _isolated(wl, 12)
-    assert sel.size >= 4
-    for p in sel:
-        a, z = int(mo.offs[p]), int(mo.offs[p + 1])
-        mp = O.Markers(mo.x[a:z], mo.y[a:z], mo.z[a:z], np.zeros(z - a, np.int32),
-                       mo.dv[p:p + 1], np.array([0, z - a], np.int64))
-        gw, uw, lo, hi = _window(wl, p)
-        ref = O.multidirect(gw, wl.delta, wl.ns, wl.dt, mp, wl.xc[p:p + 1], wl.up[p:p + 1],
-                            wl.om[p:p + 1], uw, residuals=False)
-        assert rel(Fh[a:z], ref["F"]) <= TOL32, p
