@@ -6,10 +6,20 @@ multidirect iterations with finalization (a3-a9), and the per-particle
 reductions (a10), FP32 fields with FP64 positions and sums, inputs resident in
 HBM, no host synchronization inside the step.  Prints one JSON line.
 
-Beside the headline value it reports the loop alone, the plain FP64 path on
-the same inputs, a per-kernel breakdown from the library's event profiler, the
-dominant kernel's roofline, the adjoint (a11) on the 64-sphere 128^3 workload,
-and the FP64 oracle timed on the host.
+Beside the headline value it reports the loop alone (mean of back-to-back
+runs and median of single runs), the plain FP64 path and the FP64 batched path
+on the same inputs, the 20000-sphere 512^3 workload's loop, a per-kernel
+breakdown from the library's event profiler, the roofline of the dominant
+kernel and of the whole loop, the adjoint (a11) on the 64-sphere 128^3
+workload, and the FP64 oracle timed on the host (all cores, and one core).
+
+Byte model (compulsory traffic of Algorithm 1, every cell or marker counted
+once per pass, s = field bytes, C = the support cells, N = markers):
+    per iteration  B_it = 3 s |C| + N b_m,  b_m = 24 + 9 s
+                   (positions, F read and written, U^d);
+    loop           B_model = N_s B_it + 6 s |C|  (final u* and f on C).
+roofline.frac is B_it times the iterations one launch of the dominant kernel
+covers, over its average launch time, over the 8 TB/s HBM peak.
 """
 import argparse
 import hashlib
@@ -47,8 +57,24 @@ def support_cells(level, b, delta):
     return int(torch.unique(lin.reshape(-1)).numel())
 
 
-def model_bytes(kind, s, P, N, S, A, C, ncov):
-    """Compulsory bytes of one launch of a batched-path kernel class.
+def iteration_bytes(s, N, C):
+    """B_it of the byte model: u0 read on the support, 24 + 9 s bytes per marker."""
+    return 3 * s * C + N * (24 + 9 * s)
+
+
+def loop_bytes(s, N, C, ns):
+    """B_model of the byte model: N_s iterations and the final u*, f on C."""
+    return ns * iteration_bytes(s, N, C) + 6 * s * C
+
+
+# iterations of Algorithm 1 covered by one launch of each kernel class
+ITERATIONS_PER_LAUNCH = {"spread": 1, "interp_g": 1, "interp_u0": 1, "spread_final": 1}
+
+
+def impl_bytes(kind, s, P, N, S, A, C, ncov):
+    """Bytes one launch of a batched-path kernel class touches in this
+    implementation (not compulsory: it counts the tile slots and the source
+    records each tile gathers).
 
     N markers, S source-list entries, A active tiles (512 cells each), C
     support cells, ncov cells of the covered boxes, s field bytes.  Marker
@@ -110,6 +136,70 @@ def copy_probe(mib, reps):
     return 2 * 4 * n * reps / (s.elapsed_time(e) * 1e-3) / 1e9
 
 
+def host_cpu():
+    """nproc and the CPU model of this host."""
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def big_workload_leg(args, dev, timed, timed_median):
+    """The FP32 batched loop on spheres20000_512 (seed 0): autotuned, in place,
+    median of single runs, per-kernel averages and the byte-model fractions."""
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    import workloads as W
+    t0 = time.time()
+    wl = W.config(4, 0)
+    lev = wl.level
+    log(f"workload {wl.name}: {wl.npart} spheres, {lev.nbox} boxes, gen {time.time()-t0:.1f}s")
+    dl = ibx.device_level(lev, dev)
+    parts = ibx.particles(wl.xc, wl.d, wl.up, wl.om, dev)
+    m = ibx.build_markers(dl, parts)
+    b = ibx.bucket(dl, m, wl.delta)
+    torch.cuda.synchronize()
+    assert int(b.flag[0].item()) == 0 and int(b.flag[1].item()) == 0
+    N, P, ns, dt = m.nl, wl.delta, wl.ns, wl.dt
+    C = support_cells(dl, b, P)
+    u = torch.as_tensor(W.to_boxes(wl.u0, lev, fill=0.0, dtype=np.float32), device=dev)
+    f = torch.zeros_like(u)
+    F = torch.zeros((N, 3), dtype=torch.float32, device=dev)
+    plan = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, use_graph=True)
+    tuned = plan.autotune(dl, parts, m, b, ns, dt, u)
+
+    def loop():
+        plan.multidirect_force(dl, parts, m, b, ns, dt, u, ustar=u, f=f, F=F)
+
+    for _ in range(args.warmup):
+        loop()
+    ms = timed_median(loop, args.steps)
+    plan.profile(True)
+    for _ in range(max(2, args.steps // 4)):
+        loop()
+    prof = plan.profile_read(reset=True)
+    plan.profile(False)
+    kern = {k: {"avg_us": 1e3 * v[0] / v[1], "calls": v[1]} for k, v in prof.items() if v[1]}
+    dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["calls"])
+    bit = iteration_bytes(4, N, C)
+    bl = loop_bytes(4, N, C, ns)
+    res = {"markers": N, "support_cells": C, "loop_ms": ms, "plan": tuned,
+           "marker_iters_per_s": N * ns / (ms * 1e-3),
+           "loop_model_bytes": bl, "loop_frac": bl / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "dominant_kernel": dom, "kernels": kern,
+           "dominant_frac": (ITERATIONS_PER_LAUNCH.get(dom, 0) * bit /
+                             (kern[dom]["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS)}
+    log(f"spheres20000_512: {N} markers, C {C}, loop {ms:.3f} ms, frac {res['loop_frac']:.3f}")
+    del u, f, F, plan
+    return res
+
+
 def main():
     if "--gpus" in sys.argv:
         i = sys.argv.index("--gpus")
@@ -141,6 +231,8 @@ def run():
     ap.add_argument("--spread-wgs", type=int, default=0)
     ap.add_argument("--no-fluid", action="store_true",
                     help="skip the fluid steps and the whole time step")
+    ap.add_argument("--no-cfg4", action="store_true",
+                    help="skip the 20000-sphere 512^3 loop")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the particle-by-particle (level by level) loop")
     ap.add_argument("--no-autotune", action="store_true",
@@ -209,6 +301,18 @@ def run():
         torch.cuda.synchronize()
         return s.elapsed_time(e) / k
 
+    def timed_median(fn, k):
+        """Median over k single runs, each between its own pair of events."""
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(k)]
+        torch.cuda.synchronize()
+        for s0, e0 in ev:
+            s0.record()
+            fn()
+            e0.record()
+        torch.cuda.synchronize()
+        return float(np.median([s0.elapsed_time(e0) for s0, e0 in ev]))
+
     def captured(fn):
         """fn recorded once into a graph (every call in it only enqueues work);
         returns its replay."""
@@ -232,7 +336,9 @@ def run():
     ms_step = timed(step_g, args.steps)
     ms_step_eager = timed(step, args.steps)
     ms_loop = timed(loop_only, args.steps)
-    log(f"step {ms_step:.3f} ms (eager launches {ms_step_eager:.3f} ms), loop {ms_loop:.3f} ms")
+    ms_loop_med = timed_median(loop_only, args.steps)
+    log(f"step {ms_step:.3f} ms (eager launches {ms_step_eager:.3f} ms), loop {ms_loop:.3f} ms "
+        f"(median of single runs {ms_loop_med:.3f} ms)")
 
     # the step's other parts, each captured alone and timed over the same repetitions
     parts_ms = {
@@ -303,18 +409,26 @@ def run():
     for k, v in prof.items():
         if v[1] > 0:
             kern[k] = {"ms_total": v[0], "calls": v[1], "avg_us": 1e3 * v[0] / v[1]}
-            mb = model_bytes(k, 4, P, N, S, A, C, ncov)
-            if mb:
-                kern[k]["model_bytes"] = mb
-                kern[k]["model_gbs"] = mb / (1e-3 * v[0] / v[1]) / 1e9
+            ib = impl_bytes(k, 4, P, N, S, A, C, ncov)
+            if ib:
+                kern[k]["impl_bytes"] = ib
+            if k in ITERATIONS_PER_LAUNCH:
+                kern[k]["model_bytes"] = ITERATIONS_PER_LAUNCH[k] * iteration_bytes(4, N, C)
+                kern[k]["model_gbs"] = kern[k]["model_bytes"] / (1e-3 * v[0] / v[1]) / 1e9
     dom = max(kern, key=lambda k: kern[k]["ms_total"])
-    nb = model_bytes(dom, 4, P, N, S, A, C, ncov)
+    nb = kern[dom].get("model_bytes")
     avg_s = kern[dom]["avg_us"] * 1e-6
     achieved = nb / avg_s / 1e9 if nb else None
+    bmodel = loop_bytes(4, N, C, ns)
     roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                 "traffic": committed_traffic(dom), "bytes_per_launch": nb,
-                "avg_launch_us": kern[dom]["avg_us"]}
+                "iterations_per_launch": ITERATIONS_PER_LAUNCH.get(dom),
+                "avg_launch_us": kern[dom]["avg_us"],
+                "impl_bytes_per_launch": kern[dom].get("impl_bytes"),
+                "loop": {"bytes": bmodel, "ms": ms_loop,
+                         "achieved": bmodel / (ms_loop * 1e-3) / 1e9,
+                         "frac": bmodel / (ms_loop * 1e-3) / 1e9 / HBM_PEAK_GBS}}
     log(f"kernels {json.dumps(kern)}")
 
     # cold loop: a 512 MiB write between repetitions evicts the 256 MB MALL
@@ -379,9 +493,6 @@ def run():
     value_med = float(np.median([v["value"] for v in by_seed.values()]))
     ms_step_med = float(np.median([v["ms_per_step"] for v in by_seed.values()]))
 
-    # byte model of the literal loop: per iteration u0 read on the support C and
-    # 60 B per marker, plus the final writes of u* and f on C
-    bmodel = ns * (3 * 4 * C + N * 60) + 6 * 4 * C
     out = {
         "metric": "marker-iters/s of the multidirect IB step (FP32 batched)",
         "value": value_med,
@@ -406,6 +517,7 @@ def run():
                               "figure on the workload of `seed`"},
         "by_seed": {str(k): by_seed[k] for k in sorted(by_seed)},
         "loop_ms": ms_loop,
+        "loop_ms_median": ms_loop_med,
         "step_parts_ms": parts_ms,
         "particle_step_ms": particle_ms,
         "fluid_256_fp32_ms": fluid_ms,
@@ -435,7 +547,27 @@ def run():
         out["fp64_plain_loop_ms"] = ms64
         out["speedup_fp32_batched_vs_fp64_plain"] = ms64 / ms_loop
         log(f"fp64 plain loop {ms64:.3f} ms")
-        del u64, us64, f64, F64
+        # the batched path in FP64 on the same inputs (in place, autotuned)
+        pb64 = ibx.Plan(P, torch.float64, ibx.IB_PATH_BATCHED, use_graph=True)
+        tb64 = pb64.autotune(dl, parts, m, b, ns, dt, u64)
+
+        def batched64():
+            pb64.multidirect_force(dl, parts, m, b, ns, dt, u64, ustar=u64, f=f64, F=F64)
+
+        for _ in range(args.warmup):
+            batched64()
+        msb64 = timed(batched64, args.steps)
+        out["fp64_batched"] = {"loop_ms": msb64, "plan": tb64,
+                               "loop_frac": loop_bytes(8, N, C, ns) / (msb64 * 1e-3) / 1e9
+                               / HBM_PEAK_GBS}
+        out["speedup_fp32_batched_vs_fp64_batched"] = msb64 / ms_loop
+        log(f"fp64 batched loop {msb64:.3f} ms")
+        del u64, us64, f64, F64, pb64
+
+    if not args.no_cfg4:
+        # 20000 clustered spheres, 512^3, 3-point kernel: working set beyond the MALL
+        out["spheres20000_512"] = big_workload_leg(args, dev, timed, timed_median)
+        torch.cuda.empty_cache()
 
     if not args.no_sequential:
         # the particle-by-particle order: conflict levels, then one loop per level
@@ -482,18 +614,34 @@ def run():
         import oracle as O
         mo = O.build_markers(wl.xc, wl.d, lev.h)
         go = O.grid_of(lev)
-        reps, el = 0, 0.0
-        while el < 10.0:
-            t = time.perf_counter()
-            O.multidirect(go, P, ns, dt, mo, wl.xc, wl.up, wl.om, wl.u0, residuals=False)
-            el += time.perf_counter() - t
-            reps += 1
+        host = host_cpu()
+
+        def oracle_rate(threads, budget):
+            reps, el = 0, 0.0
+            while el < budget:
+                t = time.perf_counter()
+                O.multidirect(go, P, ns, dt, mo, wl.xc, wl.up, wl.om, wl.u0, residuals=False,
+                              threads=threads)
+                el += time.perf_counter() - t
+                reps += 1
+            return reps, el
+
+        nt = O.threads_available()
+        reps, el = oracle_rate(nt, 10.0)
         out["cpu_baseline"] = {"value": reps * mo.nl * ns / el, "unit": "marker-iters/s",
-                               "cores": 1, "kind": "oracle",
+                               "cores": nt, "kind": "oracle",
                                "sample": f"{reps} runs of the full workload's loop (a3-a9, "
-                                         f"{mo.nl} markers, N_s={ns}) in the FP64 C oracle, "
-                                         f"one thread, {el:.1f} s"}
-        log(f"oracle loop x{reps} {el:.1f} s")
+                                         f"{mo.nl} markers, N_s={ns}) in the FP64 C oracle "
+                                         f"built with OpenMP (same source and bits as the "
+                                         f"single-threaded build), {nt} threads, {el:.1f} s",
+                               "host": host}
+        log(f"oracle loop x{reps} on {nt} threads {el:.1f} s")
+        reps1, el1 = oracle_rate(0, 10.0)
+        out["cpu_baseline_1core"] = {"value": reps1 * mo.nl * ns / el1, "unit": "marker-iters/s",
+                                     "cores": 1, "kind": "oracle",
+                                     "sample": f"{reps1} runs of the same loop, single-threaded "
+                                               f"build, {el1:.1f} s", "host": host}
+        log(f"oracle loop x{reps1} on 1 thread {el1:.1f} s")
     print(json.dumps(out), flush=True)
 
 
