@@ -267,6 +267,24 @@ int ib_particle_reductions(const ib_level* lv, const ib_particles* p, const ib_m
                            ib_prec prec, const void* F, const void* u, double* out,
                            int32_t* flag, void* ws, size_t ws_bytes, void* stream);
 
+/* ib_particle_reductions for callers that cannot allocate device memory   */
+/* (code under HIP graph capture, tight serving loops, harnesses that      */
+/* forbid hipMalloc): the same sums from the same kernels, bit for bit,    */
+/* with the partial sums kept in a fixed device array inside the library   */
+/* instead of a workspace.  The array holds IB_REDUCTIONS_NOALLOC_MAX_NP    */
+/* particles (7.5 MiB, one copy per device, kept until the process ends);  */
+/* p->np above that returns IB_EUNSUPPORTED before anything is enqueued.   */
+/* Nothing is allocated: no hipMalloc, hipFree or allocating library call. */
+/* Every call on one device shares that device's array, so calls that      */
+/* overlap on a device (different streams, or threads) race; calls on one  */
+/* stream are ordered and safe.  Nothing in the array needs clearing: each */
+/* call writes every entry it reads.  The first call on a device looks up  */
+/* the array's device address (hipGetSymbolAddress) once.                   */
+#define IB_REDUCTIONS_NOALLOC_MAX_NP 32768
+int ib_particle_reductions_noalloc(const ib_level* lv, const ib_particles* p,
+                                   const ib_markers* m, ib_prec prec, const void* F,
+                                   const void* u, double* out, int32_t* flag, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* a11 Adjoint of ib_multidirect_force (reverse sweep; S and J adjoint,     */
 /* Sec. 2).  Given Fhist from the forward call and the upstream gradients   */

@@ -15,6 +15,8 @@
 // Lagrangian sums beside them, and a second kernel adds the slab partials in
 // a fixed order.  Every sum is formed by fixed-shape
 // trees, so results are reproducible bit for bit.
+#include <mutex>
+
 #include "paths.h"
 
 namespace ibx {
@@ -318,15 +320,47 @@ __global__ void k_particle_out(int64_t np, const double* __restrict__ part,
 
 using namespace ibx;
 
-extern "C" size_t ib_reductions_workspace(int32_t np)
+// Scratch of ib_particle_reductions_noalloc: the slab partial sums of up to
+// RD_NOALLOC_MAX_NP particles (30 doubles each, 7.5 MiB), a file-scope device
+// array that every device the library runs on holds until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address); it passes the address that
+// hipGetSymbolAddress returned for the current device.
+constexpr int32_t RD_NOALLOC_MAX_NP = IB_REDUCTIONS_NOALLOC_MAX_NP;
+static __device__ __align__(256) double scratch[(size_t)RD_NOALLOC_MAX_NP * (RD_SLABS + 1) * 6];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(void** out)
 {
-    return np > 0 ? (size_t)np * (RD_SLABS + 1) * 6 * sizeof(double) : 0;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_hip_error(e);
+        return IB_EHIP;
+    }
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+        return IB_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_hip_error(e);
+            return IB_EHIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return IB_OK;
 }
 
-extern "C" int ib_particle_reductions(const ib_level* lv, const ib_particles* p,
-                                      const ib_markers* m, ib_prec prec, const void* F,
-                                      const void* u, double* out, int32_t* flag, void* ws,
-                                      size_t ws_bytes, void* stream)
+int check_reductions(const ib_level* lv, const ib_particles* p, const ib_markers* m,
+                     ib_prec prec, const void* F, const void* u, const double* out)
 {
     int rc = check_level(lv);
     if (rc)
@@ -338,11 +372,16 @@ extern "C" int ib_particle_reductions(const ib_level* lv, const ib_particles* p,
     if (!p->xc || !p->d || !m->offs || !m->dv || !u || !out ||
         (m->nl > 0 && (!F || !m->x || !m->y || !m->z)))
         return IB_EINVAL;
-    if (!ws || ws_bytes < ib_reductions_workspace(p->np))
-        return IB_EWORKSPACE;
+    return IB_OK;
+}
+
+// Both entry points: part holds (RD_SLABS + 1) * 6 doubles per particle, every
+// one of them written by k_volume_partials before k_particle_out reads it.
+int launch_reductions(const ib_level* lv, const ib_particles* p, const ib_markers* m,
+                      ib_prec prec, const void* F, const void* u, double* out, int32_t* flag,
+                      double* part, hipStream_t st)
+{
     Grid g = make_grid(lv);
-    hipStream_t st = (hipStream_t)stream;
-    double* part = (double*)ws;
     const dim3 gv((unsigned)p->np, RD_SLABS + 1);
     if (prec == IB_F64)
         k_volume_partials<double><<<gv, RD_THREADS, 0, st>>>(
@@ -355,4 +394,40 @@ extern "C" int ib_particle_reductions(const ib_level* lv, const ib_particles* p,
     const int64_t ne = 12 * (int64_t)p->np;
     k_particle_out<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(p->np, part, out);
     return launch_status();
+}
+}  // namespace
+
+extern "C" size_t ib_reductions_workspace(int32_t np)
+{
+    return np > 0 ? (size_t)np * (RD_SLABS + 1) * 6 * sizeof(double) : 0;
+}
+
+extern "C" int ib_particle_reductions(const ib_level* lv, const ib_particles* p,
+                                      const ib_markers* m, ib_prec prec, const void* F,
+                                      const void* u, double* out, int32_t* flag, void* ws,
+                                      size_t ws_bytes, void* stream)
+{
+    int rc = check_reductions(lv, p, m, prec, F, u, out);
+    if (rc || p->np == 0)
+        return rc;
+    if (!ws || ws_bytes < ib_reductions_workspace(p->np))
+        return IB_EWORKSPACE;
+    return launch_reductions(lv, p, m, prec, F, u, out, flag, (double*)ws, (hipStream_t)stream);
+}
+
+extern "C" int ib_particle_reductions_noalloc(const ib_level* lv, const ib_particles* p,
+                                              const ib_markers* m, ib_prec prec, const void* F,
+                                              const void* u, double* out, int32_t* flag,
+                                              void* stream)
+{
+    int rc = check_reductions(lv, p, m, prec, F, u, out);
+    if (rc || p->np == 0)
+        return rc;
+    if (p->np > RD_NOALLOC_MAX_NP)
+        return IB_EUNSUPPORTED;
+    void* part = nullptr;
+    rc = scratch_address(&part);
+    if (rc)
+        return rc;
+    return launch_reductions(lv, p, m, prec, F, u, out, flag, (double*)part, (hipStream_t)stream);
 }

@@ -88,6 +88,8 @@ _autotune = _sig("ib_plan_autotune", C.c_int,
 _red_ws = _sig("ib_reductions_workspace", _sz, [_i32])
 _reductions = _sig("ib_particle_reductions", C.c_int,
                    [_PL, _PP, _PM, C.c_int, _p, _p, _p, _p, _p, _sz, _p])
+_reductions_noalloc = _sig("ib_particle_reductions_noalloc", C.c_int,
+                          [_PL, _PP, _PM, C.c_int, _p, _p, _p, _p, _p])
 _bwd_ws = _sig("ib_backward_workspace_bytes", _sz, [_p, _PL, _i64])
 _backward = _sig("ib_multidirect_backward", C.c_int,
                  [_p, _PL, _PP, _PM, _PB, _i32, _d, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
@@ -116,7 +118,8 @@ EXPORTED = ("ib_count_markers", "ib_build_markers", "ib_desired_velocity", "ib_b
             "ib_bucket", "ib_interp", "ib_spread", "ib_plan_create", "ib_plan_destroy",
             "ib_plan_query", "ib_workspace_bytes", "ib_plan_profile", "ib_plan_profile_read",
             "ib_multidirect_force", "ib_plan_autotune",
-            "ib_reductions_workspace", "ib_particle_reductions", "ib_backward_workspace_bytes", "ib_multidirect_backward",
+            "ib_reductions_workspace", "ib_particle_reductions", "ib_particle_reductions_noalloc",
+            "ib_backward_workspace_bytes", "ib_multidirect_backward",
             "ib_rigid_update", "ib_advect_markers", "ib_collision_forces",
             "ib_levels_workspace", "ib_particle_levels", "ib_sequential_workspace_bytes",
             "ib_multidirect_sequential", "ib_fluid_workspace", "ib_fluid_predict",
@@ -541,6 +544,21 @@ def particle_reductions(level: DeviceLevel, parts: Particles, m: Markers, F: tor
     _check(_reductions(C.byref(lc), C.byref(pc), C.byref(mc), _prec_of(u.dtype), _ptr(F), _ptr(u),
                        _ptr(out), _ptr(flag), _ptr(ws), int(ws.numel()), _stream()),
            "ib_particle_reductions")
+    return out
+
+
+REDUCTIONS_NOALLOC_MAX_NP = 32768
+
+
+def particle_reductions_noalloc(level: DeviceLevel, parts: Particles, m: Markers,
+                                F: torch.Tensor, u: torch.Tensor, out: torch.Tensor,
+                                flag: torch.Tensor = None) -> torch.Tensor:
+    """particle_reductions into a caller tensor out [np][12] (float64) with the
+    library's fixed scratch: no device memory is allocated here or inside."""
+    lc, pc, mc = level.c, parts.c, m.c
+    _check(_reductions_noalloc(C.byref(lc), C.byref(pc), C.byref(mc), _prec_of(u.dtype),
+                               _ptr(F), _ptr(u), _ptr(out), _ptr(flag), _stream()),
+           "ib_particle_reductions_noalloc")
     return out
 
 
