@@ -181,13 +181,14 @@ def test_flagged_buckets_poison_outputs(dev, dtype):
     bad = torch.isnan(U).any(dim=1)
     assert bool((torch.isnan(U).all(dim=1) == bad).all())
     assert int(bad.sum().item()) == ref["flagged"] == int(b.flag[0].item())
-    # reductions: particle 1 sits in the uncovered box, particle 0 is covered
+    # reductions: particle 0's body crosses x = 1/2 into the uncovered box
+    # (boxes are indexed z, y, x), particle 1 lies in covered boxes
     rflag = torch.zeros(1, dtype=torch.int32, device=dev)
     out = ibx.particle_reductions(dl, parts, dm, torch.ones((m.nl, 3), dtype=tdt, device=dev),
                                   u0, flag=rflag)
     torch.cuda.synchronize()
     assert int(rflag.item()) == 1
-    assert bool(torch.isnan(out[1]).all()) and bool(torch.isfinite(out[0]).all())
+    assert bool(torch.isnan(out[0]).all()) and bool(torch.isfinite(out[1]).all())
 
 
 @pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
