@@ -449,8 +449,10 @@ int resident_grid(int ncu, int cap)
 // f = G^ns and ustar = u0 + dt G^ns, with G = 0 on tiles no marker reaches
 // (and everywhere when use_g is 0).  One workgroup per (box, row of tiles in
 // y, z plane): box-wide x rows, so the box layout is written in long runs.
-// In place (ustar == u0) only the cells with a force are rewritten.  With
-// f_acc, f += G^ns instead, on the cells with a force only.
+// In place (ustar == u0) only the cells whose force is not exactly zero are
+// read and rewritten (u0 + dt 0 = u0): inside the tiles that have a force
+// slot, most cells lie outside every stencil.  With f_acc, f += G^ns instead,
+// on the same cells.
 template <typename T, bool F_ACC>
 __global__ void __launch_bounds__(256)
 k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, const T* u0,
@@ -485,9 +487,9 @@ k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, co
                 // streaming stores: nothing here is read again by this kernel
                 if (f && !F_ACC)
                     __builtin_nontemporal_store(v, &f[o]);
-                else if (f && s >= 0)
+                else if (f && v != T(0))
                     f[o] += v;
-                if (s >= 0)
+                if (v != T(0))
                     __builtin_nontemporal_store(u0[o] + tdt * v, &ustar[o]);
                 else if (ustar != u0)
                     __builtin_nontemporal_store(u0[o], &ustar[o]);
@@ -548,13 +550,15 @@ k_finalize_pairs(Grid g, const int32_t* __restrict__ slot, const T* __restrict__
                 if (s >= 0)
                     v = *reinterpret_cast<const V2*>(G + go + c * TILE_CELLS);
                 const int64_t o = off + c * g.cstride;
+                // in place, a pair without force keeps u0 and needs no traffic
+                const bool force = v.x != T(0) || v.y != T(0);
                 if (f && !F_ACC) {
                     __builtin_nontemporal_store(v, reinterpret_cast<V2*>(f + o));
-                } else if (f && s >= 0) {
+                } else if (f && force) {
                     V2 w = *reinterpret_cast<const V2*>(f + o);
                     *reinterpret_cast<V2*>(f + o) = w + v;
                 }
-                if (s >= 0) {
+                if (force) {
                     const V2 a = *reinterpret_cast<const V2*>(u0 + o);
                     __builtin_nontemporal_store(a + tdt * v, reinterpret_cast<V2*>(ustar + o));
                 } else if (ustar != u0) {
