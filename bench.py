@@ -606,9 +606,18 @@ def run():
         def bwd():
             pl5.backward(dl5, p5, m5, b5, wl5.ns, wl5.dt, u5, Fh, g_f=f5, g_F=gF)
 
+        def fwd5():
+            pl5.multidirect_force(dl5, p5, m5, b5, wl5.ns, wl5.dt, u5, Fhist=Fh)
+
         bwd()
-        out["backward_spheres64_128_fp32_ms"] = timed(bwd, 3)
-        log(f"backward {out['backward_spheres64_128_fp32_ms']:.3f} ms")
+        fwd5()
+        ms_b = timed(bwd, max(3, args.steps // 4))
+        ms_f = timed(fwd5, max(3, args.steps // 4))
+        out["backward_spheres64_128_fp32_ms"] = ms_b
+        out["backward_spheres64_128"] = {"backward_ms": ms_b, "forward_loop_ms": ms_f,
+                                         "backward_over_forward": ms_b / ms_f,
+                                         "markers": m5.nl, "ns": wl5.ns}
+        log(f"backward {ms_b:.3f} ms, forward loop with history {ms_f:.3f} ms")
 
     if not args.no_cpu_baseline:
         import oracle as O

@@ -529,7 +529,8 @@ extern "C" int ib_multidirect_backward(ib_plan* plan, const ib_level* lv, const 
         return IB_EINVAL;
     if (!ws || ws_bytes < ib_backward_workspace_bytes(plan, lv, m->nl))
         return IB_EWORKSPACE;
-    return multidirect_backward(make_grid(lv), plan->P, plan->prec, p, m, b, ns, dt, u0, Fhist,
+    return multidirect_backward(make_grid(lv), plan->P, plan->prec, cfg_of(plan), p, m, b, ns, dt,
+                                u0, Fhist,
                                 g_ustar, g_f, g_F, g_u0, g_up, g_om, g_X, ws, ws_bytes,
                                 (hipStream_t)stream);
 }

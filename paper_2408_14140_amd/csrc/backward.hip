@@ -13,12 +13,19 @@
 //   g_up = sum a_Ud,  g_om = sum R x a_Ud,  g_X += a_Ud x W_r.
 // S and J are adjoint (Sec. 2): J^T is spreading without dV and S^T is
 // interpolation weighted by dV/h^3.  grad w uses the kernel derivative.
-// Every step reuses the plain kernels; fields are recomputed, never stored.
+// Fields are recomputed, never stored.  The two spreads of every step (the
+// recomputed u^(m-1) and J^T Ubar) run on the forward loop's tile kernel,
+// with its marker records and work lists formed once per call (grids of at
+// least 16 cells per axis; the plain per-cell kernel otherwise), and so do
+// J a_f and the position gradients (the tile interpolation in its adjoint
+// mode, J a_f and its gradient in one pass over a_f; four lanes per marker
+// gathering from global memory otherwise).
 #include "paths.h"
 
 namespace ibx {
 
-// mode 0: a = 0; 1: a = b; 2: a += b; 3: a = u0 + dt b; 4: (a += b, c += dt b)
+// mode 0: a = 0; 1: a = b; 2: a += b; 3: a = u0 + dt b; 4: (a += b, c += dt b);
+// 5: (a += b, c = dt b)
 template <typename T, int MODE>
 __global__ void k_field_op(Grid g, T* __restrict__ a, const T* __restrict__ b,
                            T* __restrict__ c, const T* __restrict__ u0, double dt)
@@ -44,23 +51,34 @@ __global__ void k_field_op(Grid g, T* __restrict__ a, const T* __restrict__ b,
                 a[o] += b[o];
                 c[o] += (T)dt * b[o];
             }
+            if (MODE == 5) {
+                a[o] += b[o];
+                c[o] = (T)dt * b[o];
+            }
         }
     }
 }
 
-// gX_l += scale_l * sum over the stencil of (fld(x) . v_l) grad_X w_l(x),
-// scale_l = dV_l/h^3 when use_dv, else 1.
+// Interpolation and position gradient of one field in one pass, four lanes
+// per marker (lane k of the four takes the stencil's z planes k, k+4, ...,
+// then a fixed shuffle tree sums the four): U_l = J fld (when U is given) and
+// gX_l += scale_l * sum over the stencil of (fld(x) . v_l) grad_X w_l(x)
+// (when v is given), scale_l = dV_l/h^3 when use_dv, else 1.  A stencil cell
+// off a bounded axis or in an uncovered box is skipped (the bucket flags
+// report such markers and the call's outputs are poisoned).
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
-k_grad_pos(Grid g, int64_t nl, const double* __restrict__ x, const double* __restrict__ y,
-           const double* __restrict__ z, const int32_t* __restrict__ pid,
-           const double* __restrict__ dv, const T* __restrict__ fld, const T* __restrict__ v,
-           int use_dv, double* __restrict__ gX)
+k_interp_grad(Grid g, int64_t nl, const double* __restrict__ x, const double* __restrict__ y,
+              const double* __restrict__ z, const int32_t* __restrict__ pid,
+              const double* __restrict__ dv, const T* __restrict__ fld, T* __restrict__ U,
+              const T* __restrict__ v, int use_dv, double* __restrict__ gX)
 {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= nl)
-        return;
-    const double X[3] = {x[l], y[l], z[l]};
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t l = q >> 2;
+    const int sub = (int)(q & 3);
+    const bool live = l < nl;
+    const int64_t lc = live ? l : 0;
+    const double X[3] = {x[lc], y[lc], z[lc]};
     T w[3][P], dw[3][P];
     int c[3][P];
     const T ih = (T)(1.0 / g.h);
@@ -70,34 +88,83 @@ k_grad_pos(Grid g, int64_t nl, const double* __restrict__ x, const double* __res
 #pragma unroll
         for (int o = 0; o < P; ++o) {
             dw[a][o] *= ih;
-            int q = b + o;
+            int cq = b + o;
             if (g.periodic[a])
-                q = wrapi(q, g.n[a]);
-            else if (q < 0 || q >= g.n[a])
-                q = -1;
-            c[a][o] = q;
+                cq = wrapi(cq, g.n[a]);
+            else if (cq < 0 || cq >= g.n[a])
+                cq = -1;
+            c[a][o] = cq;
         }
     }
-    const T v0 = v[3 * l], v1 = v[3 * l + 1], v2 = v[3 * l + 2];
-    T a0 = 0, a1 = 0, a2 = 0;
-    for (int k = 0; k < P; ++k)
-        for (int j = 0; j < P; ++j)
+    T v0 = T(0), v1 = T(0), v2 = T(0);
+    if (v && live) {
+        v0 = v[3 * l];
+        v1 = v[3 * l + 1];
+        v2 = v[3 * l + 2];
+    }
+    T u0 = 0, u1 = 0, u2 = 0, a0 = 0, a1 = 0, a2 = 0;
+    for (int k = sub; live && k < P; k += 4) {
+        if (c[2][k] < 0)
+            continue;
+        for (int j = 0; j < P; ++j) {
+            if (c[1][j] < 0)
+                continue;
             for (int i = 0; i < P; ++i) {
-                if ((c[0][i] | c[1][j] | c[2][k]) < 0)
+                if (c[0][i] < 0)
                     continue;
                 const int64_t off = cell_offset(g, c[0][i], c[1][j], c[2][k]);
                 if (off < 0)
                     continue;
-                const T dot = fld[off] * v0 + fld[off + g.cstride] * v1 +
-                              fld[off + 2 * g.cstride] * v2;
-                a0 += dot * dw[0][i] * w[1][j] * w[2][k];
+                const T f0 = fld[off], f1 = fld[off + g.cstride], f2 = fld[off + 2 * g.cstride];
+                const T wyz = w[1][j] * w[2][k];
+                const T wt = w[0][i] * wyz;
+                u0 += f0 * wt;
+                u1 += f1 * wt;
+                u2 += f2 * wt;
+                const T dot = f0 * v0 + f1 * v1 + f2 * v2;
+                a0 += dot * dw[0][i] * wyz;
                 a1 += dot * w[0][i] * dw[1][j] * w[2][k];
                 a2 += dot * w[0][i] * w[1][j] * dw[2][k];
             }
-    const double sc = use_dv ? dv[pid[l]] * g.inv_h3 : 1.0;
-    gX[3 * l + 0] += sc * (double)a0;
-    gX[3 * l + 1] += sc * (double)a1;
-    gX[3 * l + 2] += sc * (double)a2;
+        }
+    }
+    // fixed tree over the four lanes of the marker
+#pragma unroll
+    for (int o = 1; o < 4; o <<= 1) {
+        u0 += __shfl_xor(u0, o);
+        u1 += __shfl_xor(u1, o);
+        u2 += __shfl_xor(u2, o);
+        a0 += __shfl_xor(a0, o);
+        a1 += __shfl_xor(a1, o);
+        a2 += __shfl_xor(a2, o);
+    }
+    if (!live || sub != 0)
+        return;
+    if (U) {
+        U[3 * l + 0] = u0;
+        U[3 * l + 1] = u1;
+        U[3 * l + 2] = u2;
+    }
+    if (v) {
+        const double sc = use_dv ? dv[pid[l]] * g.inv_h3 : 1.0;
+        gX[3 * l + 0] += sc * (double)a0;
+        gX[3 * l + 1] += sc * (double)a1;
+        gX[3 * l + 2] += sc * (double)a2;
+    }
+}
+
+template <typename T>
+static void launch_interp_grad(const Grid& g, int P, const ib_markers* m, const T* fld, T* U,
+                               const T* v, int use_dv, double* gX, hipStream_t st)
+{
+    const int64_t nth = 4 * m->nl;
+    const unsigned gb = (unsigned)((nth + 255) / 256);
+    if (P == 3)
+        k_interp_grad<T, 3><<<gb, 256, 0, st>>>(g, m->nl, m->x, m->y, m->z, m->pid, m->dv, fld,
+                                                 U, v, use_dv, gX);
+    else
+        k_interp_grad<T, 4><<<gb, 256, 0, st>>>(g, m->nl, m->x, m->y, m->z, m->pid, m->dv, fld,
+                                                 U, v, use_dv, gX);
 }
 
 // a_F += (dV/h^3) Ui;  a_Ud += a_F/dt;  Ubar = -a_F/dt.
@@ -193,11 +260,14 @@ size_t backward_workspace(const Grid& g, ib_prec prec, int64_t nl)
     for (int k = 0; k < 3; ++k)
         cv.take<char>(s * 3 * nl);
     cv.take<double>(3 * nl);
+    if (tile_spread_supported(g))
+        cv.take<char>(tile_spread_workspace(g, prec, nl));
     return cv.used;
 }
 
 template <typename T>
-static int run_backward(const Grid& g, int P, const ib_particles* p, const ib_markers* m,
+static int run_backward(const Grid& g, int P, const BatchedCfg& cfg, const ib_particles* p,
+                        const ib_markers* m,
                         const ib_buckets* b, int ns, double dt, const T* u0, const T* Fhist,
                         const T* gus, const T* gf, const T* gF, T* gu0, double* gup,
                         double* gom, double* gX, void* ws, size_t ws_bytes, hipStream_t st)
@@ -212,8 +282,16 @@ static int run_backward(const Grid& g, int P, const ib_particles* p, const ib_ma
     T* Ub = cv.take<T>(3 * nl);
     T* Ui = cv.take<T>(3 * nl);
     double* aUd = cv.take<double>(3 * nl);
+    const bool tiled = tile_spread_supported(g);
+    const size_t tsb = tiled ? tile_spread_workspace(g, prec, nl) : 0;
+    void* tws = tiled ? cv.take<char>(tsb) : nullptr;
     if (!ws || !cv.ok())
         return IB_EWORKSPACE;
+    if (tiled) {
+        const int rc = tile_spread_setup(g, P, prec, cfg, p, m, b, tws, tsb, st);
+        if (rc)
+            return rc;
+    }
     const unsigned gc = grid_n((int64_t)g.nbox * g.box * g.box * g.box);
     const unsigned gm = grid_n(nl);
     k_field_op<T, 0><<<gc, 256, 0, st>>>(g, gu0, nullptr, nullptr, nullptr, dt);
@@ -232,33 +310,51 @@ static int run_backward(const Grid& g, int P, const ib_particles* p, const ib_ma
     }
     for (int mi = ns; mi >= 1; --mi) {
         const T* Fm = Fhist + (int64_t)(mi - 1) * 3 * nl;
-        k_field_op<T, 4><<<gc, 256, 0, st>>>(g, gu0, au, af, nullptr, dt);
+        // a_f holds g_f on the first step and nothing afterwards
+        if (mi == ns)
+            k_field_op<T, 4><<<gc, 256, 0, st>>>(g, gu0, au, af, nullptr, dt);
+        else
+            k_field_op<T, 5><<<gc, 256, 0, st>>>(g, gu0, au, af, nullptr, dt);
         if (nl > 0) {
-            plain_interp(g, P, prec, m, af, Ui, st);
-            if (P == 3)
-                k_grad_pos<T, 3><<<gm, 256, 0, st>>>(g, nl, m->x, m->y, m->z, m->pid, m->dv, af,
-                                                     Fm, 1, gX);
-            else
-                k_grad_pos<T, 4><<<gm, 256, 0, st>>>(g, nl, m->x, m->y, m->z, m->pid, m->dv, af,
-                                                     Fm, 1, gX);
+            // U = J a_f and the position gradient of S^T with F^m, one gather
+            if (tiled) {
+                const int rc = tile_interp_grad(g, P, prec, cfg, m, b, af, Fm, Ui, 1, gX, tws,
+                                                tsb, st);
+                if (rc)
+                    return rc;
+            } else {
+                launch_interp_grad<T>(g, P, m, af, Ui, Fm, 1, gX, st);
+            }
             k_marker_step<T><<<gm, 256, 0, st>>>(g, nl, dt, m->pid, m->dv, Ui, aF, aUd, Ub);
         }
         const T* uprev = u0;
         if (mi > 1) {
-            plain_spread(g, P, prec, m, b, Fhist + (int64_t)(mi - 2) * 3 * nl, tmp, 1.0, 1, st);
-            k_field_op<T, 3><<<gc, 256, 0, st>>>(g, tmp, tmp, nullptr, u0, dt);
+            const T* Fp = Fhist + (int64_t)(mi - 2) * 3 * nl;
+            if (tiled) {
+                const int rc = tile_spread(g, P, prec, cfg, m, b, Fp, 1, u0, dt, tmp, tws, tsb, st);
+                if (rc)
+                    return rc;
+            } else {
+                plain_spread(g, P, prec, m, b, Fp, tmp, 1.0, 1, st);
+                k_field_op<T, 3><<<gc, 256, 0, st>>>(g, tmp, tmp, nullptr, u0, dt);
+            }
             uprev = tmp;
         }
-        if (nl > 0) {
-            if (P == 3)
-                k_grad_pos<T, 3><<<gm, 256, 0, st>>>(g, nl, m->x, m->y, m->z, m->pid, m->dv,
-                                                     uprev, Ub, 0, gX);
-            else
-                k_grad_pos<T, 4><<<gm, 256, 0, st>>>(g, nl, m->x, m->y, m->z, m->pid, m->dv,
-                                                     uprev, Ub, 0, gX);
+        if (nl > 0 && tiled) {
+            const int rc = tile_interp_grad(g, P, prec, cfg, m, b, uprev, Ub, nullptr, 0, gX, tws,
+                                            tsb, st);
+            if (rc)
+                return rc;
+        } else if (nl > 0) {
+            launch_interp_grad<T>(g, P, m, uprev, nullptr, Ub, 0, gX, st);
         }
-        plain_spread(g, P, prec, m, b, Ub, au, 1.0, 0, st);
-        k_field_op<T, 0><<<gc, 256, 0, st>>>(g, af, nullptr, nullptr, nullptr, dt);
+        if (tiled) {
+            const int rc = tile_spread(g, P, prec, cfg, m, b, Ub, 0, nullptr, dt, au, tws, tsb, st);
+            if (rc)
+                return rc;
+        } else {
+            plain_spread(g, P, prec, m, b, Ub, au, 1.0, 0, st);
+        }
     }
     k_field_op<T, 2><<<gc, 256, 0, st>>>(g, gu0, au, nullptr, nullptr, dt);
     if (p->np > 0)
@@ -267,7 +363,8 @@ static int run_backward(const Grid& g, int P, const ib_particles* p, const ib_ma
     return launch_status();
 }
 
-int multidirect_backward(const Grid& g, int P, ib_prec prec, const ib_particles* p,
+int multidirect_backward(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg,
+                         const ib_particles* p,
                          const ib_markers* m, const ib_buckets* b, int ns, double dt,
                          const void* u0, const void* Fhist, const void* gus, const void* gf,
                          const void* gF, void* gu0, double* gup, double* gom, double* gX,
@@ -275,12 +372,12 @@ int multidirect_backward(const Grid& g, int P, ib_prec prec, const ib_particles*
 {
     int rc;
     if (prec == IB_F64)
-        rc = run_backward<double>(g, P, p, m, b, ns, dt, (const double*)u0,
+        rc = run_backward<double>(g, P, cfg, p, m, b, ns, dt, (const double*)u0,
                                   (const double*)Fhist, (const double*)gus, (const double*)gf,
                                   (const double*)gF, (double*)gu0, gup, gom, gX, ws, ws_bytes,
                                   st);
     else
-        rc = run_backward<float>(g, P, p, m, b, ns, dt, (const float*)u0, (const float*)Fhist,
+        rc = run_backward<float>(g, P, cfg, p, m, b, ns, dt, (const float*)u0, (const float*)Fhist,
                                  (const float*)gus, (const float*)gf, (const float*)gF,
                                  (float*)gu0, gup, gom, gX, ws, ws_bytes, st);
     if (rc)

@@ -115,6 +115,40 @@ __device__ inline void axis_weights_r(T r, T* w)
     }
 }
 
+// The same P weights and their derivatives with respect to r (= with respect
+// to the grid coordinate s; divide by h for the derivative in X).  P = 4:
+// dq/dd = (1 - 2d)/(4 sqrt(1 + 4d - 4d^2)); P = 3: dq/dd = -3d/q.  The roots
+// stay away from zero on these branches (1 + 4d - 4d^2 >= 1, 1 - 3d^2 >= 1/4).
+template <typename T, int P>
+__device__ inline void axis_weights_rd(T r, T* w, T* dw)
+{
+    const T d = r - T(1);
+    if (P == 4) {
+        const T S = root(T(1) + T(4) * d * (T(1) - d));
+        const T q = S * T(0.125);
+        const T dq = (T(1) - T(2) * d) / (T(4) * S);
+        const T a = T(0.375) - T(0.25) * d, b = T(0.125) + T(0.25) * d;
+        w[0] = a - q;
+        w[1] = a + q;
+        w[2] = b + q;
+        w[3] = b - q;
+        dw[0] = T(-0.25) - dq;
+        dw[1] = T(-0.25) + dq;
+        dw[2] = T(0.25) + dq;
+        dw[3] = T(0.25) - dq;
+    } else {
+        const T q = root(T(1) - T(3) * d * d);
+        const T q6 = q * T(1.0 / 6.0);
+        const T dq = T(-3) * d / q;
+        w[0] = T(1.0 / 3.0) - T(0.5) * d - q6;
+        w[1] = T(1.0 / 3.0) + T(1.0 / 3.0) * q;
+        w[P - 1] = T(1.0 / 3.0) + T(0.5) * d - q6;
+        dw[0] = T(-0.5) - dq * T(1.0 / 6.0);
+        dw[1] = dq * T(1.0 / 3.0);
+        dw[P - 1] = T(0.5) - dq * T(1.0 / 6.0);
+    }
+}
+
 template <typename T>
 struct MarkerData {
     typename Vec4<T>::type* geo;      // [n] (r_x, r_y, r_z, dV/h^3)
@@ -452,7 +486,7 @@ int resident_grid(int ncu, int cap)
 // In place (ustar == u0) only the cells whose force is not exactly zero are
 // read and rewritten (u0 + dt 0 = u0): inside the tiles that have a force
 // slot, most cells lie outside every stencil.  With f_acc, f += G^ns instead,
-// on the same cells.
+// on the same cells.  ustar may be null (f only).
 template <typename T, bool F_ACC>
 __global__ void __launch_bounds__(256)
 k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, const T* u0,
@@ -489,6 +523,8 @@ k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, co
                     __builtin_nontemporal_store(v, &f[o]);
                 else if (f && v != T(0))
                     f[o] += v;
+                if (!ustar)
+                    continue;
                 if (v != T(0))
                     __builtin_nontemporal_store(u0[o] + tdt * v, &ustar[o]);
                 else if (ustar != u0)
@@ -558,7 +594,8 @@ k_finalize_pairs(Grid g, const int32_t* __restrict__ slot, const T* __restrict__
                     V2 w = *reinterpret_cast<const V2*>(f + o);
                     *reinterpret_cast<V2*>(f + o) = w + v;
                 }
-                if (force) {
+                if (!ustar) {
+                } else if (force) {
                     const V2 a = *reinterpret_cast<const V2*>(u0 + o);
                     __builtin_nontemporal_store(a + tdt * v, reinterpret_cast<V2*>(ustar + o));
                 } else if (ustar != u0) {
@@ -673,26 +710,69 @@ template <typename T, int P, int MODE>
 static void launch_interp(const BatchedCfg& cfg, hipStream_t st, const Grid& g, int64_t nl,
                           double dt, const Item* items, const int32_t* nitems, const T* u0,
                           const T* G, const int64_t* nbase, const MarkerData<T>& s, double* e2,
-                          T* Fout = nullptr, const int32_t* perm = nullptr)
+                          T* Fout = nullptr, const int32_t* perm = nullptr,
+                          const T* vin = nullptr, double* gX = nullptr, int use_dv = 0)
 {
     if (cfg.bw == 64)
         k_interp_tiles<T, P, MODE, 64>
             <<<resident_grid<k_interp_tiles<T, P, MODE, 64>, 64>(cfg.ncu, 0), 64, 0, st>>>(
-                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm);
+                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm, vin, gX, use_dv);
     else if (cfg.bw == 128)
         k_interp_tiles<T, P, MODE, 128>
             <<<resident_grid<k_interp_tiles<T, P, MODE, 128>, 128>(cfg.ncu, 0), 128, 0, st>>>(
-                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm);
+                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm, vin, gX, use_dv);
     else
         k_interp_tiles<T, P, MODE, 256>
             <<<resident_grid<k_interp_tiles<T, P, MODE, 256>, 256>(cfg.ncu, 0), 256, 0, st>>>(
-                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm);
+                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm, vin, gX, use_dv);
 }
 
 #define IBX_PROF_BEGIN(k) \
     if (cfg.prof) cfg.prof->begin(k, st)
 #define IBX_PROF_END() \
     if (cfg.prof) cfg.prof->end(st)
+
+// Marker records in bucket order and the work lists of the tile kernels
+// (interpolation items, G slots, spreading order, neighbour offsets).
+template <typename T, int P>
+static void records_and_lists(const Grid& g, const BatchedCfg& cfg, const ib_particles* p,
+                              const ib_markers* m, const ib_buckets* b, BatchedWs<T>& w,
+                              hipStream_t st)
+{
+    const int64_t nl = m->nl;
+    const int64_t T_ = g.ntiles;
+    const unsigned gm = (unsigned)((nl + 255) / 256 > 0 ? (nl + 255) / 256 : 1);
+    const unsigned gt = (unsigned)((T_ + 255) / 256);
+    IBX_PROF_BEGIN(PK_PREP);
+    k_prep<T, P><<<gm, 256, 0, st>>>(g, nl, m->x, m->y, m->z, m->pid, m->dv, b->perm, p->xc,
+                                     p->up, p->om, w.s);
+    IBX_PROF_END();
+    IBX_PROF_BEGIN(PK_LISTS);
+    const int64_t nbl = (T_ + SCAN_TILE - 1) / SCAN_TILE;
+    if (2 * nbl <= SCAN_FUSE) {
+        int32_t* sums = (int32_t*)w.scan;
+        k_list_scan<<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
+            T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs, w.act_offs, sums, w.hist);
+        k_list_add<<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
+            T_, b->src_offs, w.item_offs, w.act_offs, sums, w.nitems, w.nactive, w.hist);
+    } else {
+        k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt,
+                                          w.act, w.hist);
+        scan_exclusive2(w.item_cnt, w.item_offs, w.act, w.act_offs, T_, w.nitems, w.nactive,
+                        w.scan, st);
+        k_cost_hist<<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.hist);
+    }
+    k_bin_scan<<<NXCD, COST_BINS, 0, st>>>(w.hist, w.nactive, w.cur);
+    k_fill_lists<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs,
+                                     w.act_offs, w.nactive, w.items, w.slot, w.cur,
+                                     w.sent);
+    {
+        const int64_t nth = 27 * w.max_items;
+        k_item_bases<<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(g, w.items, w.nitems, w.slot,
+                                                                    w.nb_u, w.nb_g);
+    }
+    IBX_PROF_END();
+}
 
 // Every output set to NaN when the bucket set is flagged (checked on the
 // device at the end of the loop; nothing is read back).
@@ -736,35 +816,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         poison_outputs(g, b, ustar, f, F, resid, Fhist, nl, ns, st);
         return launch_status();
     }
-    IBX_PROF_BEGIN(PK_PREP);
-    k_prep<T, P><<<gm, 256, 0, st>>>(g, nl, m->x, m->y, m->z, m->pid, m->dv, b->perm, p->xc,
-                                     p->up, p->om, w.s);
-    IBX_PROF_END();
-    IBX_PROF_BEGIN(PK_LISTS);
-    const int64_t nbl = (T_ + SCAN_TILE - 1) / SCAN_TILE;
-    if (2 * nbl <= SCAN_FUSE) {
-        int32_t* sums = (int32_t*)w.scan;
-        k_list_scan<<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
-            T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs, w.act_offs, sums, w.hist);
-        k_list_add<<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
-            T_, b->src_offs, w.item_offs, w.act_offs, sums, w.nitems, w.nactive, w.hist);
-    } else {
-        k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt,
-                                          w.act, w.hist);
-        scan_exclusive2(w.item_cnt, w.item_offs, w.act, w.act_offs, T_, w.nitems, w.nactive,
-                        w.scan, st);
-        k_cost_hist<<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.hist);
-    }
-    k_bin_scan<<<NXCD, COST_BINS, 0, st>>>(w.hist, w.nactive, w.cur);
-    k_fill_lists<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs,
-                                     w.act_offs, w.nactive, w.items, w.slot, w.cur,
-                                     w.sent);
-    {
-        const int64_t nth = 27 * w.max_items;
-        k_item_bases<<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(g, w.items, w.nitems, w.slot,
-                                                                    w.nb_u, w.nb_g);
-    }
-    IBX_PROF_END();
+    records_and_lists<T, P>(g, cfg, p, m, b, w, st);
     double* e2 = resid ? w.e2 : nullptr;
     IBX_PROF_BEGIN(PK_INTERP_U0);
     // the last interpolation of the loop also writes F in marker order
@@ -786,7 +838,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         IBX_PROF_BEGIN(PK_SPREAD);
         k_spread_tiles<T, P>
             <<<resident_grid<k_spread_tiles<T, P>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
-                w.sent, w.nactive, b->src_idx, g, w.s, w.G);
+                w.sent, w.nactive, b->src_idx, g, w.s, w.G, 1);
         IBX_PROF_END();
         IBX_PROF_BEGIN(PK_INTERP_G);
         launch_interp<T, P, 1>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_g, w.s, e2,
@@ -801,7 +853,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     IBX_PROF_BEGIN(PK_SPREAD_FINAL);
     k_spread_tiles<T, P>
         <<<resident_grid<k_spread_tiles<T, P>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
-            w.sent, w.nactive, b->src_idx, g, w.s, w.G);
+            w.sent, w.nactive, b->src_idx, g, w.s, w.G, 1);
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_FILL);
     launch_finalize<T>(gfin, st, g, w.slot, w.G, u0, ustar, f, dt, 1, f_acc);
@@ -814,6 +866,156 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         sum_to(w.e2, nl, w.part, resid + ns, true, st);
     }
     poison_outputs(g, b, ustar, f, F, resid, Fhist, nl, ns, st);
+    return launch_status();
+}
+
+// ------------------------------------------------------------------ spreading outside the loop
+
+// The spreads of the adjoint (the recomputed u^(m-1) = u0 + dt S F^(m-1) and
+// the transpose of interpolation, J^T Ubar) run on the loop's tile kernel:
+// tile_spread_setup forms the marker records and work lists once per call,
+// then each tile_spread puts its marker vector into bucket order, spreads it
+// into the G slots and writes the field.
+
+template <typename T>
+__global__ void k_sort_vec(int64_t nl, const int32_t* __restrict__ perm, const T* __restrict__ v,
+                           typename Vec4<T>::type* __restrict__ f4)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl)
+        return;
+    const int64_t l = perm[i];
+    typename Vec4<T>::type q;
+    q.x = v[3 * l];
+    q.y = v[3 * l + 1];
+    q.z = v[3 * l + 2];
+    q.w = T(0);
+    f4[i] = q;
+}
+
+bool tile_spread_supported(const Grid& g)
+{
+    for (int a = 0; a < 3; ++a)
+        if (g.n[a] < 2 * TILE || g.n[a] > (int)RB_MASK - RB_BIAS)
+            return false;
+    return g.box <= 64 * TILE;
+}
+
+size_t tile_spread_workspace(const Grid& g, ib_prec prec, int64_t nl)
+{
+    BatchedCfg c{};
+    c.bw = 64;
+    return batched_workspace(g, prec, nl, c);
+}
+
+template <typename T, int P>
+static void setup_t(const Grid& g, const BatchedCfg& cfg, const ib_particles* p,
+                    const ib_markers* m, const ib_buckets* b, void* ws, size_t bytes,
+                    hipStream_t st)
+{
+    size_t need = 0;
+    BatchedWs<T> w = carve_batched<T>(g, m->nl, cfg.bw, ws, bytes, &need);
+    records_and_lists<T, P>(g, cfg, p, m, b, w, st);
+}
+
+int tile_spread_setup(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg,
+                      const ib_particles* p, const ib_markers* m, const ib_buckets* b, void* ws,
+                      size_t ws_bytes, hipStream_t st)
+{
+    if (ws_bytes < tile_spread_workspace(g, prec, m->nl) || m->nl == 0)
+        return m->nl == 0 ? IB_OK : IB_EWORKSPACE;
+    BatchedCfg c = cfg;
+    c.prof = nullptr;
+    if (prec == IB_F64)
+        P == 3 ? setup_t<double, 3>(g, c, p, m, b, ws, ws_bytes, st)
+               : setup_t<double, 4>(g, c, p, m, b, ws, ws_bytes, st);
+    else
+        P == 3 ? setup_t<float, 3>(g, c, p, m, b, ws, ws_bytes, st)
+               : setup_t<float, 4>(g, c, p, m, b, ws, ws_bytes, st);
+    return launch_status();
+}
+
+template <typename T, int P>
+static void spread_t(const Grid& g, const BatchedCfg& cfg, const ib_markers* m,
+                     const ib_buckets* b, const T* v, int use_dv, const T* u0, double dt, T* out,
+                     void* ws, size_t bytes, hipStream_t st)
+{
+    size_t need = 0;
+    const int64_t nl = m->nl;
+    BatchedWs<T> w = carve_batched<T>(g, nl, cfg.bw, ws, bytes, &need);
+    const int64_t nfin = (int64_t)g.nbox * (g.box / TILE) * g.box;
+    const unsigned gfin = (unsigned)(nfin < 65535 ? (nfin > 0 ? nfin : 1) : 65535);
+    if (nl > 0) {
+        k_sort_vec<T><<<(unsigned)((nl + 255) / 256), 256, 0, st>>>(nl, b->perm, v, w.s.f4);
+        k_spread_tiles<T, P>
+            <<<resident_grid<k_spread_tiles<T, P>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
+                w.sent, w.nactive, b->src_idx, g, w.s, w.G, use_dv);
+    }
+    // u0 given: out = u0 + dt G; else out = G (zero where no marker reaches)
+    if (u0)
+        launch_finalize<T>(gfin, st, g, w.slot, w.G, u0, out, nullptr, dt, nl > 0, 0);
+    else
+        launch_finalize<T>(gfin, st, g, w.slot, w.G, nullptr, nullptr, out, dt, nl > 0, 0);
+}
+
+int tile_spread(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg, const ib_markers* m,
+                const ib_buckets* b, const void* v, int use_dv, const void* u0, double dt,
+                void* out, void* ws, size_t ws_bytes, hipStream_t st)
+{
+    if (ws_bytes < tile_spread_workspace(g, prec, m->nl))
+        return IB_EWORKSPACE;
+    if (prec == IB_F64) {
+        if (P == 3)
+            spread_t<double, 3>(g, cfg, m, b, (const double*)v, use_dv, (const double*)u0, dt,
+                                (double*)out, ws, ws_bytes, st);
+        else
+            spread_t<double, 4>(g, cfg, m, b, (const double*)v, use_dv, (const double*)u0, dt,
+                                (double*)out, ws, ws_bytes, st);
+    } else {
+        if (P == 3)
+            spread_t<float, 3>(g, cfg, m, b, (const float*)v, use_dv, (const float*)u0, dt,
+                               (float*)out, ws, ws_bytes, st);
+        else
+            spread_t<float, 4>(g, cfg, m, b, (const float*)v, use_dv, (const float*)u0, dt,
+                               (float*)out, ws, ws_bytes, st);
+    }
+    return launch_status();
+}
+
+template <typename T, int P>
+static void interp_grad_t(const Grid& g, const BatchedCfg& cfg, const ib_markers* m,
+                          const ib_buckets* b, const T* fld, const T* v, T* U, int use_dv,
+                          double* gX, void* ws, size_t bytes, hipStream_t st)
+{
+    size_t need = 0;
+    BatchedWs<T> w = carve_batched<T>(g, m->nl, cfg.bw, ws, bytes, &need);
+    launch_interp<T, P, 3>(cfg, st, g, m->nl, 0.0, w.items, w.nitems, fld, nullptr, w.nb_u, w.s,
+                           nullptr, U, b->perm, v, gX, use_dv);
+}
+
+int tile_interp_grad(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg,
+                     const ib_markers* m, const ib_buckets* b, const void* fld, const void* v,
+                     void* U, int use_dv, double* gX, void* ws, size_t ws_bytes, hipStream_t st)
+{
+    if (ws_bytes < tile_spread_workspace(g, prec, m->nl))
+        return IB_EWORKSPACE;
+    if (m->nl == 0)
+        return IB_OK;
+    if (prec == IB_F64) {
+        if (P == 3)
+            interp_grad_t<double, 3>(g, cfg, m, b, (const double*)fld, (const double*)v,
+                                     (double*)U, use_dv, gX, ws, ws_bytes, st);
+        else
+            interp_grad_t<double, 4>(g, cfg, m, b, (const double*)fld, (const double*)v,
+                                     (double*)U, use_dv, gX, ws, ws_bytes, st);
+    } else {
+        if (P == 3)
+            interp_grad_t<float, 3>(g, cfg, m, b, (const float*)fld, (const float*)v,
+                                    (float*)U, use_dv, gX, ws, ws_bytes, st);
+        else
+            interp_grad_t<float, 4>(g, cfg, m, b, (const float*)fld, (const float*)v,
+                                    (float*)U, use_dv, gX, ws, ws_bytes, st);
+    }
     return launch_status();
 }
 

@@ -37,6 +37,26 @@ int batched_multidirect(const Grid& g, int P, ib_prec prec, const BatchedCfg& cf
                         double dt, const void* u0, void* ustar, void* f, void* F, double* resid,
                         void* Fhist, void* ws, size_t ws_bytes, hipStream_t st, int f_acc = 0);
 
+// Spreading with the loop's tile kernel outside the loop (the adjoint):
+// records and work lists once per call, then out = S v (use_dv: with dV/h^3,
+// else without) on every valid covered cell, or out = u0 + dt S v when u0 is
+// given.  v: [nl][3] in marker order.  Grids with fewer than 16 cells on an
+// axis, or boxes above 512, are not supported (tile_spread_supported).
+bool tile_spread_supported(const Grid& g);
+size_t tile_spread_workspace(const Grid& g, ib_prec prec, int64_t nl);
+int tile_spread_setup(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg,
+                      const ib_particles* p, const ib_markers* m, const ib_buckets* b, void* ws,
+                      size_t ws_bytes, hipStream_t st);
+int tile_spread(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg, const ib_markers* m,
+                const ib_buckets* b, const void* v, int use_dv, const void* u0, double dt,
+                void* out, void* ws, size_t ws_bytes, hipStream_t st);
+// With the same set-up: U = J fld (U nullable, marker order) and
+// gX += sc sum over the stencil of (fld . v_l) grad_X w_l, sc = dV/h^3
+// (use_dv) or 1, for a field fld in the box layout and v [nl][3].
+int tile_interp_grad(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg,
+                     const ib_markers* m, const ib_buckets* b, const void* fld, const void* v,
+                     void* U, int use_dv, double* gX, void* ws, size_t ws_bytes, hipStream_t st);
+
 // Particle-by-particle order of the loop, run level by level (sequential.hip).
 constexpr int SEQ_MAX_LEVELS = 4096;
 size_t sequential_workspace(const ib_level* lv, const Grid& g, ib_prec prec, int32_t np,
@@ -51,7 +71,8 @@ int sequential_multidirect(const ib_level* lv, const Grid& g, int P, ib_prec pre
 
 namespace ibx {
 size_t backward_workspace(const Grid& g, ib_prec prec, int64_t nl);
-int multidirect_backward(const Grid& g, int P, ib_prec prec, const ib_particles* p,
+int multidirect_backward(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg,
+                         const ib_particles* p,
                          const ib_markers* m, const ib_buckets* b, int ns, double dt,
                          const void* u0, const void* Fhist, const void* gus, const void* gf,
                          const void* gF, void* gu0, double* gup, double* gom, double* gX,

@@ -90,14 +90,20 @@ __global__ void k_item_bases(Grid g, const Item* __restrict__ items,
 // mode 0: field = u0 (box layout): D = (U^d - J u0)/dt, F = D.
 // mode 1: field = G (slots): F += D - J G.
 // mode 2: field = G (slots): residual only.
+// mode 3: field = u0 (any field in the box layout), for the adjoint:
+//         Fout[l] = J field (if Fout) and gX[l] += sc sum over the stencil of
+//         (field . vin_l) grad_X w_l, sc = dV/h^3 (use_dv) or 1, in marker
+//         order (the weights' derivatives from the same shared root).
 // e2 (nullable) receives dV |U^d - J u^(m)|^2 per marker.
 template <typename T, int P, int MODE, int BW>
 __global__ void __launch_bounds__(BW)
 k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                const int32_t* __restrict__ nitems, const T* __restrict__ u0,
                const T* __restrict__ G, const int64_t* __restrict__ nbase, MarkerData<T> s,
-               double* __restrict__ e2, T* __restrict__ Fout, const int32_t* __restrict__ perm)
+               double* __restrict__ e2, T* __restrict__ Fout, const int32_t* __restrict__ perm,
+               const T* __restrict__ vin, double* __restrict__ gX, int use_dv)
 {
+    constexpr bool BOX = MODE == 0 || MODE == 3;   // field in the box layout
     constexpr int gh = Halo<P>::g, R = Halo<P>::R;
     // LDS holds the halo as rows [c][jz][jy] of pitch RP = 12 with halo x
     // index jx at position jx + XO, so the tile's own 8 cells sit at 2..9
@@ -109,10 +115,10 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     const int n_items = *nitems;
     const double h3 = g.h * g.h * g.h;
     const int tid = threadIdx.x;
-    const int64_t comp = MODE == 0 ? g.cstride : (int64_t)TILE_CELLS;
-    const int sy = MODE == 0 ? g.ext : TILE;
-    const int sz = MODE == 0 ? g.ext * g.ext : TILE * TILE;
-    const T* src = MODE == 0 ? u0 : G;
+    const int64_t comp = BOX ? g.cstride : (int64_t)TILE_CELLS;
+    const int sy = BOX ? g.ext : TILE;
+    const int sz = BOX ? g.ext * g.ext : TILE * TILE;
+    const T* src = BOX ? u0 : G;
     const bool paired = true;   // tile slots: rows start on multiples of 8 elements
     const Slab sl = xcd_slab(n_items);
     // the neighbour offsets of each item are loaded one item ahead, so the
@@ -138,8 +144,9 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
         const bool mine = (tid >> lg) < cnt;
         const int64_t i = item.start + (mine ? (tid >> lg) : 0);
         int lb[3];
-        T w[3][P];
+        T w[3][P], dw[3][P];
         T dd[3] = {T(0), T(0), T(0)};
+        T vv[3] = {T(0), T(0), T(0)};
         T rs = T(0);
         typename Vec4<T>::type fv;
         fv.x = fv.y = fv.z = fv.w = T(0);
@@ -147,14 +154,24 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
             const typename Vec4<T>::type gq = s.geo[i];
             int rb[3];
             unpack_rb(s.rb[i], rb);
-            axis_weights_r<T, P>(gq.x, w[0]);
-            axis_weights_r<T, P>(gq.y, w[1]);
-            axis_weights_r<T, P>(gq.z, w[2]);
+            if (MODE == 3) {
+                axis_weights_rd<T, P>(gq.x, w[0], dw[0]);
+                axis_weights_rd<T, P>(gq.y, w[1], dw[1]);
+                axis_weights_rd<T, P>(gq.z, w[2], dw[2]);
+                const int64_t l = perm[i];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    vv[c] = vin[3 * l + c];
+            } else {
+                axis_weights_r<T, P>(gq.x, w[0]);
+                axis_weights_r<T, P>(gq.y, w[1]);
+                axis_weights_r<T, P>(gq.z, w[2]);
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a)
                 lb[a] = rb[a] - lo[a] + gh;
             rs = gq.w;
-            if (sub == 0) {
+            if (sub == 0 && MODE != 3) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     dd[c] = MODE == 0 ? s.ud[c * nl + i] : s.d[c * nl + i];
@@ -162,7 +179,7 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                     fv = s.f4[i];
             }
         }
-        if (MODE == 0) {
+        if (BOX) {
             // box layout: rows are a box extent apart, so consecutive lanes
             // take consecutive cells of the halo
             constexpr int R3 = R * R * R, NPT = (R3 + BW - 1) / BW;
@@ -191,7 +208,7 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
         }
         // tile slots: stage the halo row by row -- left segment (gh cells of
         // the -x neighbour), the 8 cells of the middle tile, right segment
-        for (int task = tid; MODE != 0 && task < NROW; task += BW) {
+        for (int task = tid; !BOX && task < NROW; task += BW) {
             const int c = task / (R * R), rr = task - c * (R * R);
             const int jy = rr % R, jz = rr / R;
             const int ys = (jy - gh + TILE) >> 3, zs = (jz - gh + TILE) >> 3;
@@ -263,6 +280,7 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
         }
         __syncthreads();
         T acc0 = 0, acc1 = 0, acc2 = 0;
+        T gr0 = 0, gr1 = 0, gr2 = 0;      // mode 3: position gradient
         if (mine) {
             bool ok = true;
 #pragma unroll
@@ -274,10 +292,13 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                 const int k = sub + (n << lg);
                 if (!ok || k >= P)
                     continue;
-                T wz = w[2][0];
+                T wz = w[2][0], dwz = MODE == 3 ? dw[2][0] : T(0);
 #pragma unroll
-                for (int o = 1; o < P; ++o)
+                for (int o = 1; o < P; ++o) {
                     wz = k == o ? w[2][o] : wz;
+                    if (MODE == 3)
+                        dwz = k == o ? dw[2][o] : dwz;
+                }
 #pragma unroll
                 for (int j = 0; j < P; ++j) {
                     const T wyz = w[1][j] * wz;
@@ -285,9 +306,17 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
 #pragma unroll
                     for (int q = 0; q < P; ++q) {
                         const T wt = w[0][q] * wyz;
-                        acc0 += fld[row + q] * wt;
-                        acc1 += fld[PL + row + q] * wt;
-                        acc2 += fld[2 * PL + row + q] * wt;
+                        const T f0 = fld[row + q], f1 = fld[PL + row + q],
+                                f2 = fld[2 * PL + row + q];
+                        acc0 += f0 * wt;
+                        acc1 += f1 * wt;
+                        acc2 += f2 * wt;
+                        if (MODE == 3) {
+                            const T dot = f0 * vv[0] + f1 * vv[1] + f2 * vv[2];
+                            gr0 += dot * dw[0][q] * wyz;
+                            gr1 += dot * w[0][q] * dw[1][j] * wz;
+                            gr2 += dot * w[0][q] * w[1][j] * dwz;
+                        }
                     }
                 }
             }
@@ -296,13 +325,36 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
             acc0 += __shfl_xor(acc0, 1);
             acc1 += __shfl_xor(acc1, 1);
             acc2 += __shfl_xor(acc2, 1);
+            if (MODE == 3) {
+                gr0 += __shfl_xor(gr0, 1);
+                gr1 += __shfl_xor(gr1, 1);
+                gr2 += __shfl_xor(gr2, 1);
+            }
         }
         if (lg >= 2) {
             acc0 += __shfl_xor(acc0, 2);
             acc1 += __shfl_xor(acc1, 2);
             acc2 += __shfl_xor(acc2, 2);
+            if (MODE == 3) {
+                gr0 += __shfl_xor(gr0, 2);
+                gr1 += __shfl_xor(gr1, 2);
+                gr2 += __shfl_xor(gr2, 2);
+            }
         }
-        if (mine && sub == 0) {
+        if (MODE == 3 && mine && sub == 0) {
+            const int64_t l = perm[i];
+            if (Fout) {
+                Fout[3 * l + 0] = acc0;
+                Fout[3 * l + 1] = acc1;
+                Fout[3 * l + 2] = acc2;
+            }
+            // d/dX = (d/ds) / h
+            const double sc = (use_dv ? (double)rs : 1.0) / g.h;
+            gX[3 * l + 0] += sc * (double)gr0;
+            gX[3 * l + 1] += sc * (double)gr1;
+            gX[3 * l + 2] += sc * (double)gr2;
+        }
+        if (MODE != 3 && mine && sub == 0) {
             const T acc[3] = {acc0, acc1, acc2};
             double err = 0.0;
             const T idt = (T)(1.0 / dt);
@@ -417,7 +469,8 @@ __device__ inline uint64_t drop_low_bits(uint64_t m, int s)
 //
 // Sources are staged 64 at a time as structure-of-arrays in LDS: the weight
 // of every tile x cell (zero outside the stencil), the P weights along y and
-// along z with the stencil's first row, and F dV/h^3.  Sixteen ballots give,
+// along z with the stencil's first row, and F dV/h^3 (F alone when use_dv is
+// 0: the transpose of interpolation in the adjoint).  Sixteen ballots give,
 // per tile row y and per tile row z, the 64-bit set of staged sources whose
 // stencil covers it; a lane's own set is the AND of its two, and the lane
 // visits exactly those sources in list order.  Each lane holds one (y, z) row
@@ -431,7 +484,7 @@ __global__ void __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8)))
 k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactive,
                const int32_t* __restrict__ src_idx, Grid g, MarkerData<T> s,
-               T* __restrict__ G)
+               T* __restrict__ G, int use_dv)
 {
     constexpr int NW = TILE + 2 * P + 3;                   // staged values per source
     constexpr int NBUF = NW * 64;
@@ -523,9 +576,10 @@ k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactiv
                     sz[o * 64 + lane] = gw[2][o];
                 }
                 sb[lane] = make_int2(lane - 64 * by, lane - 64 * bz);
-                sf[0 * 64 + lane] = Fv.x * gq.w;
-                sf[1 * 64 + lane] = Fv.y * gq.w;
-                sf[2 * 64 + lane] = Fv.z * gq.w;
+                const T sc = use_dv ? gq.w : T(1);
+                sf[0 * 64 + lane] = Fv.x * sc;
+                sf[1 * 64 + lane] = Fv.y * sc;
+                sf[2 * 64 + lane] = Fv.z * sc;
             }
             uint64_t my = 0, mz = 0;
 #pragma unroll
