@@ -196,6 +196,12 @@ def big_workload_leg(args, dev, timed, timed_median):
            "dominant_frac": (ITERATIONS_PER_LAUNCH.get(dom, 0) * bit /
                              (kern[dom]["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS)}
     log(f"spheres20000_512: {N} markers, C {C}, loop {ms:.3f} ms, frac {res['loop_frac']:.3f}")
+    # the collision force of Eq. (DKT_model) on the clumped spheres (bin search)
+    rho_p = torch.full((wl.npart,), 2.0, dtype=torch.float64, device=dev)
+    ibx.collision_forces(dl, parts, rho_p, 9.81, 1e-4)
+    res["collision_forces_ms"] = timed_median(
+        lambda: ibx.collision_forces(dl, parts, rho_p, 9.81, 1e-4), args.steps)
+    log(f"spheres20000_512: collision forces {res['collision_forces_ms']:.3f} ms")
     del u, f, F, plan
     return res
 

@@ -342,9 +342,16 @@ int ib_advect_markers(const ib_markers* m, const double* xc_n, const double* xc_
 /* the finest spacing, m the mean of the two masses rho V (the paper's case  */
 /* has equal spheres).  Fc (device [np][3], out) = sum over j of F_c,ij; the */
 /* force is central, so the collision torque is zero.  rho_p: device [np];  */
-/* the paper uses eps_c = 1e-4.  Every sum runs in a fixed order.          */
+/* the paper uses eps_c = 1e-4.  Partners are found through bins of whole  */
+/* tiles at least max D_c (plus one cell) wide, so a particle meets only    */
+/* the particles of its own and the neighbouring bins; each particle's sum  */
+/* runs over those bins and, within a bin, ascending partner index: a fixed */
+/* order.  ws: device workspace of ib_collision_workspace(lv, np) bytes     */
+/* (IB_EWORKSPACE when short).  The call only enqueues work on stream.      */
+size_t ib_collision_workspace(const ib_level* lv, int32_t np);
 int ib_collision_forces(const ib_level* lv, const ib_particles* p, const double* rho_p,
-                        double g_norm, double eps_c, double* Fc, void* stream);
+                        double g_norm, double eps_c, double* Fc, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Particle-by-particle order of the coupling loop (Sec. 3.1, the remarks   */

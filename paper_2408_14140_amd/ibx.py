@@ -97,7 +97,8 @@ _backward = _sig("ib_multidirect_backward", C.c_int,
 _rigid = _sig("ib_rigid_update", C.c_int,
               [_PP, _p, _p, _p, _p, _p, _p, _d, _p, _d, _p, _p, _p, _p])
 _advect = _sig("ib_advect_markers", C.c_int, [_PM, _p, _p, _p, _p, _d, _p, _p, _p, _p])
-_collide = _sig("ib_collision_forces", C.c_int, [_PL, _PP, _p, _d, _d, _p, _p])
+_coll_ws = _sig("ib_collision_workspace", _sz, [_PL, _i32])
+_collide = _sig("ib_collision_forces", C.c_int, [_PL, _PP, _p, _d, _d, _p, _p, _sz, _p])
 _lv_ws = _sig("ib_levels_workspace", _sz, [_i32])
 _levels = _sig("ib_particle_levels", C.c_int, [_PL, _PP, C.c_int, _p, _p, _p, _sz, _p])
 _seq_ws = _sig("ib_sequential_workspace_bytes", _sz, [_p, _PL, _i32, _i64, _i32])
@@ -120,7 +121,8 @@ EXPORTED = ("ib_count_markers", "ib_build_markers", "ib_desired_velocity", "ib_b
             "ib_multidirect_force", "ib_plan_autotune",
             "ib_reductions_workspace", "ib_particle_reductions", "ib_particle_reductions_noalloc",
             "ib_backward_workspace_bytes", "ib_multidirect_backward",
-            "ib_rigid_update", "ib_advect_markers", "ib_collision_forces",
+            "ib_rigid_update", "ib_advect_markers", "ib_collision_workspace",
+            "ib_collision_forces",
             "ib_levels_workspace", "ib_particle_levels", "ib_sequential_workspace_bytes",
             "ib_multidirect_sequential", "ib_fluid_workspace", "ib_fluid_predict",
             "ib_fluid_project", "ib_field_to_boxes", "ib_field_from_boxes", "ib_status_string", "ib_last_hip_error", "ib_version")
@@ -598,8 +600,10 @@ def collision_forces(level: DeviceLevel, parts: Particles, rho_p: torch.Tensor, 
     """Repulsive collision force of Eq. (DKT_model) on every particle, [np][3]."""
     Fc = torch.empty_like(parts.xc)
     lc, pc = level.c, parts.c
+    ws = torch.empty(max(int(_coll_ws(C.byref(lc), parts.np)), 1), dtype=torch.uint8,
+                     device=parts.xc.device)
     _check(_collide(C.byref(lc), C.byref(pc), _ptr(rho_p), float(g_norm), float(eps_c), _ptr(Fc),
-                    _stream()), "ib_collision_forces")
+                    _ptr(ws), int(ws.numel()), _stream()), "ib_collision_forces")
     return Fc
 
 

@@ -135,3 +135,37 @@ def test_collision_forces_match_oracle(dev, cfg):
     assert rel(g, ref) <= 1e-13
     assert np.abs(g.sum(axis=0)).max() <= 1e-12 * np.abs(g).sum()
 
+
+
+@pytest.mark.parametrize("npart", [400, 9000], ids=["np400", "np9000"])
+@pytest.mark.parametrize("n,periodic,dmax", [
+    ((16, 24, 40), (1, 0, 1), 6.0),
+    ((16, 48, 32), (0, 1, 1), 10.0),
+    ((8, 8, 8), (1, 1, 0), 3.0),
+], ids=["bins2x3x5", "bins1x3x2", "onebin"])
+def test_collision_forces_few_bins(dev, n, periodic, dmax, npart):
+    """Small domains where an axis has one, two or three bins, bounded and
+    periodic, with centroids beyond both ends of every axis (clamped or
+    wrapped): every force against the oracle's all-pairs sum.  400 particles
+    are put in bin order by counting, 9000 by the device-wide radix sort."""
+    import torch
+
+    import oracle as O
+    import paper_2408_14140_amd as ibx
+    announce(f"collision forces few bins n={n} periodic={periodic}")
+    h = 1.0 / 32
+    lev = W.make_level(n, h, periodic=periodic, box=8)
+    rng = np.random.default_rng(sum(n) + npart)
+    ext = np.array(n) * h
+    xc = rng.uniform(0, 1, (npart, 3)) * (ext + 4 * h) - 2 * h
+    d = rng.uniform(1.0, dmax, npart) * h
+    rho = rng.uniform(1000.0, 3000.0, npart)
+    L = [n[a] * h if periodic[a] else 0.0 for a in range(3)]
+    ref = O.collision_forces(xc, d, rho, 9.81, h, 1e-4, L)
+    dl = ibx.device_level(lev, dev)
+    parts = ibx.particles(xc, d, np.zeros((npart, 3)), np.zeros((npart, 3)), dev)
+    got = ibx.collision_forces(dl, parts, torch.as_tensor(rho, device=dev), 9.81, 1e-4)
+    torch.cuda.synchronize()
+    g = got.cpu().numpy()
+    assert (np.abs(ref).sum(axis=1) > 0).mean() > 0.5
+    assert rel(g, ref) <= 1e-13
