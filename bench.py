@@ -38,6 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # figure is reported only while these are unchanged since the counters were taken.
 TRAFFIC_SOURCES = ("paper_2408_14140_amd/csrc/tiles.h", "paper_2408_14140_amd/csrc/batched.hip")
 TRAFFIC_FILE = "profiles/spread_spheres1000_256_hbm_counters.txt"
+TRAFFIC_FILE_CFG4 = "profiles/loop_spheres20000_512_hbm_counters.txt"
 
 
 def log(msg):
@@ -102,11 +103,11 @@ def sources_sha():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
+def committed_traffic(kernel, fname=TRAFFIC_FILE):
+    """HBM bytes per launch of `kernel` from a committed counter summary
     (FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration), or None if
     the summary is absent or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
+    path = os.path.join(ROOT, fname)
     if not os.path.exists(path):
         return None
     sha, val = None, None
@@ -149,6 +150,33 @@ def host_cpu():
     return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
 
 
+def timed(fn, k):
+    """Mean over k back-to-back runs between one pair of events (current stream)."""
+    import torch
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(k):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / k
+
+
+def timed_median(fn, k):
+    """Median over k single runs, each between its own pair of events."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(k)]
+    torch.cuda.synchronize()
+    for s0, e0 in ev:
+        s0.record()
+        fn()
+        e0.record()
+    torch.cuda.synchronize()
+    return float(np.median([s0.elapsed_time(e0) for s0, e0 in ev]))
+
+
 def big_workload_leg(args, dev, timed, timed_median):
     """The FP32 batched loop on spheres20000_512 (seed 0): autotuned, in place,
     median of single runs, per-kernel averages and the byte-model fractions."""
@@ -171,8 +199,13 @@ def big_workload_leg(args, dev, timed, timed_median):
     u = torch.as_tensor(W.to_boxes(wl.u0, lev, fill=0.0, dtype=np.float32), device=dev)
     f = torch.zeros_like(u)
     F = torch.zeros((N, 3), dtype=torch.float32, device=dev)
-    plan = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, use_graph=True)
-    tuned = plan.autotune(dl, parts, m, b, ns, dt, u)
+    plan = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, bucket_width=args.bucket_width,
+                    spread_wgs_per_cu=args.spread_wgs, use_graph=True)
+    if not args.no_autotune and not args.bucket_width and not args.spread_wgs:
+        tuned = plan.autotune(dl, parts, m, b, ns, dt, u)
+    else:
+        tuned = {"bucket_width": args.bucket_width, "spread_wgs_per_cu": args.spread_wgs,
+                 "fixed": True}
 
     def loop():
         plan.multidirect_force(dl, parts, m, b, ns, dt, u, ustar=u, f=f, F=F)
@@ -194,7 +227,9 @@ def big_workload_leg(args, dev, timed, timed_median):
            "loop_model_bytes": bl, "loop_frac": bl / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "dominant_kernel": dom, "kernels": kern,
            "dominant_frac": (ITERATIONS_PER_LAUNCH.get(dom, 0) * bit /
-                             (kern[dom]["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS)}
+                             (kern[dom]["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS),
+           "dominant_traffic": committed_traffic(dom, TRAFFIC_FILE_CFG4),
+           "dominant_model_bytes": ITERATIONS_PER_LAUNCH.get(dom, 0) * bit}
     log(f"spheres20000_512: {N} markers, C {C}, loop {ms:.3f} ms, frac {res['loop_frac']:.3f}")
     # the collision force of Eq. (DKT_model) on the clumped spheres (bin search)
     rho_p = torch.full((wl.npart,), 2.0, dtype=torch.float64, device=dev)
@@ -243,6 +278,8 @@ def run():
                     help="skip the particle-by-particle (level by level) loop")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the plan's default bucket width and spreading residency")
+    ap.add_argument("--only-cfg4", action="store_true",
+                    help="only the 20000-sphere 512^3 loop (its line holds that leg alone)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only time a plain MiB-sized device copy (counter calibration)")
     args = ap.parse_args()
@@ -258,6 +295,10 @@ def run():
     import workloads as W
 
     dev = torch.device("cuda", 0)
+    if args.only_cfg4:
+        print(json.dumps({"spheres20000_512": big_workload_leg(args, dev, timed, timed_median)}),
+              flush=True)
+        return
     t0 = time.time()
     wl = W.config(3, args.seed)
     log(f"workload {wl.name}: {wl.npart} spheres, {wl.level.nbox} boxes, gen {time.time()-t0:.1f}s")
@@ -296,28 +337,6 @@ def run():
 
     def loop_only():
         plan.multidirect_force(dl, parts, m, b, ns, dt, u32, ustar=u32, f=f32, F=F32)
-
-    def timed(fn, k):
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        s.record()
-        for _ in range(k):
-            fn()
-        e.record()
-        torch.cuda.synchronize()
-        return s.elapsed_time(e) / k
-
-    def timed_median(fn, k):
-        """Median over k single runs, each between its own pair of events."""
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(k)]
-        torch.cuda.synchronize()
-        for s0, e0 in ev:
-            s0.record()
-            fn()
-            e0.record()
-        torch.cuda.synchronize()
-        return float(np.median([s0.elapsed_time(e0) for s0, e0 in ev]))
 
     def captured(fn):
         """fn recorded once into a graph (every call in it only enqueues work);
