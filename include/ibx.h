@@ -426,7 +426,10 @@ int ib_fluid_predict(int32_t n, double h, ib_prec prec, double rho, double mu, d
 /* p_new = D V (Fourier modes where the symbol of D G vanishes -- the      */
 /* constant and those with two or more Nyquist components -- get p_new = 0); */
 /* u_new = dt (V - G p_new / rho), so D u_new = 0.  u_new may alias ustar,  */
-/* p_new may alias p_old.                                                   */
+/* p_new may alias p_old.  In FP32 the solve's own rounding would reach p  */
+/* amplified by up to the condition number of D G (about n^2/pi^2), so the  */
+/* residual D (V - G p1/rho) of the first solve p1 is summed in FP64 and a  */
+/* second FP32 solve of it corrects p (one step of iterative refinement).   */
 int ib_fluid_project(int32_t n, double h, ib_prec prec, double rho, double dt,
                      const void* ustar, const void* p_old, void* u_new, void* p_new, void* ws,
                      size_t ws_bytes, void* stream);

@@ -229,6 +229,28 @@ __device__ inline T grad_node(const T* __restrict__ p, const Idx& I, int i, int 
     return (T(0.25) * hi - T(0.25) * lo) * inv_h;
 }
 
+// the same, read from values of type T and formed in A
+template <typename A, typename T>
+__device__ inline A grad_node_as(const T* __restrict__ p, const Idx& I, int i, int j, int k, int d,
+                                 A inv_h)
+{
+    int o[3] = {0, 0, 0};
+    A lo = 0, hi = 0;
+    const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            o[e1] = a;
+            o[e2] = b;
+            o[d] = 0;
+            lo += (A)p[I.at(i + o[0], j + o[1], k + o[2])];
+            o[d] = 1;
+            hi += (A)p[I.at(i + o[0], j + o[1], k + o[2])];
+        }
+    return (A(0.25) * hi - A(0.25) * lo) * inv_h;
+}
+
 // rhs of Eq. (31) for every cell, paired into two complex planes
 template <typename T>
 __global__ void k_predict_rhs(int n, T h, T rho, T a, T dt, T g0, T g1, T g2,
@@ -418,6 +440,88 @@ __global__ void k_proj_scale(int n, double h, double rho, Cx<T>* __restrict__ r)
     r[q] = v;
 }
 
+// The FP32 projection with one step of iterative refinement.  The FFT solve
+// rounds its spectrum to FP32, and the low modes of that rounding are
+// amplified by up to the condition number of D G (about n^2/pi^2).  A second
+// solve of the first one's residual removes that error; the residual and the
+// divergences are summed in A = FP64 from the FP32 cell values (whose own
+// rounding perturbs p only as much as rounding the inputs does).
+//   V = u*/dt + G p_old/rho;  p1 = rho (D G)^+ D V
+//   W = V - G p1/rho;  d = rho (D G)^+ D W  (D W is the residual of p1)
+//   p = p1 + d;  u^{n+1} = dt (W - G d/rho)
+
+// D V at every node summed in A from V of type T, rounded to complex T
+template <typename T, typename A>
+__global__ void k_proj_div_as(int n, A h, const T* __restrict__ V, Cx<T>* __restrict__ r)
+{
+    const int64_t N = (int64_t)n * n * n;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N)
+        return;
+    const Idx I{n};
+    const int i = (int)(q & (n - 1)), j = (int)((q / n) & (n - 1)), k = (int)(q / ((int64_t)n * n));
+    const A inv_h = A(1) / h;
+    A div = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T* v = V + d * N;
+        const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+        A sl[2] = {0, 0};
+#pragma unroll
+        for (int l = 0; l < 2; ++l)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    int o[3];
+                    o[d] = l - 1;
+                    o[e1] = -a;
+                    o[e2] = -b;
+                    sl[l] += (A)v[I.at(i + o[0], j + o[1], k + o[2])];
+                }
+        div += (A(0.25) * sl[1] - A(0.25) * sl[0]) * inv_h;
+    }
+    Cx<T> c;
+    c.x = (T)div;
+    c.y = T(0);
+    r[q] = c;
+}
+
+// W = V - G p/rho, in place, formed in A
+template <typename T, typename A>
+__global__ void k_proj_W(int n, A h, A rho, const T* __restrict__ p, T* __restrict__ V)
+{
+    const int64_t N = (int64_t)n * n * n;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N)
+        return;
+    const Idx I{n};
+    const int i = (int)(q & (n - 1)), j = (int)((q / n) & (n - 1)), k = (int)(q / ((int64_t)n * n));
+    const A inv_h = A(1) / h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        V[c * N + q] = (T)((A)V[c * N + q] - grad_node_as<A>(p, I, i, j, k, c, inv_h) / rho);
+}
+
+// u^{n+1} = dt (W - G d/rho) and p = p1 + d
+template <typename T, typename A>
+__global__ void k_proj_final_refined(int n, A h, A rho, A dt, const T* __restrict__ W,
+                                     const T* __restrict__ p1, const T* __restrict__ dl,
+                                     T* __restrict__ un, T* __restrict__ pn)
+{
+    const int64_t N = (int64_t)n * n * n;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N)
+        return;
+    const Idx I{n};
+    const int i = (int)(q & (n - 1)), j = (int)((q / n) & (n - 1)), k = (int)(q / ((int64_t)n * n));
+    const A inv_h = A(1) / h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        un[c * N + q] = (T)(dt * ((A)W[c * N + q] - grad_node_as<A>(dl, I, i, j, k, c, inv_h) / rho));
+    pn[q] = (T)((A)p1[q] + (A)dl[q]);
+}
+
 // u^{n+1} = dt (V - G p / rho), Eq. (ns_lp3)
 template <typename T>
 __global__ void k_proj_final(int n, T h, T rho, T dt, const T* __restrict__ V, const T* __restrict__ pr,
@@ -547,6 +651,27 @@ static int project_t(int32_t n, double h, double rho, double dt, const T* ustar,
     const int64_t N = (int64_t)n * n * n;
     const unsigned gc = (unsigned)((N + 255) / 256);
     k_twiddles<T><<<(unsigned)((n / 2 + 255) / 256), 256, 0, st>>>(n, w.W);
+    if constexpr (sizeof(T) == 4) {
+        // FP32: two solves, the divergences and the residual summed in FP64;
+        // p1 and the correction as reals in the second complex plane
+        T* p1 = reinterpret_cast<T*>(w.r + N);
+        T* dl = p1 + N;
+        k_proj_V<T><<<gc, 256, 0, st>>>(n, (T)h, (T)rho, (T)dt, ustar, p_old, w.V);
+        k_proj_div_as<T, double><<<gc, 256, 0, st>>>(n, h, w.V, w.r);
+        fft3<T>(w.r, n, logn, w.W, false, st);
+        k_proj_scale<T><<<gc, 256, 0, st>>>(n, h, rho, w.r);
+        fft3<T>(w.r, n, logn, w.W, true, st);
+        k_real_part<T><<<gc, 256, 0, st>>>(N, w.r, p1);
+        k_proj_W<T, double><<<gc, 256, 0, st>>>(n, h, rho, p1, w.V);
+        k_proj_div_as<T, double><<<gc, 256, 0, st>>>(n, h, w.V, w.r);
+        fft3<T>(w.r, n, logn, w.W, false, st);
+        k_proj_scale<T><<<gc, 256, 0, st>>>(n, h, rho, w.r);
+        fft3<T>(w.r, n, logn, w.W, true, st);
+        k_real_part<T><<<gc, 256, 0, st>>>(N, w.r, dl);
+        k_proj_final_refined<T, double><<<gc, 256, 0, st>>>(n, h, rho, dt, w.V, p1, dl, u_new,
+                                                             p_new);
+        return launch_status();
+    }
     k_proj_V<T><<<gc, 256, 0, st>>>(n, (T)h, (T)rho, (T)dt, ustar, p_old, w.V);
     k_proj_div<T><<<gc, 256, 0, st>>>(n, (T)h, w.V, w.r);
     fft3<T>(w.r, n, logn, w.W, false, st);

@@ -62,7 +62,12 @@ def test_predict_and_project_match_oracle(dev, n, dtype):
     torch.cuda.synchronize()
     assert rel(s.cpu().numpy(), ref_s) <= tol
     assert rel(u1.cpu().numpy(), ref_u) <= tol
-    kap = _kappa(n)
+    # FP64: the solve amplifies the rounding of D V by up to kappa (p) and
+    # sqrt(kappa) (G p).  FP32 refines p once with a residual summed in FP64,
+    # which takes it near the error that rounding the inputs to FP32 alone
+    # gives (4.6e-7 against 2.7e-7 at 256^3), so it is held to the plain
+    # tolerance.
+    kap = _kappa(n) if dtype == "f64" else 1.0
     gp = FL.grad_nodes(p1.double().cpu().numpy(), h)
     assert rel(gp, FL.grad_nodes(ref_p, h)) <= tol * np.sqrt(kap)
     assert rel(p1.cpu().numpy(), ref_p) <= tol * kap
@@ -164,4 +169,6 @@ def test_whole_time_step(dev, dtype):
     torch.cuda.synchronize()
     assert rel(F.cpu().numpy(), ib["F"]) <= tol
     assert rel(u1.cpu().numpy(), ref_u) <= tol
+    # here the projection's input carries the loop's own error (up to tol),
+    # which the solve amplifies like any error of D V
     assert rel(p1.cpu().numpy(), ref_p) <= tol * _kappa(n)
