@@ -200,12 +200,13 @@ def big_workload_leg(args, dev, timed, timed_median):
     f = torch.zeros_like(u)
     F = torch.zeros((N, 3), dtype=torch.float32, device=dev)
     plan = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, bucket_width=args.bucket_width,
-                    spread_wgs_per_cu=args.spread_wgs, use_graph=True)
+                    spread_wgs_per_cu=args.spread_wgs, use_graph=True,
+                    row_masks=bool(args.row_masks))
     if not args.no_autotune and not args.bucket_width and not args.spread_wgs:
         tuned = plan.autotune(dl, parts, m, b, ns, dt, u)
     else:
         tuned = {"bucket_width": args.bucket_width, "spread_wgs_per_cu": args.spread_wgs,
-                 "fixed": True}
+                 "row_masks": int(bool(args.row_masks)), "fixed": True}
 
     def loop():
         plan.multidirect_force(dl, parts, m, b, ns, dt, u, ustar=u, f=f, F=F)
@@ -270,6 +271,8 @@ def run():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--bucket-width", type=int, default=0)
     ap.add_argument("--spread-wgs", type=int, default=0)
+    ap.add_argument("--row-masks", type=int, default=0,
+                    help="G slot row masks on (1) or off (0) when the tuning is fixed")
     ap.add_argument("--no-fluid", action="store_true",
                     help="skip the fluid steps and the whole time step")
     ap.add_argument("--no-cfg4", action="store_true",
@@ -322,7 +325,8 @@ def run():
     f32 = torch.zeros_like(u32)
     F32 = torch.zeros((N, 3), dtype=torch.float32, device=dev)
     plan = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, bucket_width=args.bucket_width,
-                    spread_wgs_per_cu=args.spread_wgs, use_graph=True)
+                    spread_wgs_per_cu=args.spread_wgs, use_graph=True,
+                    row_masks=bool(args.row_masks))
     red = torch.zeros((wl.npart, 12), dtype=torch.float64, device=dev)
     tuned = None
     if not args.no_autotune and not args.bucket_width and not args.spread_wgs:
@@ -489,7 +493,8 @@ def run():
         red2 = torch.zeros((w2.npart, 12), dtype=torch.float64, device=dev)
         q = plan.query()
         pl2 = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, bucket_width=q["bucket_width"],
-                       spread_wgs_per_cu=q["spread_wgs_per_cu"], use_graph=True)
+                       spread_wgs_per_cu=q["spread_wgs_per_cu"], use_graph=True,
+                       row_masks=bool(q["row_masks"]))
 
         def step2():
             ibx.build_markers_into(dl2, p2, m2)
@@ -598,7 +603,7 @@ def run():
         # the particle-by-particle order: conflict levels, then one loop per level
         q = plan.query()
         pseq = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, bucket_width=q["bucket_width"],
-                        spread_wgs_per_cu=q["spread_wgs_per_cu"])
+                        spread_wgs_per_cu=q["spread_wgs_per_cu"], row_masks=bool(q["row_masks"]))
         useq = torch.empty_like(u32)
         fseq = torch.empty_like(u32)
         Fseq = torch.empty_like(F32)

@@ -193,15 +193,23 @@ int ib_spread(const ib_level* lv, const ib_markers* m, const ib_buckets* b, ib_d
 /* use_graph: replay the launch sequence from a captured hipGraph when the  */
 /* arguments repeat (batched path, non-null stream).  On a stream that is   */
 /* already being captured the launches go into the caller's graph instead.  */
+/* row_masks (batched path): the spreading records which rows of each tile's */
+/* G slot are not all zeros and stores only those, and the interpolation    */
+/* and the finalize step load only those; it pays when the slots do not fit */
+/* in the caches (on the 20000-sphere 512^3 workload, not on 1000 spheres   */
+/* at 256^3).  Results are the same either way (a row of zeros reads back  */
+/* as +0).                                                                  */
 /* ib_plan_autotune, ib_plan_profile_read, ib_particle_levels and           */
 /* ib_multidirect_sequential synchronize and must not be captured; every    */
 /* other call only enqueues work on its stream and may be.                  */
 /* ---------------------------------------------------------------------- */
 int ib_plan_create(ib_plan** plan, ib_delta delta, ib_prec prec, ib_path path,
-                   int32_t bucket_width, int32_t spread_wgs_per_cu, int32_t use_graph);
+                   int32_t bucket_width, int32_t spread_wgs_per_cu, int32_t use_graph,
+                   int32_t row_masks);
 void ib_plan_destroy(ib_plan* plan);
-/* Current tuning of a plan: out[0] = path, out[1] = bucket_width,
- * out[2] = spread_wgs_per_cu, out[3] = use_graph. */
+/* Current tuning of a plan (out: int32[5]): out[0] = path, out[1] =
+ * bucket_width, out[2] = spread_wgs_per_cu, out[3] = use_graph, out[4] =
+ * row_masks. */
 int ib_plan_query(const ib_plan* plan, int32_t* out);
 /* Workspace of ib_multidirect_force and ib_plan_autotune (device bytes); it
  * does not depend on the plan's tuning. */
@@ -234,10 +242,11 @@ int ib_multidirect_force(ib_plan* plan, const ib_level* lv, const ib_particles* 
                          void* Fhist, void* ws, size_t ws_bytes, void* stream);
 
 /* Autotuning of a batched plan (the batching extension of the coupling loop:
- * the work-item width and the spreading residency are chosen on the real
- * inputs).  Times the loop of ib_multidirect_force for every bucket_width in
- * {64, 128, 256} and spread_wgs_per_cu in {4, 8, 16, 32} (3 runs each after
- * one warm-up) and keeps the fastest in the plan (see ib_plan_query).  The
+ * the work-item width, the spreading residency and the slot row masks are
+ * chosen on the real inputs).  Times the loop of ib_multidirect_force for
+ * every bucket_width in {64, 128, 256}, spread_wgs_per_cu in {4, 8, 16, 32}
+ * and row_masks in {0, 1} (one warm-up, then the faster of two samples of
+ * 3 runs) and keeps the fastest in the plan (see ib_plan_query).  The
  * tile stays 8^3: one 64-wide wavefront holds the 64 rows of a tile.
  * Arguments as ib_multidirect_force, except that ustar must not alias u0 and
  * no residual or history is taken; ustar, f and F hold the result of the

@@ -31,6 +31,7 @@ struct ib_plan {
     int32_t bucket_width;
     int32_t spread_wgs_per_cu;
     int32_t use_graph;
+    int32_t row_masks;
     int32_t ncu;
     // launch sequence captured for one argument set
     hipGraph_t graph;
@@ -114,6 +115,7 @@ static BatchedCfg cfg_of(const ib_plan* pl)
     c.bw = pl->bucket_width;
     c.ncu = pl->ncu;
     c.wgs_s = pl->spread_wgs_per_cu;
+    c.masks = pl->row_masks;
     c.prof = pl->prof;
     return c;
 }
@@ -133,7 +135,7 @@ using namespace ibx;
 
 extern "C" int ib_plan_create(ib_plan** plan, ib_delta delta, ib_prec prec, ib_path path,
                               int32_t bucket_width, int32_t spread_wgs_per_cu,
-                              int32_t use_graph)
+                              int32_t use_graph, int32_t row_masks)
 {
     if (!plan || (delta != IB_DELTA3 && delta != IB_DELTA4) ||
         (prec != IB_F32 && prec != IB_F64) ||
@@ -157,6 +159,7 @@ extern "C" int ib_plan_create(ib_plan** plan, ib_delta delta, ib_prec prec, ib_p
     pl->bucket_width = bucket_width;
     pl->spread_wgs_per_cu = spread_wgs_per_cu;
     pl->use_graph = use_graph ? 1 : 0;
+    pl->row_masks = row_masks ? 1 : 0;
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
@@ -228,6 +231,7 @@ extern "C" int ib_plan_query(const ib_plan* plan, int32_t* out)
     out[1] = plan->bucket_width;
     out[2] = plan->spread_wgs_per_cu;
     out[3] = plan->use_graph;
+    out[4] = plan->row_masks;
     return IB_OK;
 }
 
@@ -432,8 +436,9 @@ extern "C" int ib_multidirect_sequential(ib_plan* plan, const ib_level* lv,
                                   (hipStream_t)stream);
 }
 
-// Autotuning: time the batched loop for every bucket width and spreading
-// residency on the caller's inputs and keep the fastest.
+// Autotuning: time the batched loop for every bucket width, spreading
+// residency and use of the slot row masks on the caller's inputs and keep the
+// fastest.
 extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_particles* p,
                                 const ib_markers* m, const ib_buckets* b, int32_t ns, double dt,
                                 const void* u0, void* ustar, void* f, void* F, void* ws,
@@ -457,33 +462,44 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess)
         e = hipEventCreate(&e1);
-    const int32_t keep_bw = plan->bucket_width, keep_wgs = plan->spread_wgs_per_cu;
+    const int32_t keep_bw = plan->bucket_width, keep_wgs = plan->spread_wgs_per_cu,
+                  keep_masks = plan->row_masks;
     float best = -1.f;
-    int32_t best_bw = keep_bw, best_wgs = keep_wgs;
+    int32_t best_bw = keep_bw, best_wgs = keep_wgs, best_masks = keep_masks;
     Profiler* prof = plan->prof;
     plan->prof = nullptr;
-    for (int i = 0; i < 3 && e == hipSuccess && rc == IB_OK; ++i)
+    for (int q = 0; q < 6 && e == hipSuccess && rc == IB_OK; ++q)
         for (int j = 0; j < 4 && e == hipSuccess && rc == IB_OK; ++j) {
+            const int i = q % 3, mk = q / 3;
             plan->bucket_width = widths[i];
             plan->spread_wgs_per_cu = wgs[j];
+            plan->row_masks = mk;
             const BatchedCfg cfg = cfg_of(plan);
             rc = batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0, ustar, f,
                                      F, nullptr, nullptr, ws, ws_bytes, st);
-            e = hipEventRecord(e0, st);
-            for (int r = 0; r < REPS && rc == IB_OK; ++r)
-                rc = batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0, ustar,
-                                         f, F, nullptr, nullptr, ws, ws_bytes, st);
-            if (e == hipSuccess)
-                e = hipEventRecord(e1, st);
-            if (e == hipSuccess)
-                e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess)
-                e = hipEventElapsedTime(&ms, e0, e1);
+            // the faster of two samples of REPS runs each (one-off stalls
+            // would otherwise decide between configurations a few % apart)
+            float ms = -1.f;
+            for (int k = 0; k < 2 && e == hipSuccess && rc == IB_OK; ++k) {
+                e = hipEventRecord(e0, st);
+                for (int r = 0; r < REPS && rc == IB_OK; ++r)
+                    rc = batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0,
+                                             ustar, f, F, nullptr, nullptr, ws, ws_bytes, st);
+                if (e == hipSuccess)
+                    e = hipEventRecord(e1, st);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(e1);
+                float sample_ms = 0.f;
+                if (e == hipSuccess)
+                    e = hipEventElapsedTime(&sample_ms, e0, e1);
+                if (ms < 0.f || sample_ms < ms)
+                    ms = sample_ms;
+            }
             if (e == hipSuccess && rc == IB_OK && (best < 0.f || ms < best)) {
                 best = ms;
                 best_bw = widths[i];
                 best_wgs = wgs[j];
+                best_masks = mk;
             }
         }
     plan->prof = prof;
@@ -495,12 +511,14 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
     if (e != hipSuccess || rc != IB_OK) {
         plan->bucket_width = keep_bw;
         plan->spread_wgs_per_cu = keep_wgs;
+        plan->row_masks = keep_masks;
         if (e != hipSuccess)
             set_hip_error(e);
         return rc != IB_OK ? rc : IB_EHIP;
     }
     plan->bucket_width = best_bw;
     plan->spread_wgs_per_cu = best_wgs;
+    plan->row_masks = best_masks;
     if (out_ms)
         *out_ms = best / REPS;
     return IB_OK;

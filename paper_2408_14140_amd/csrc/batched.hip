@@ -481,18 +481,22 @@ int resident_grid(int ncu, int cap)
 
 // Last step of Algorithm 1 on every valid cell of the covered boxes:
 // f = G^ns and ustar = u0 + dt G^ns, with G = 0 on tiles no marker reaches
-// (and everywhere when use_g is 0).  One workgroup per (box, row of tiles in
-// y, z plane): box-wide x rows, so the box layout is written in long runs.
+// (and everywhere when use_g is 0) and on the slot rows whose bit in the
+// tile's row mask (tilemask, indexed by tile) is clear.  One workgroup per
+// (box, row of tiles in y, z plane): box-wide x rows, so the box layout is
+// written in long runs.
 // In place (ustar == u0) only the cells whose force is not exactly zero are
 // read and rewritten (u0 + dt 0 = u0): inside the tiles that have a force
 // slot, most cells lie outside every stencil.  With f_acc, f += G^ns instead,
 // on the same cells.  ustar may be null (f only).
-template <typename T, bool F_ACC>
+template <typename T, bool F_ACC, bool MASK>
 __global__ void __launch_bounds__(256)
-k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, const T* u0,
-           T* ustar, T* __restrict__ f, double dt, int use_g)
+k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G,
+           const uint64_t* __restrict__ tilemask, const T* u0, T* ustar, T* __restrict__ f,
+           double dt, int use_g)
 {
     __shared__ int tslot[64];                 // G slot of each tile along the row
+    __shared__ uint64_t tmask[64];            // and its row mask
     const int B = g.box;
     const int nty = B / TILE, ntx = B / TILE;
     const int64_t items = (int64_t)g.nbox * nty * B;
@@ -503,13 +507,18 @@ k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, co
         const int ty = rem / B, lz = rem - ty * B;
         const int bx0 = g.box_lo[3 * bid], by0 = g.box_lo[3 * bid + 1], bz0 = g.box_lo[3 * bid + 2];
         const int cz = bz0 + lz, cyt = (by0 >> 3) + ty;
-        for (int k = threadIdx.x; k < ntx; k += blockDim.x)
-            tslot[k] = use_g ? slot[(bx0 >> 3) + k + g.nt[0] * (cyt + g.nt[1] * (cz >> 3))] : -1;
+        for (int k = threadIdx.x; k < ntx; k += blockDim.x) {
+            const int64_t tk = (bx0 >> 3) + k + g.nt[0] * (cyt + g.nt[1] * (cz >> 3));
+            tslot[k] = use_g ? slot[tk] : -1;
+            if (MASK)
+                tmask[k] = use_g ? tilemask[tk] : 0ull;
+        }
         __syncthreads();
         for (int q = threadIdx.x; q < TILE * B; q += blockDim.x) {
             const int yy = q / B, lx = q - yy * B;
             const int ly = ty * TILE + yy;
-            const int s = tslot[lx >> 3];
+            const int s =
+                !MASK || (tmask[lx >> 3] >> (yy + TILE * (cz & 7))) & 1 ? tslot[lx >> 3] : -1;
             const int64_t off = (int64_t)bid * g.bstride +
                                 ((int64_t)(lz + g.ngrow) * g.ext + (ly + g.ngrow)) * g.ext +
                                 (lx + g.ngrow);
@@ -549,13 +558,15 @@ struct Pair<double> {
 // The same for an even ghost width, two neighbouring x cells per thread (every
 // pair starts on an even element of the box layout and of the tile slots):
 // one workgroup per (box, row of tiles in y, pair of z planes).
-template <typename T, bool F_ACC>
+template <typename T, bool F_ACC, bool MASK>
 __global__ void __launch_bounds__(256)
-k_finalize_pairs(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G, const T* u0,
-                 T* ustar, T* __restrict__ f, double dt, int use_g)
+k_finalize_pairs(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G,
+                 const uint64_t* __restrict__ tilemask, const T* u0, T* ustar, T* __restrict__ f,
+                 double dt, int use_g)
 {
     using V2 = typename Pair<T>::type;
     __shared__ int tslot[64];                 // G slot of each tile along the row
+    __shared__ uint64_t tmask[64];            // and its row mask
     const int B = g.box;
     const int nty = B / TILE, ntx = B / TILE, npx = B / 2;
     const int per_box = nty * (B / 2);
@@ -567,14 +578,20 @@ k_finalize_pairs(Grid g, const int32_t* __restrict__ slot, const T* __restrict__
         const int ty = rem / (B / 2), lz0 = 2 * (rem - ty * (B / 2));
         const int bx0 = g.box_lo[3 * bid], by0 = g.box_lo[3 * bid + 1], bz0 = g.box_lo[3 * bid + 2];
         const int cz0 = bz0 + lz0, cyt = (by0 >> 3) + ty;
-        for (int k = threadIdx.x; k < ntx; k += blockDim.x)
-            tslot[k] = use_g ? slot[(bx0 >> 3) + k + g.nt[0] * (cyt + g.nt[1] * (cz0 >> 3))] : -1;
+        for (int k = threadIdx.x; k < ntx; k += blockDim.x) {
+            const int64_t tk = (bx0 >> 3) + k + g.nt[0] * (cyt + g.nt[1] * (cz0 >> 3));
+            tslot[k] = use_g ? slot[tk] : -1;
+            if (MASK)
+                tmask[k] = use_g ? tilemask[tk] : 0ull;
+        }
         __syncthreads();
         for (int q = threadIdx.x; q < 2 * TILE * npx; q += blockDim.x) {
             const int px = q % npx, r = q / npx;
             const int yy = r & (TILE - 1), pz = r >> 3;
             const int lx = 2 * px, ly = ty * TILE + yy, lz = lz0 + pz;
-            const int s = tslot[lx >> 3];
+            const int s = !MASK || (tmask[lx >> 3] >> (yy + TILE * ((cz0 + pz) & 7))) & 1
+                              ? tslot[lx >> 3]
+                              : -1;
             const int64_t off = (int64_t)bid * g.bstride +
                                 ((int64_t)(lz + g.ngrow) * g.ext + (ly + g.ngrow)) * g.ext +
                                 (lx + g.ngrow);
@@ -608,28 +625,43 @@ k_finalize_pairs(Grid g, const int32_t* __restrict__ slot, const T* __restrict__
     }
 }
 
+template <typename T, bool F_ACC, bool MASK>
+static void finalize_kernel(bool pairs, unsigned grid, unsigned gp, hipStream_t st, const Grid& g,
+                            const int32_t* slot, const T* G, const uint64_t* tilemask,
+                            const T* u0, T* ustar, T* f, double dt, int use_g)
+{
+    if (pairs)
+        k_finalize_pairs<T, F_ACC, MASK>
+            <<<gp, 256, 0, st>>>(g, slot, G, tilemask, u0, ustar, f, dt, use_g);
+    else
+        k_finalize<T, F_ACC, MASK>
+            <<<grid, 256, 0, st>>>(g, slot, G, tilemask, u0, ustar, f, dt, use_g);
+}
+
 template <typename T>
 static void launch_finalize(unsigned grid, hipStream_t st, const Grid& g, const int32_t* slot,
-                            const T* G, const T* u0, T* ustar, T* f, double dt, int use_g,
-                            int f_acc)
+                            const T* G, const uint64_t* tilemask, const T* u0, T* ustar, T* f,
+                            double dt, int use_g, int f_acc, int masks)
 {
     // pairs of cells: rows start on even elements when ngrow is even, and the
     // pair loads and stores need the fields aligned to two elements
     const uintptr_t am = 2 * sizeof(T) - 1;
-    if ((g.ngrow & 1) == 0 && !((uintptr_t)u0 & am) && !((uintptr_t)ustar & am) &&
-        !((uintptr_t)f & am)) {
-        const int64_t items = (int64_t)g.nbox * (g.box / TILE) * (g.box / 2);
-        const unsigned gp = (unsigned)(items < 65535 ? (items > 0 ? items : 1) : 65535);
-        if (f_acc)
-            k_finalize_pairs<T, true><<<gp, 256, 0, st>>>(g, slot, G, u0, ustar, f, dt, use_g);
-        else
-            k_finalize_pairs<T, false><<<gp, 256, 0, st>>>(g, slot, G, u0, ustar, f, dt, use_g);
-        return;
-    }
-    if (f_acc)
-        k_finalize<T, true><<<grid, 256, 0, st>>>(g, slot, G, u0, ustar, f, dt, use_g);
+    const bool pairs = (g.ngrow & 1) == 0 && !((uintptr_t)u0 & am) &&
+                       !((uintptr_t)ustar & am) && !((uintptr_t)f & am);
+    const int64_t items = (int64_t)g.nbox * (g.box / TILE) * (g.box / 2);
+    const unsigned gp = (unsigned)(items < 65535 ? (items > 0 ? items : 1) : 65535);
+    if (f_acc && masks)
+        finalize_kernel<T, true, true>(pairs, grid, gp, st, g, slot, G, tilemask, u0, ustar, f,
+                                       dt, use_g);
+    else if (f_acc)
+        finalize_kernel<T, true, false>(pairs, grid, gp, st, g, slot, G, tilemask, u0, ustar, f,
+                                        dt, use_g);
+    else if (masks)
+        finalize_kernel<T, false, true>(pairs, grid, gp, st, g, slot, G, tilemask, u0, ustar, f,
+                                        dt, use_g);
     else
-        k_finalize<T, false><<<grid, 256, 0, st>>>(g, slot, G, u0, ustar, f, dt, use_g);
+        finalize_kernel<T, false, false>(pairs, grid, gp, st, g, slot, G, tilemask, u0, ustar, f,
+                                         dt, use_g);
 }
 
 template <typename T>
@@ -666,6 +698,8 @@ struct BatchedWs {
     int32_t *hist, *cur;
     int4* sent;     // spreading order by decreasing cost: (slot, tile, sources begin, end)
     T* G;
+    uint64_t* rmask;   // per slot: bit r set when row r of the slot is not all zeros
+    uint64_t* tmask;   // the same per tile (stale on tiles without a slot)
     void* scan;
     int64_t max_items;
     int64_t *nb_u, *nb_g;   // [item][27] element offsets of the neighbouring tiles
@@ -699,6 +733,8 @@ static BatchedWs<T> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, s
     w.nactive = cv.take<int32_t>(1);
     const int64_t max_active = T_ < 8 * nl ? T_ : 8 * nl;
     w.G = cv.take<T>((size_t)3 * TILE_CELLS * (max_active > 0 ? max_active : 1));
+    w.rmask = cv.take<uint64_t>(max_active > 0 ? max_active : 1);
+    w.tmask = cv.take<uint64_t>(T_ > 0 ? T_ : 1);
     w.nb_u = cv.take<int64_t>(27 * w.max_items);
     w.nb_g = cv.take<int64_t>(27 * w.max_items);
     w.scan = cv.take<char>(scan2_workspace(T_));
@@ -706,25 +742,58 @@ static BatchedWs<T> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, s
     return w;
 }
 
+template <typename T, int P, int MODE, bool MASK>
+static void launch_interp_bw(const BatchedCfg& cfg, hipStream_t st, const Grid& g, int64_t nl,
+                          double dt, const Item* items, const int32_t* nitems, const T* u0,
+                          const T* G, const uint64_t* rmask, const int64_t* nbase,
+                          const MarkerData<T>& s, double* e2,
+                          T* Fout, const int32_t* perm, const T* vin, double* gX, int use_dv)
+{
+    if (cfg.bw == 64)
+        k_interp_tiles<T, P, MODE, 64, MASK>
+            <<<resident_grid<k_interp_tiles<T, P, MODE, 64, MASK>, 64>(cfg.ncu, 0), 64, 0, st>>>(
+                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm, vin, gX, use_dv, rmask);
+    else if (cfg.bw == 128)
+        k_interp_tiles<T, P, MODE, 128, MASK>
+            <<<resident_grid<k_interp_tiles<T, P, MODE, 128, MASK>, 128>(cfg.ncu, 0), 128, 0, st>>>(
+                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm, vin, gX, use_dv, rmask);
+    else
+        k_interp_tiles<T, P, MODE, 256, MASK>
+            <<<resident_grid<k_interp_tiles<T, P, MODE, 256, MASK>, 256>(cfg.ncu, 0), 256, 0, st>>>(
+                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm, vin, gX, use_dv, rmask);
+}
+
+// Interpolation from the G slots (modes 1, 2) uses the slot row masks when the
+// plan does.
 template <typename T, int P, int MODE>
 static void launch_interp(const BatchedCfg& cfg, hipStream_t st, const Grid& g, int64_t nl,
                           double dt, const Item* items, const int32_t* nitems, const T* u0,
-                          const T* G, const int64_t* nbase, const MarkerData<T>& s, double* e2,
-                          T* Fout = nullptr, const int32_t* perm = nullptr,
-                          const T* vin = nullptr, double* gX = nullptr, int use_dv = 0)
+                          const T* G, const uint64_t* rmask, const int64_t* nbase,
+                          const MarkerData<T>& s, double* e2, T* Fout = nullptr,
+                          const int32_t* perm = nullptr, const T* vin = nullptr,
+                          double* gX = nullptr, int use_dv = 0)
 {
-    if (cfg.bw == 64)
-        k_interp_tiles<T, P, MODE, 64>
-            <<<resident_grid<k_interp_tiles<T, P, MODE, 64>, 64>(cfg.ncu, 0), 64, 0, st>>>(
-                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm, vin, gX, use_dv);
-    else if (cfg.bw == 128)
-        k_interp_tiles<T, P, MODE, 128>
-            <<<resident_grid<k_interp_tiles<T, P, MODE, 128>, 128>(cfg.ncu, 0), 128, 0, st>>>(
-                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm, vin, gX, use_dv);
+    if ((MODE == 1 || MODE == 2) && cfg.masks)
+        launch_interp_bw<T, P, MODE, true>(cfg, st, g, nl, dt, items, nitems, u0, G, rmask, nbase,
+                                           s, e2, Fout, perm, vin, gX, use_dv);
     else
-        k_interp_tiles<T, P, MODE, 256>
-            <<<resident_grid<k_interp_tiles<T, P, MODE, 256>, 256>(cfg.ncu, 0), 256, 0, st>>>(
-                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm, vin, gX, use_dv);
+        launch_interp_bw<T, P, MODE, false>(cfg, st, g, nl, dt, items, nitems, u0, G, rmask,
+                                            nbase, s, e2, Fout, perm, vin, gX, use_dv);
+}
+
+// The tile spreading, with or without the slot row masks.
+template <typename T, int P>
+static void launch_spread(const BatchedCfg& cfg, hipStream_t st, const Grid& g,
+                          const BatchedWs<T>& w, const ib_buckets* b, int use_dv)
+{
+    if (cfg.masks)
+        k_spread_tiles<T, P, true>
+            <<<resident_grid<k_spread_tiles<T, P, true>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
+                w.sent, w.nactive, b->src_idx, g, w.s, w.G, w.rmask, w.tmask, use_dv);
+    else
+        k_spread_tiles<T, P, false>
+            <<<resident_grid<k_spread_tiles<T, P, false>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
+                w.sent, w.nactive, b->src_idx, g, w.s, w.G, w.rmask, w.tmask, use_dv);
 }
 
 #define IBX_PROF_BEGIN(k) \
@@ -810,7 +879,8 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     const int64_t nfin = (int64_t)g.nbox * (g.box / TILE) * g.box;
     const unsigned gfin = (unsigned)(nfin < 65535 ? (nfin > 0 ? nfin : 1) : 65535);
     if (nl == 0) {
-        launch_finalize<T>(gfin, st, g, w.slot, w.G, u0, ustar, f, dt, 0, f_acc);
+        launch_finalize<T>(gfin, st, g, w.slot, w.G, w.tmask, u0, ustar, f, dt, 0, f_acc,
+                          cfg.masks);
         if (resid)
             k_zero<double><<<1, 64, 0, st>>>(ns + 1, resid);
         poison_outputs(g, b, ustar, f, F, resid, Fhist, nl, ns, st);
@@ -820,14 +890,15 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     double* e2 = resid ? w.e2 : nullptr;
     IBX_PROF_BEGIN(PK_INTERP_U0);
     // the last interpolation of the loop also writes F in marker order
-    launch_interp<T, P, 0>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_u, w.s, e2,
-                           ns == 1 ? F : nullptr, b->perm);
+    launch_interp<T, P, 0>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.rmask, w.nb_u, w.s,
+                           e2, ns == 1 ? F : nullptr, b->perm);
     IBX_PROF_END();
     if (resid)
         sum_to(w.e2, nl, w.part, resid + 0, true, st);
     if (ns == 0) {
         // no iteration: ustar = u0, f = 0, F = 0
-        launch_finalize<T>(gfin, st, g, w.slot, w.G, u0, ustar, f, dt, 0, f_acc);
+        launch_finalize<T>(gfin, st, g, w.slot, w.G, w.tmask, u0, ustar, f, dt, 0, f_acc,
+                          cfg.masks);
         k_zero<T><<<gm, 256, 0, st>>>(3 * nl, F);
         poison_outputs(g, b, ustar, f, F, resid, Fhist, nl, ns, st);
         return launch_status();
@@ -836,13 +907,11 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         k_unsort<T><<<gm, 256, 0, st>>>(nl, b->perm, w.s.f4, Fhist);
     for (int mi = 2; mi <= ns; ++mi) {
         IBX_PROF_BEGIN(PK_SPREAD);
-        k_spread_tiles<T, P>
-            <<<resident_grid<k_spread_tiles<T, P>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
-                w.sent, w.nactive, b->src_idx, g, w.s, w.G, 1);
+        launch_spread<T, P>(cfg, st, g, w, b, 1);
         IBX_PROF_END();
         IBX_PROF_BEGIN(PK_INTERP_G);
-        launch_interp<T, P, 1>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_g, w.s, e2,
-                               mi == ns ? F : nullptr, b->perm);
+        launch_interp<T, P, 1>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.rmask, w.nb_g,
+                               w.s, e2, mi == ns ? F : nullptr, b->perm);
         IBX_PROF_END();
         if (resid)
             sum_to(w.e2, nl, w.part, resid + (mi - 1), true, st);
@@ -851,17 +920,15 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
                                             Fhist + (int64_t)(mi - 1) * 3 * nl);
     }
     IBX_PROF_BEGIN(PK_SPREAD_FINAL);
-    k_spread_tiles<T, P>
-        <<<resident_grid<k_spread_tiles<T, P>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
-            w.sent, w.nactive, b->src_idx, g, w.s, w.G, 1);
+    launch_spread<T, P>(cfg, st, g, w, b, 1);
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_FILL);
-    launch_finalize<T>(gfin, st, g, w.slot, w.G, u0, ustar, f, dt, 1, f_acc);
+    launch_finalize<T>(gfin, st, g, w.slot, w.G, w.tmask, u0, ustar, f, dt, 1, f_acc, cfg.masks);
     IBX_PROF_END();
     if (resid) {
         IBX_PROF_BEGIN(PK_RESID);
-        launch_interp<T, P, 2>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.nb_g, w.s,
-                               w.e2);
+        launch_interp<T, P, 2>(cfg, st, g, nl, dt, w.items, w.nitems, u0, w.G, w.rmask, w.nb_g,
+                               w.s, w.e2);
         IBX_PROF_END();
         sum_to(w.e2, nl, w.part, resid + ns, true, st);
     }
@@ -947,15 +1014,15 @@ static void spread_t(const Grid& g, const BatchedCfg& cfg, const ib_markers* m,
     const unsigned gfin = (unsigned)(nfin < 65535 ? (nfin > 0 ? nfin : 1) : 65535);
     if (nl > 0) {
         k_sort_vec<T><<<(unsigned)((nl + 255) / 256), 256, 0, st>>>(nl, b->perm, v, w.s.f4);
-        k_spread_tiles<T, P>
-            <<<resident_grid<k_spread_tiles<T, P>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
-                w.sent, w.nactive, b->src_idx, g, w.s, w.G, use_dv);
+        launch_spread<T, P>(cfg, st, g, w, b, use_dv);
     }
     // u0 given: out = u0 + dt G; else out = G (zero where no marker reaches)
     if (u0)
-        launch_finalize<T>(gfin, st, g, w.slot, w.G, u0, out, nullptr, dt, nl > 0, 0);
+        launch_finalize<T>(gfin, st, g, w.slot, w.G, w.tmask, u0, out, nullptr, dt, nl > 0, 0,
+                          cfg.masks);
     else
-        launch_finalize<T>(gfin, st, g, w.slot, w.G, nullptr, nullptr, out, dt, nl > 0, 0);
+        launch_finalize<T>(gfin, st, g, w.slot, w.G, w.tmask, nullptr, nullptr, out, dt, nl > 0, 0,
+                          cfg.masks);
 }
 
 int tile_spread(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg, const ib_markers* m,
@@ -989,8 +1056,8 @@ static void interp_grad_t(const Grid& g, const BatchedCfg& cfg, const ib_markers
 {
     size_t need = 0;
     BatchedWs<T> w = carve_batched<T>(g, m->nl, cfg.bw, ws, bytes, &need);
-    launch_interp<T, P, 3>(cfg, st, g, m->nl, 0.0, w.items, w.nitems, fld, nullptr, w.nb_u, w.s,
-                           nullptr, U, b->perm, v, gX, use_dv);
+    launch_interp<T, P, 3>(cfg, st, g, m->nl, 0.0, w.items, w.nitems, fld, nullptr, nullptr,
+                           w.nb_u, w.s, nullptr, U, b->perm, v, gX, use_dv);
 }
 
 int tile_interp_grad(const Grid& g, int P, ib_prec prec, const BatchedCfg& cfg,

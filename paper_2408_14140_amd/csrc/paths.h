@@ -28,6 +28,7 @@ struct BatchedCfg {
     int bw;        // markers per interpolation work item (= threads per workgroup)
     int ncu;       // compute units of the device
     int wgs_s;     // cap on resident spreading workgroups per CU (0 = as many as fit)
+    int masks;     // G slot row masks: zero rows neither stored nor loaded
     Profiler* prof;  // nullable: per-kernel event timing
 };
 

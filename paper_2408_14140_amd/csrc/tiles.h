@@ -95,13 +95,14 @@ __global__ void k_item_bases(Grid g, const Item* __restrict__ items,
 //         (field . vin_l) grad_X w_l, sc = dV/h^3 (use_dv) or 1, in marker
 //         order (the weights' derivatives from the same shared root).
 // e2 (nullable) receives dV |U^d - J u^(m)|^2 per marker.
-template <typename T, int P, int MODE, int BW>
+template <typename T, int P, int MODE, int BW, bool MASK = false>
 __global__ void __launch_bounds__(BW)
 k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                const int32_t* __restrict__ nitems, const T* __restrict__ u0,
                const T* __restrict__ G, const int64_t* __restrict__ nbase, MarkerData<T> s,
                double* __restrict__ e2, T* __restrict__ Fout, const int32_t* __restrict__ perm,
-               const T* __restrict__ vin, double* __restrict__ gX, int use_dv)
+               const T* __restrict__ vin, double* __restrict__ gX, int use_dv,
+               const uint64_t* __restrict__ rmask)
 {
     constexpr bool BOX = MODE == 0 || MODE == 3;   // field in the box layout
     constexpr int gh = Halo<P>::g, R = Halo<P>::R;
@@ -112,6 +113,7 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     using T2 = typename Vec2<T>::type;
     __shared__ __align__(16) T fld[3 * PL];
     __shared__ int64_t nb[27];
+    __shared__ uint64_t nbm[27];        // tile slots: rows of each neighbour's slot not all zero
     const int n_items = *nitems;
     const double h3 = g.h * g.h * g.h;
     const int tid = threadIdx.x;
@@ -121,15 +123,38 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     const T* src = BOX ? u0 : G;
     const bool paired = true;   // tile slots: rows start on multiples of 8 elements
     const Slab sl = xcd_slab(n_items);
-    // the neighbour offsets of each item are loaded one item ahead, so the
-    // staging and compute of an item hide the next one's load
+    // The neighbour offsets of each item are loaded one item ahead (two with
+    // the row masks, whose loads follow them one item ahead), so the staging
+    // and compute of an item hide those loads.
+    auto row_mask = [&](int64_t off) -> uint64_t {
+        return off >= 0 ? rmask[off / (3 * TILE_CELLS)] : 0ull;
+    };
     int64_t pnb = sl.begin < sl.end && tid < 27 ? nbase[(int64_t)sl.begin * 27 + tid] : 0;
+    uint64_t pm = 0ull;
+    int64_t qnb = 0;
+    if constexpr (MASK) {
+        if (tid < 27 && sl.begin < sl.end)
+            pm = row_mask(pnb);
+        if (tid < 27 && sl.begin + sl.stride < sl.end)
+            qnb = nbase[(int64_t)(sl.begin + sl.stride) * 27 + tid];
+    }
     for (int it = sl.begin; it < sl.end; it += sl.stride) {
-        if (tid < 27)
+        if (tid < 27) {
             nb[tid] = pnb;
+            if constexpr (MASK)
+                nbm[tid] = pm;
+        }
         __syncthreads();
-        if (tid < 27 && it + sl.stride < sl.end)
+        if constexpr (MASK) {
+            if (tid < 27) {
+                pnb = qnb;
+                pm = it + sl.stride < sl.end ? row_mask(qnb) : 0ull;
+                if (it + 2 * sl.stride < sl.end)
+                    qnb = nbase[(int64_t)(it + 2 * sl.stride) * 27 + tid];
+            }
+        } else if (tid < 27 && it + sl.stride < sl.end) {
             pnb = nbase[(int64_t)(it + sl.stride) * 27 + tid];
+        }
         const Item item = items[it];
         int lo[3];
         tile_coords(g, item.tile, lo);
@@ -214,8 +239,15 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
             const int ys = (jy - gh + TILE) >> 3, zs = (jz - gh + TILE) >> 3;
             const int64_t roff = (int64_t)sy * ((jy - gh) & 7) + (int64_t)sz * ((jz - gh) & 7) +
                                  c * comp;
-            const int64_t bl = nb[3 * (ys + 3 * zs)], bc = nb[1 + 3 * (ys + 3 * zs)],
-                          br = nb[2 + 3 * (ys + 3 * zs)];
+            const int q0 = 3 * (ys + 3 * zs);
+            int64_t bl = nb[q0], bc = nb[q0 + 1], br = nb[q0 + 2];
+            if constexpr (MASK) {
+                // a neighbour row whose mask bit is clear is all zeros in its slot
+                const int rbit = ((jy - gh) & 7) + TILE * ((jz - gh) & 7);
+                bl = (nbm[q0] >> rbit) & 1 ? bl : -1;
+                bc = (nbm[q0 + 1] >> rbit) & 1 ? bc : -1;
+                br = (nbm[q0 + 2] >> rbit) & 1 ? br : -1;
+            }
             T* row = fld + ((c * R + jz) * R + jy) * RP;
             T m[TILE];
             T l[gh], r[gh];
@@ -479,12 +511,13 @@ __device__ inline uint64_t drop_low_bits(uint64_t m, int s)
 // (FP32: registers capped so that 6 waves fit per SIMD, the residency that the
 // latency-bound visit chain wants; at that cap the 4-point kernel spills two
 // registers, which costs less than the prefetch of the source indices saves.)
-template <typename T, int P>
+template <typename T, int P, bool MASK = false>
 __global__ void __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8)))
 k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactive,
                const int32_t* __restrict__ src_idx, Grid g, MarkerData<T> s,
-               T* __restrict__ G, int use_dv)
+               T* __restrict__ G, uint64_t* __restrict__ rmask, uint64_t* __restrict__ tmask,
+               int use_dv)
 {
     constexpr int NW = TILE + 2 * P + 3;                   // staged values per source
     constexpr int NBUF = NW * 64;
@@ -653,21 +686,37 @@ k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactiv
             }
             __syncthreads();
         }
-        // the lane's row is 8 consecutive cells of each component in the slot
-        T* gs = G + (int64_t)a * 3 * TILE_CELLS + TILE * lane;
+        // the lane's row is 8 consecutive cells of each component in the slot;
+        // with MASK, rows of zeros are not stored and their bit in the slot's
+        // row mask (kept by slot and by tile) is clear
+        bool nz = true;
+        if constexpr (MASK) {
+            nz = false;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            typename Vec4<T>::type v0, v1;
-            v0.x = acc[0][c];
-            v0.y = acc[1][c];
-            v0.z = acc[2][c];
-            v0.w = acc[3][c];
-            v1.x = acc[4][c];
-            v1.y = acc[5][c];
-            v1.z = acc[6][c];
-            v1.w = acc[7][c];
-            *reinterpret_cast<typename Vec4<T>::type*>(gs + c * TILE_CELLS) = v0;
-            *reinterpret_cast<typename Vec4<T>::type*>(gs + c * TILE_CELLS + 4) = v1;
+            for (int xx = 0; xx < TILE; ++xx)
+                nz = nz || acc[xx][0] != T(0) || acc[xx][1] != T(0) || acc[xx][2] != T(0);
+            const uint64_t rm = __ballot(nz);
+            if (lane == 0) {
+                rmask[a] = rm;
+                tmask[ent.y] = rm;
+            }
+        }
+        T* gs = G + (int64_t)a * 3 * TILE_CELLS + TILE * lane;
+        if (nz) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                typename Vec4<T>::type v0, v1;
+                v0.x = acc[0][c];
+                v0.y = acc[1][c];
+                v0.z = acc[2][c];
+                v0.w = acc[3][c];
+                v1.x = acc[4][c];
+                v1.y = acc[5][c];
+                v1.z = acc[6][c];
+                v1.w = acc[7][c];
+                *reinterpret_cast<typename Vec4<T>::type*>(gs + c * TILE_CELLS) = v0;
+                *reinterpret_cast<typename Vec4<T>::type*>(gs + c * TILE_CELLS + 4) = v1;
+            }
         }
         idx = nidx;
         ent = nent;

@@ -255,6 +255,40 @@ def test_multidirect_matches_oracle(dev, name, mk, dtype, path):
     assert np.all(np.abs(r.cpu().numpy() - ref["resid"]) <= bound)
 
 
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_row_masks_match_oracle_and_unmasked(dev, name, mk, dtype):
+    """The batched loop with the slot row masks (zero rows of G neither stored
+    nor loaded): against the oracle, and the same values as without them,
+    with residuals, force history and in place."""
+    import torch
+
+    import oracle as O
+    announce(f"row masks {name} {dtype}")
+    wl = mk()
+    c = Case(wl, dev)
+    ref = O.multidirect(c.g, wl.delta, wl.ns, wl.dt, c.m, wl.xc, wl.up, wl.om, wl.u0,
+                        history=True)
+    a = _run(c, dtype, 2, fhist=True)
+    mk_ = _run(c, dtype, 2, fhist=True, row_masks=True)
+    tol = TOL64 if dtype == "f64" else TOL32
+    ustar, f, F, r, Fh, _ = mk_
+    assert rel(F.cpu().numpy(), ref["F"]) <= tol
+    assert c.field_rel(f, ref["f"]) <= tol
+    assert c.field_rel(ustar, ref["ustar"]) <= tol
+    assert rel(Fh.cpu().numpy(), ref["Fhist"]) <= tol
+    bound = resid_bounds(c.g, wl.delta, c.m, wl.xc, wl.up, wl.om, wl.u0, ref["resid"], tol)
+    assert np.all(np.abs(r.cpu().numpy() - ref["resid"]) <= bound)
+    m = np.broadcast_to(c.mask, (3,) + c.mask.shape)
+    for x, y in zip(a[:2], mk_[:2]):
+        assert np.array_equal(c.to_global(x)[m], c.to_global(y)[m])
+    for x, y in zip(a[2:5], mk_[2:5]):
+        assert torch.equal(x, y)
+    ip = _run(c, dtype, 2, inplace=True, resid=False, row_masks=True)
+    assert np.array_equal(c.to_global(ip[0])[m], c.to_global(a[0])[m])
+    assert torch.equal(ip[2], a[2])
+
+
 def test_batched_in_place_and_deterministic(dev):
     import torch
     announce("in-place + determinism")
