@@ -289,6 +289,24 @@ def test_row_masks_match_oracle_and_unmasked(dev, name, mk, dtype):
     assert torch.equal(ip[2], a[2])
 
 
+@pytest.mark.parametrize("ns", [1, 2])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_row_masks_short_loops(dev, ns, dtype):
+    """One and two iterations with the slot row masks: the last spreading
+    writes the masks that the finalize step and the residual read."""
+    import torch
+    announce(f"row masks ns={ns} {dtype}")
+    wl = small_workload(32, 16, 4, 3, 1)
+    c = Case(wl, dev)
+    a = _run(c, dtype, 2, ns=ns)
+    b = _run(c, dtype, 2, ns=ns, row_masks=True)
+    m = np.broadcast_to(c.mask, (3,) + c.mask.shape)
+    for x, y in zip(a[:2], b[:2]):
+        assert np.array_equal(c.to_global(x)[m], c.to_global(y)[m])
+    for x, y in zip(a[2:4], b[2:4]):
+        assert torch.equal(x, y)
+
+
 def test_batched_in_place_and_deterministic(dev):
     import torch
     announce("in-place + determinism")

@@ -42,14 +42,15 @@ def test_levels_bit_exact(dev, which):
     assert n == int(ref.max()) + 1
 
 
+@pytest.mark.parametrize("masks", [False, True], ids=["", "masks"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("P", [4, 3])
-def test_sequential_matches_oracle(dev, dtype, P):
+def test_sequential_matches_oracle(dev, dtype, P, masks):
     import torch
 
     import oracle as O
     import paper_2408_14140_amd as ibx
-    announce(f"sequential chain P={P} {dtype}")
+    announce(f"sequential chain P={P} {dtype} masks={masks}")
     wl = chain_workload(delta=P, seed=0)
     c = Case(wl, dev)
     ref = O.multidirect(c.g, P, wl.ns, wl.dt, c.m, wl.xc, wl.up, wl.om, wl.u0,
@@ -58,7 +59,7 @@ def test_sequential_matches_oracle(dev, dtype, P):
     tdt = torch.float64 if dtype == "f64" else torch.float32
     tol = TOL64 if dtype == "f64" else TOL32
     assert rel(jac["F"], ref["F"]) > 100 * tol      # the order matters here
-    plan = ibx.Plan(P, tdt, ibx.IB_PATH_BATCHED)
+    plan = ibx.Plan(P, tdt, ibx.IB_PATH_BATCHED, row_masks=masks)
     levels = ibx.particle_levels(c.dl, c.parts, P)
     assert levels[1] >= 3
     flag = torch.ones(2, dtype=torch.int32, device=dev)
