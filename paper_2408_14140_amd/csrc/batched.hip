@@ -773,12 +773,15 @@ static void launch_interp(const BatchedCfg& cfg, hipStream_t st, const Grid& g, 
                           const int32_t* perm = nullptr, const T* vin = nullptr,
                           double* gX = nullptr, int use_dv = 0)
 {
-    if ((MODE == 1 || MODE == 2) && cfg.masks)
-        launch_interp_bw<T, P, MODE, true>(cfg, st, g, nl, dt, items, nitems, u0, G, rmask, nbase,
-                                           s, e2, Fout, perm, vin, gX, use_dv);
-    else
-        launch_interp_bw<T, P, MODE, false>(cfg, st, g, nl, dt, items, nitems, u0, G, rmask,
-                                            nbase, s, e2, Fout, perm, vin, gX, use_dv);
+    if constexpr (MODE == 1 || MODE == 2) {
+        if (cfg.masks) {
+            launch_interp_bw<T, P, MODE, true>(cfg, st, g, nl, dt, items, nitems, u0, G, rmask,
+                                               nbase, s, e2, Fout, perm, vin, gX, use_dv);
+            return;
+        }
+    }
+    launch_interp_bw<T, P, MODE, false>(cfg, st, g, nl, dt, items, nitems, u0, G, rmask, nbase,
+                                        s, e2, Fout, perm, vin, gX, use_dv);
 }
 
 // The tile spreading, with or without the slot row masks.
