@@ -95,8 +95,11 @@ __global__ void k_item_bases(Grid g, const Item* __restrict__ items,
 //         (field . vin_l) grad_X w_l, sc = dV/h^3 (use_dv) or 1, in marker
 //         order (the weights' derivatives from the same shared root).
 // e2 (nullable) receives dV |U^d - J u^(m)|^2 per marker.
+// (FP32 with the row masks, 256-marker items: registers capped at the
+// unmasked kernel's seven waves per SIMD.)
 template <typename T, int P, int MODE, int BW, bool MASK = false>
 __global__ void __launch_bounds__(BW)
+__attribute__((amdgpu_waves_per_eu(MASK && sizeof(T) == 4 && BW == 256 ? 7 : 1, 8)))
 k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                const int32_t* __restrict__ nitems, const T* __restrict__ u0,
                const T* __restrict__ G, const int64_t* __restrict__ nbase, MarkerData<T> s,
