@@ -20,7 +20,9 @@ corner of cell (i, j, k).  Readings of what the paper leaves open:
 * The convective term of Eq. (31): the paper's second-order Godunov scheme is
   cited, not given; here it is the second-order central flux form at t^n,
   div(u u) = sum_d [(u_d u)(i+1/2) - (u_d u)(i-1/2)] / h with face values the
-  mean of the two cells.
+  mean of the two cells.  Parity unpinned to the paper for this term: it is
+  pinned to its own definition (second-order convergence to the analytic
+  divergence of u u), not to the scheme the paper cites.
 * Step 1 solve: (I - (nu dt / 2) L) u~* = u^n - dt div(uu) - (dt/rho) G p
   + (nu dt / 2) L u^n + dt g  (Eq. (31) with constant mu = rho nu), exactly by
   FFT.
