@@ -495,7 +495,9 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
                 if (ms < 0.f || sample_ms < ms)
                     ms = sample_ms;
             }
-            if (e == hipSuccess && rc == IB_OK && (best < 0.f || ms < best)) {
+            // the row masks must win by more than 1% (the candidates without
+            // them come first), so near-ties keep the simpler setting
+            if (e == hipSuccess && rc == IB_OK && (best < 0.f || ms < best * (mk ? 0.99f : 1.f))) {
                 best = ms;
                 best_bw = widths[i];
                 best_wgs = wgs[j];
