@@ -201,12 +201,13 @@ def big_workload_leg(args, dev, timed, timed_median):
     F = torch.zeros((N, 3), dtype=torch.float32, device=dev)
     plan = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, bucket_width=args.bucket_width,
                     spread_wgs_per_cu=args.spread_wgs, use_graph=True,
-                    row_masks=bool(args.row_masks))
+                    row_masks=bool(args.row_masks), interp_tile=args.interp_tile)
     if not args.no_autotune and not args.bucket_width and not args.spread_wgs:
         tuned = plan.autotune(dl, parts, m, b, ns, dt, u)
     else:
         tuned = {"bucket_width": args.bucket_width, "spread_wgs_per_cu": args.spread_wgs,
-                 "row_masks": int(bool(args.row_masks)), "fixed": True}
+                 "row_masks": int(bool(args.row_masks)), "interp_tile": args.interp_tile or 8,
+                 "fixed": True}
 
     def loop():
         plan.multidirect_force(dl, parts, m, b, ns, dt, u, ustar=u, f=f, F=F)
@@ -273,6 +274,9 @@ def run():
     ap.add_argument("--spread-wgs", type=int, default=0)
     ap.add_argument("--row-masks", type=int, default=0,
                     help="G slot row masks on (1) or off (0) when the tuning is fixed")
+    ap.add_argument("--interp-tile", type=int, default=0,
+                    help="x extent of the interpolation work tiles (8 or 16) when the tuning "
+                         "is fixed")
     ap.add_argument("--no-fluid", action="store_true",
                     help="skip the fluid steps and the whole time step")
     ap.add_argument("--no-cfg4", action="store_true",
@@ -326,7 +330,7 @@ def run():
     F32 = torch.zeros((N, 3), dtype=torch.float32, device=dev)
     plan = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, bucket_width=args.bucket_width,
                     spread_wgs_per_cu=args.spread_wgs, use_graph=True,
-                    row_masks=bool(args.row_masks))
+                    row_masks=bool(args.row_masks), interp_tile=args.interp_tile)
     red = torch.zeros((wl.npart, 12), dtype=torch.float64, device=dev)
     tuned = None
     if not args.no_autotune and not args.bucket_width and not args.spread_wgs:
@@ -494,7 +498,7 @@ def run():
         q = plan.query()
         pl2 = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, bucket_width=q["bucket_width"],
                        spread_wgs_per_cu=q["spread_wgs_per_cu"], use_graph=True,
-                       row_masks=bool(q["row_masks"]))
+                       row_masks=bool(q["row_masks"]), interp_tile=q["interp_tile"])
 
         def step2():
             ibx.build_markers_into(dl2, p2, m2)
@@ -603,7 +607,8 @@ def run():
         # the particle-by-particle order: conflict levels, then one loop per level
         q = plan.query()
         pseq = ibx.Plan(P, torch.float32, ibx.IB_PATH_BATCHED, bucket_width=q["bucket_width"],
-                        spread_wgs_per_cu=q["spread_wgs_per_cu"], row_masks=bool(q["row_masks"]))
+                        spread_wgs_per_cu=q["spread_wgs_per_cu"], row_masks=bool(q["row_masks"]),
+                        interp_tile=q["interp_tile"])
         useq = torch.empty_like(u32)
         fseq = torch.empty_like(u32)
         Fseq = torch.empty_like(F32)

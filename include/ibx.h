@@ -198,18 +198,23 @@ int ib_spread(const ib_level* lv, const ib_markers* m, const ib_buckets* b, ib_d
 /* and the finalize step load only those; it pays when the slots do not fit */
 /* in the caches (on the 20000-sphere 512^3 workload, not on 1000 spheres   */
 /* at 256^3).  Results are the same either way (a row of zeros reads back  */
-/* as +0).                                                                  */
+/* as +0).  interp_tile (batched path): x extent of the interpolation work  */
+/* tiles, 8 (one 8^3 tile; 0 = 8) or 16 (two x neighbours, whose markers    */
+/* share one staged halo: 20 x 12 x 12 cells instead of two 12^3; FP32      */
+/* plans only, else IB_EUNSUPPORTED).  Spreading, bucketing and the G slots */
+/* stay on 8^3 tiles; results agree to rounding (an item's marker count    */
+/* decides over how many lanes each marker's stencil sum is split).         */
 /* ib_plan_autotune, ib_plan_profile_read, ib_particle_levels and           */
 /* ib_multidirect_sequential synchronize and must not be captured; every    */
 /* other call only enqueues work on its stream and may be.                  */
 /* ---------------------------------------------------------------------- */
 int ib_plan_create(ib_plan** plan, ib_delta delta, ib_prec prec, ib_path path,
                    int32_t bucket_width, int32_t spread_wgs_per_cu, int32_t use_graph,
-                   int32_t row_masks);
+                   int32_t row_masks, int32_t interp_tile);
 void ib_plan_destroy(ib_plan* plan);
-/* Current tuning of a plan (out: int32[5]): out[0] = path, out[1] =
+/* Current tuning of a plan (out: int32[6]): out[0] = path, out[1] =
  * bucket_width, out[2] = spread_wgs_per_cu, out[3] = use_graph, out[4] =
- * row_masks. */
+ * row_masks, out[5] = interp_tile. */
 int ib_plan_query(const ib_plan* plan, int32_t* out);
 /* Workspace of ib_multidirect_force and ib_plan_autotune (device bytes); it
  * does not depend on the plan's tuning. */
@@ -244,10 +249,11 @@ int ib_multidirect_force(ib_plan* plan, const ib_level* lv, const ib_particles* 
 /* Autotuning of a batched plan (the batching extension of the coupling loop:
  * the work-item width, the spreading residency and the slot row masks are
  * chosen on the real inputs).  Times the loop of ib_multidirect_force for
- * every bucket_width in {64, 128, 256}, spread_wgs_per_cu in {4, 8, 16, 32}
- * and row_masks in {0, 1} (one warm-up, then the faster of two samples of
- * 3 runs) and keeps the fastest in the plan (see ib_plan_query); the row
- * masks are kept only when they win by more than 1%.  The
+ * every bucket_width in {64, 128, 256}, spread_wgs_per_cu in {4, 8, 16, 32},
+ * row_masks in {0, 1} and (FP32) interp_tile in {8, 16} (one warm-up, then
+ * the faster of two samples of 3 runs) and keeps the fastest in the plan
+ * (see ib_plan_query); the row masks and the 16-wide work tile are kept only
+ * when they win by more than 1%.  The
  * tile stays 8^3: one 64-wide wavefront holds the 64 rows of a tile.
  * Arguments as ib_multidirect_force, except that ustar must not alias u0 and
  * no residual or history is taken; ustar, f and F hold the result of the

@@ -32,6 +32,7 @@ struct ib_plan {
     int32_t spread_wgs_per_cu;
     int32_t use_graph;
     int32_t row_masks;
+    int32_t interp_tile;   // x extent of an interpolation work tile: 8 or 16
     int32_t ncu;
     // launch sequence captured for one argument set
     hipGraph_t graph;
@@ -116,6 +117,7 @@ static BatchedCfg cfg_of(const ib_plan* pl)
     c.ncu = pl->ncu;
     c.wgs_s = pl->spread_wgs_per_cu;
     c.masks = pl->row_masks;
+    c.txw = pl->interp_tile;
     c.prof = pl->prof;
     return c;
 }
@@ -135,7 +137,7 @@ using namespace ibx;
 
 extern "C" int ib_plan_create(ib_plan** plan, ib_delta delta, ib_prec prec, ib_path path,
                               int32_t bucket_width, int32_t spread_wgs_per_cu,
-                              int32_t use_graph, int32_t row_masks)
+                              int32_t use_graph, int32_t row_masks, int32_t interp_tile)
 {
     if (!plan || (delta != IB_DELTA3 && delta != IB_DELTA4) ||
         (prec != IB_F32 && prec != IB_F64) ||
@@ -149,6 +151,12 @@ extern "C" int ib_plan_create(ib_plan** plan, ib_delta delta, ib_prec prec, ib_p
         spread_wgs_per_cu = 16;
     if (spread_wgs_per_cu < 1 || spread_wgs_per_cu > 32)
         return IB_EINVAL;
+    if (interp_tile == 0)
+        interp_tile = 8;
+    if (interp_tile != 8 && interp_tile != 16)
+        return IB_EINVAL;
+    if (interp_tile == 16 && prec != IB_F32)
+        return IB_EUNSUPPORTED;
     ib_plan* pl = new (std::nothrow) ib_plan;
     if (!pl)
         return IB_EINVAL;
@@ -160,6 +168,7 @@ extern "C" int ib_plan_create(ib_plan** plan, ib_delta delta, ib_prec prec, ib_p
     pl->spread_wgs_per_cu = spread_wgs_per_cu;
     pl->use_graph = use_graph ? 1 : 0;
     pl->row_masks = row_masks ? 1 : 0;
+    pl->interp_tile = interp_tile;
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
@@ -232,6 +241,7 @@ extern "C" int ib_plan_query(const ib_plan* plan, int32_t* out)
     out[2] = plan->spread_wgs_per_cu;
     out[3] = plan->use_graph;
     out[4] = plan->row_masks;
+    out[5] = plan->interp_tile;
     return IB_OK;
 }
 
@@ -436,9 +446,9 @@ extern "C" int ib_multidirect_sequential(ib_plan* plan, const ib_level* lv,
                                   (hipStream_t)stream);
 }
 
-// Autotuning: time the batched loop for every bucket width, spreading
-// residency and use of the slot row masks on the caller's inputs and keep the
-// fastest.
+// Autotuning: time the batched loop for every interpolation work tile (FP32:
+// 8^3 or 16 x 8 x 8), bucket width, spreading residency and use of the slot
+// row masks on the caller's inputs and keep the fastest.
 extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_particles* p,
                                 const ib_markers* m, const ib_buckets* b, int32_t ns, double dt,
                                 const void* u0, void* ustar, void* f, void* F, void* ws,
@@ -463,17 +473,20 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
     if (e == hipSuccess)
         e = hipEventCreate(&e1);
     const int32_t keep_bw = plan->bucket_width, keep_wgs = plan->spread_wgs_per_cu,
-                  keep_masks = plan->row_masks;
+                  keep_masks = plan->row_masks, keep_tile = plan->interp_tile;
     float best = -1.f;
-    int32_t best_bw = keep_bw, best_wgs = keep_wgs, best_masks = keep_masks;
+    int32_t best_bw = keep_bw, best_wgs = keep_wgs, best_masks = keep_masks,
+            best_tile = keep_tile;
+    const int ntile = plan->prec == IB_F32 ? 2 : 1;
     Profiler* prof = plan->prof;
     plan->prof = nullptr;
-    for (int q = 0; q < 6 && e == hipSuccess && rc == IB_OK; ++q)
+    for (int q = 0; q < 6 * ntile && e == hipSuccess && rc == IB_OK; ++q)
         for (int j = 0; j < 4 && e == hipSuccess && rc == IB_OK; ++j) {
-            const int i = q % 3, mk = q / 3;
+            const int i = q % 3, mk = (q / 3) % 2, tl = q / 6;
             plan->bucket_width = widths[i];
             plan->spread_wgs_per_cu = wgs[j];
             plan->row_masks = mk;
+            plan->interp_tile = tl ? 16 : 8;
             const BatchedCfg cfg = cfg_of(plan);
             rc = batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0, ustar, f,
                                      F, nullptr, nullptr, ws, ws_bytes, st);
@@ -495,13 +508,16 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
                 if (ms < 0.f || sample_ms < ms)
                     ms = sample_ms;
             }
-            // the row masks must win by more than 1% (the candidates without
-            // them come first), so near-ties keep the simpler setting
-            if (e == hipSuccess && rc == IB_OK && (best < 0.f || ms < best * (mk ? 0.99f : 1.f))) {
+            // the row masks and the wider work tile must win by more than 1%
+            // (the candidates without them come first), so near-ties keep
+            // the simpler setting
+            const float edge = mk || tl ? 0.99f : 1.f;
+            if (e == hipSuccess && rc == IB_OK && (best < 0.f || ms < best * edge)) {
                 best = ms;
                 best_bw = widths[i];
                 best_wgs = wgs[j];
                 best_masks = mk;
+                best_tile = tl ? 16 : 8;
             }
         }
     plan->prof = prof;
@@ -514,6 +530,7 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
         plan->bucket_width = keep_bw;
         plan->spread_wgs_per_cu = keep_wgs;
         plan->row_masks = keep_masks;
+        plan->interp_tile = keep_tile;
         if (e != hipSuccess)
             set_hip_error(e);
         return rc != IB_OK ? rc : IB_EHIP;
@@ -521,6 +538,7 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
     plan->bucket_width = best_bw;
     plan->spread_wgs_per_cu = best_wgs;
     plan->row_masks = best_masks;
+    plan->interp_tile = best_tile;
     if (out_ms)
         *out_ms = best / REPS;
     return IB_OK;

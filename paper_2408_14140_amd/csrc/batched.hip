@@ -247,8 +247,30 @@ __device__ inline int slab_of(int a, int n_act)
     return a / per;
 }
 
+// Markers of the interpolation work tile that tile t leads (first one in
+// *start): tile t alone, or with PAIR (work tiles of two x neighbours) tiles
+// t and t + 1 when t has an even x index (t alone when it ends its row), and
+// none when its x index is odd.  Markers are sorted by tile, so the two
+// tiles' markers are one run.  (Tile indices fit 32 bits: the marker offsets
+// are 32-bit.)
+template <bool PAIR>
+__device__ inline int item_markers(const int32_t* __restrict__ tile_offs, int64_t t, int nt0,
+                                   int* start)
+{
+    const int s = tile_offs[t];
+    *start = s;
+    if (!PAIR)
+        return tile_offs[t + 1] - s;
+    const int tx = (int)t % nt0;
+    if (tx & 1)
+        return 0;
+    return (tx + 1 < nt0 ? tile_offs[t + 2] : tile_offs[t + 1]) - s;
+}
+
 // (block 0 also clears the cost histogram that k_cost_hist fills next)
-__global__ void k_tile_counts(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
+template <bool PAIR>
+__global__ void k_tile_counts(int64_t T, int bw, int nt0,
+                              const int32_t* __restrict__ tile_offs,
                               const int32_t* __restrict__ src_offs, int32_t* item_cnt,
                               int32_t* act, int32_t* __restrict__ hist)
 {
@@ -258,7 +280,8 @@ __global__ void k_tile_counts(int64_t T, int bw, const int32_t* __restrict__ til
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T)
         return;
-    const int cnt = tile_offs[t + 1] - tile_offs[t];
+    int start;
+    const int cnt = item_markers<PAIR>(tile_offs, t, nt0, &start);
     item_cnt[t] = (cnt + bw - 1) / bw;
     act[t] = src_offs[t + 1] > src_offs[t] ? 1 : 0;
 }
@@ -290,8 +313,9 @@ k_cost_hist(int64_t T, const int32_t* __restrict__ src_offs, const int32_t* __re
 // ceil(markers / bw) of scan tile b, workgroup nb + b the flags "source list
 // not empty" (the inputs are formed from the offsets on the fly); workgroup 0
 // also clears the cost histogram.
+template <bool PAIR>
 __global__ void __launch_bounds__(SCAN_THREADS)
-k_list_scan(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
+k_list_scan(int64_t T, int bw, int nt0, const int32_t* __restrict__ tile_offs,
             const int32_t* __restrict__ src_offs, int32_t* __restrict__ item_offs,
             int32_t* __restrict__ act_offs, int32_t* __restrict__ sums,
             int32_t* __restrict__ hist)
@@ -312,9 +336,11 @@ k_list_scan(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         const int64_t i = base + k;
         v[k] = 0;
-        if (i < T)
+        if (i < T) {
+            int start;
             v[k] = second ? (src_offs[i + 1] > src_offs[i] ? 1 : 0)
-                          : (tile_offs[i + 1] - tile_offs[i] + bw - 1) / bw;
+                          : (item_markers<PAIR>(tile_offs, i, nt0, &start) + bw - 1) / bw;
+        }
         tsum += v[k];
     }
     ts[t] = tsum;
@@ -412,8 +438,9 @@ k_bin_scan(const int32_t* __restrict__ hist, const int32_t* __restrict__ nactive
 // (-1 when its source list is empty), and the spreading entries (slot, tile,
 // source range) in spreading order (cur[x][b] holds the first free position
 // of bin b of slab x).
+template <bool PAIR>
 __global__ void __launch_bounds__(256)
-k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
+k_fill_lists(int64_t T, int bw, int nt0, const int32_t* __restrict__ tile_offs,
              const int32_t* __restrict__ src_offs, const int32_t* __restrict__ item_offs,
              const int32_t* __restrict__ act_offs, const int32_t* __restrict__ nactive,
              Item* items, int32_t* slot, int32_t* __restrict__ cur,
@@ -428,8 +455,8 @@ k_fill_lists(int64_t T, int bw, const int32_t* __restrict__ tile_offs,
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int bin = -1, rank = 0, s0 = 0, s1 = 0;
     if (t < T) {
-        const int start = tile_offs[t];
-        const int cnt = tile_offs[t + 1] - start;
+        int start;
+        const int cnt = item_markers<PAIR>(tile_offs, t, nt0, &start);
         const int io = item_offs[t];
         for (int k = 0; k * bw < cnt; ++k) {
             Item it;
@@ -522,7 +549,8 @@ k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G,
             const int64_t off = (int64_t)bid * g.bstride +
                                 ((int64_t)(lz + g.ngrow) * g.ext + (ly + g.ngrow)) * g.ext +
                                 (lx + g.ngrow);
-            const int64_t go = (int64_t)s * 3 * TILE_CELLS + (lx & 7) + TILE * (yy + TILE * (cz & 7));
+            const int64_t go =
+                (int64_t)s * 3 * TILE_CELLS + (lx & 7) + TILE * (yy + TILE * (cz & 7));
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const T v = s >= 0 ? G[go + c * TILE_CELLS] : T(0);
@@ -688,6 +716,10 @@ __global__ void k_zero(int64_t n, T* a)
 
 // ------------------------------------------------------------------ host
 
+// Neighbour tiles per interpolation item: 27 for an 8^3 work tile, 36 for a
+// 16 x 8 x 8 one.
+constexpr int NB_MAX = 36;
+
 template <typename T>
 struct BatchedWs {
     MarkerData<T> s;
@@ -702,7 +734,7 @@ struct BatchedWs {
     uint64_t* tmask;   // the same per tile (stale on tiles without a slot)
     void* scan;
     int64_t max_items;
-    int64_t *nb_u, *nb_g;   // [item][27] element offsets of the neighbouring tiles
+    int64_t *nb_u, *nb_g;   // [item][9 NBX] element offsets of the neighbouring tiles
 };
 
 template <typename T>
@@ -735,32 +767,70 @@ static BatchedWs<T> carve_batched(const Grid& g, int64_t nl, int bw, void* ws, s
     w.G = cv.take<T>((size_t)3 * TILE_CELLS * (max_active > 0 ? max_active : 1));
     w.rmask = cv.take<uint64_t>(max_active > 0 ? max_active : 1);
     w.tmask = cv.take<uint64_t>(T_ > 0 ? T_ : 1);
-    w.nb_u = cv.take<int64_t>(27 * w.max_items);
-    w.nb_g = cv.take<int64_t>(27 * w.max_items);
+    w.nb_u = cv.take<int64_t>(NB_MAX * w.max_items);
+    w.nb_g = cv.take<int64_t>(NB_MAX * w.max_items);
     w.scan = cv.take<char>(scan2_workspace(T_));
     *need = cv.used;
     return w;
 }
 
-template <typename T, int P, int MODE, bool MASK>
-static void launch_interp_bw(const BatchedCfg& cfg, hipStream_t st, const Grid& g, int64_t nl,
+template <typename T, int P, int MODE, bool MASK, int TXW, int BW>
+static void interp_kernel(const BatchedCfg& cfg, hipStream_t st, const Grid& g, int64_t nl,
                           double dt, const Item* items, const int32_t* nitems, const T* u0,
                           const T* G, const uint64_t* rmask, const int64_t* nbase,
-                          const MarkerData<T>& s, double* e2,
-                          T* Fout, const int32_t* perm, const T* vin, double* gX, int use_dv)
+                          const MarkerData<T>& s, double* e2, T* Fout, const int32_t* perm,
+                          const T* vin, double* gX, int use_dv)
+{
+    constexpr auto K = k_interp_tiles<T, P, MODE, BW, MASK, TXW>;
+    K<<<resident_grid<K, BW>(cfg.ncu, 0), BW, 0, st>>>(g, nl, dt, items, nitems, u0, G, nbase, s,
+                                                       e2, Fout, perm, vin, gX, use_dv, rmask);
+}
+
+template <typename T, int P, int MODE, bool MASK, int TXW>
+static void launch_interp_txw(const BatchedCfg& cfg, hipStream_t st, const Grid& g, int64_t nl,
+                              double dt, const Item* items, const int32_t* nitems, const T* u0,
+                              const T* G, const uint64_t* rmask, const int64_t* nbase,
+                              const MarkerData<T>& s, double* e2, T* Fout, const int32_t* perm,
+                              const T* vin, double* gX, int use_dv)
 {
     if (cfg.bw == 64)
-        k_interp_tiles<T, P, MODE, 64, MASK>
-            <<<resident_grid<k_interp_tiles<T, P, MODE, 64, MASK>, 64>(cfg.ncu, 0), 64, 0, st>>>(
-                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm, vin, gX, use_dv, rmask);
+        interp_kernel<T, P, MODE, MASK, TXW, 64>(cfg, st, g, nl, dt, items, nitems, u0, G, rmask,
+                                                 nbase, s, e2, Fout, perm, vin, gX, use_dv);
     else if (cfg.bw == 128)
-        k_interp_tiles<T, P, MODE, 128, MASK>
-            <<<resident_grid<k_interp_tiles<T, P, MODE, 128, MASK>, 128>(cfg.ncu, 0), 128, 0, st>>>(
-                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm, vin, gX, use_dv, rmask);
+        interp_kernel<T, P, MODE, MASK, TXW, 128>(cfg, st, g, nl, dt, items, nitems, u0, G,
+                                                  rmask, nbase, s, e2, Fout, perm, vin, gX,
+                                                  use_dv);
     else
-        k_interp_tiles<T, P, MODE, 256, MASK>
-            <<<resident_grid<k_interp_tiles<T, P, MODE, 256, MASK>, 256>(cfg.ncu, 0), 256, 0, st>>>(
-                g, nl, dt, items, nitems, u0, G, nbase, s, e2, Fout, perm, vin, gX, use_dv, rmask);
+        interp_kernel<T, P, MODE, MASK, TXW, 256>(cfg, st, g, nl, dt, items, nitems, u0, G,
+                                                  rmask, nbase, s, e2, Fout, perm, vin, gX,
+                                                  use_dv);
+}
+
+// Work tiles of two x neighbours are compiled for FP32 only (their halo in
+// FP64 would need 69 KB of LDS).
+template <typename T>
+static int pair_items(const BatchedCfg& cfg)
+{
+    return sizeof(T) == 4 && cfg.txw == 2 * TILE;
+}
+
+template <typename T, int P, int MODE, bool MASK>
+static void launch_interp_bw(const BatchedCfg& cfg, hipStream_t st, const Grid& g, int64_t nl,
+                             double dt, const Item* items, const int32_t* nitems, const T* u0,
+                             const T* G, const uint64_t* rmask, const int64_t* nbase,
+                             const MarkerData<T>& s, double* e2, T* Fout, const int32_t* perm,
+                             const T* vin, double* gX, int use_dv)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (pair_items<T>(cfg)) {
+            launch_interp_txw<T, P, MODE, MASK, 2 * TILE>(cfg, st, g, nl, dt, items, nitems, u0,
+                                                          G, rmask, nbase, s, e2, Fout, perm,
+                                                          vin, gX, use_dv);
+            return;
+        }
+    }
+    launch_interp_txw<T, P, MODE, MASK, TILE>(cfg, st, g, nl, dt, items, nitems, u0, G, rmask,
+                                              nbase, s, e2, Fout, perm, vin, gX, use_dv);
 }
 
 // Interpolation from the G slots (modes 1, 2) uses the slot row masks when the
@@ -804,6 +874,40 @@ static void launch_spread(const BatchedCfg& cfg, hipStream_t st, const Grid& g,
 #define IBX_PROF_END() \
     if (cfg.prof) cfg.prof->end(st)
 
+// Work lists of the interpolation items (work tiles of one tile, or with
+// PAIR of two x neighbours) and of the active tiles, and each item's
+// neighbour offsets.
+template <typename T, bool PAIR>
+static void build_lists(const Grid& g, const BatchedCfg& cfg, const ib_buckets* b,
+                        BatchedWs<T>& w, hipStream_t st)
+{
+    const int64_t T_ = g.ntiles;
+    const unsigned gt = (unsigned)((T_ + 255) / 256);
+    const int64_t nbl = (T_ + SCAN_TILE - 1) / SCAN_TILE;
+    if (2 * nbl <= SCAN_FUSE) {
+        int32_t* sums = (int32_t*)w.scan;
+        k_list_scan<PAIR><<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
+            T_, cfg.bw, g.nt[0], b->tile_offs, b->src_offs, w.item_offs, w.act_offs, sums,
+            w.hist);
+        k_list_add<<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
+            T_, b->src_offs, w.item_offs, w.act_offs, sums, w.nitems, w.nactive, w.hist);
+    } else {
+        k_tile_counts<PAIR><<<gt, 256, 0, st>>>(T_, cfg.bw, g.nt[0], b->tile_offs, b->src_offs,
+                                                w.item_cnt, w.act, w.hist);
+        scan_exclusive2(w.item_cnt, w.item_offs, w.act, w.act_offs, T_, w.nitems, w.nactive,
+                        w.scan, st);
+        k_cost_hist<<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.hist);
+    }
+    k_bin_scan<<<NXCD, COST_BINS, 0, st>>>(w.hist, w.nactive, w.cur);
+    k_fill_lists<PAIR><<<gt, 256, 0, st>>>(T_, cfg.bw, g.nt[0], b->tile_offs, b->src_offs,
+                                           w.item_offs, w.act_offs, w.nactive, w.items, w.slot,
+                                           w.cur, w.sent);
+    constexpr int NBX = PAIR ? 4 : 3;
+    const int64_t nth = 9 * NBX * w.max_items;
+    k_item_bases<NBX><<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(g, w.items, w.nitems,
+                                                                     w.slot, w.nb_u, w.nb_g);
+}
+
 // Marker records in bucket order and the work lists of the tile kernels
 // (interpolation items, G slots, spreading order, neighbour offsets).
 template <typename T, int P>
@@ -812,37 +916,16 @@ static void records_and_lists(const Grid& g, const BatchedCfg& cfg, const ib_par
                               hipStream_t st)
 {
     const int64_t nl = m->nl;
-    const int64_t T_ = g.ntiles;
     const unsigned gm = (unsigned)((nl + 255) / 256 > 0 ? (nl + 255) / 256 : 1);
-    const unsigned gt = (unsigned)((T_ + 255) / 256);
     IBX_PROF_BEGIN(PK_PREP);
     k_prep<T, P><<<gm, 256, 0, st>>>(g, nl, m->x, m->y, m->z, m->pid, m->dv, b->perm, p->xc,
                                      p->up, p->om, w.s);
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_LISTS);
-    const int64_t nbl = (T_ + SCAN_TILE - 1) / SCAN_TILE;
-    if (2 * nbl <= SCAN_FUSE) {
-        int32_t* sums = (int32_t*)w.scan;
-        k_list_scan<<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
-            T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs, w.act_offs, sums, w.hist);
-        k_list_add<<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
-            T_, b->src_offs, w.item_offs, w.act_offs, sums, w.nitems, w.nactive, w.hist);
-    } else {
-        k_tile_counts<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_cnt,
-                                          w.act, w.hist);
-        scan_exclusive2(w.item_cnt, w.item_offs, w.act, w.act_offs, T_, w.nitems, w.nactive,
-                        w.scan, st);
-        k_cost_hist<<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.hist);
-    }
-    k_bin_scan<<<NXCD, COST_BINS, 0, st>>>(w.hist, w.nactive, w.cur);
-    k_fill_lists<<<gt, 256, 0, st>>>(T_, cfg.bw, b->tile_offs, b->src_offs, w.item_offs,
-                                     w.act_offs, w.nactive, w.items, w.slot, w.cur,
-                                     w.sent);
-    {
-        const int64_t nth = 27 * w.max_items;
-        k_item_bases<<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(g, w.items, w.nitems, w.slot,
-                                                                    w.nb_u, w.nb_g);
-    }
+    if (pair_items<T>(cfg))
+        build_lists<T, true>(g, cfg, b, w, st);
+    else
+        build_lists<T, false>(g, cfg, b, w, st);
     IBX_PROF_END();
 }
 

@@ -29,6 +29,7 @@ struct BatchedCfg {
     int ncu;       // compute units of the device
     int wgs_s;     // cap on resident spreading workgroups per CU (0 = as many as fit)
     int masks;     // G slot row masks: zero rows neither stored nor loaded
+    int txw;       // x extent of an interpolation work tile: 8 (one tile) or 16 (FP32)
     Profiler* prof;  // nullable: per-kernel event timing
 };
 

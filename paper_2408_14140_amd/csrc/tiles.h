@@ -47,25 +47,28 @@ __device__ inline Slab xcd_slab(int n)
     return r;
 }
 
-// Element offsets of the 27 tiles around every interpolation item: [it][27]
-// for the velocity field (box layout) and for the per-tile force buffer.
-// -1 where the tile lies outside a bounded axis, in an uncovered box, or has
-// no force slot.
+// Element offsets of the 9 NBX tiles around every interpolation item (NBX
+// along x: the work tile's own TXW / 8 tiles and one on each side; 3 along y
+// and z): [it][9 NBX] for the velocity field (box layout) and for the
+// per-tile force buffer.  -1 where the tile lies outside a bounded axis, in
+// an uncovered box, or has no force slot.
+template <int NBX>
 __global__ void k_item_bases(Grid g, const Item* __restrict__ items,
                              const int32_t* __restrict__ nitems, const int32_t* __restrict__ slot,
                              int64_t* __restrict__ nb_u, int64_t* __restrict__ nb_g)
 {
+    constexpr int NNB = 9 * NBX;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t it = q / 27;
+    const int64_t it = q / NNB;
     if (it >= *nitems)
         return;
-    const int k = (int)(q - it * 27);
+    const int k = (int)(q - it * NNB);
     int lo[3];
     const int t = items[it].tile;
     lo[0] = (t % g.nt[0]) * TILE;
     lo[1] = ((t / g.nt[0]) % g.nt[1]) * TILE;
     lo[2] = (t / (g.nt[0] * g.nt[1])) * TILE;
-    const int sel[3] = {k % 3, (k / 3) % 3, k / 9};
+    const int sel[3] = {k % NBX, (k / NBX) % 3, k / (3 * NBX)};
     int c[3];
     bool ok = true;
     for (int a = 0; a < 3; ++a) {
@@ -95,11 +98,11 @@ __global__ void k_item_bases(Grid g, const Item* __restrict__ items,
 //         (field . vin_l) grad_X w_l, sc = dV/h^3 (use_dv) or 1, in marker
 //         order (the weights' derivatives from the same shared root).
 // e2 (nullable) receives dV |U^d - J u^(m)|^2 per marker.
-// (FP32 with the row masks, 256-marker items: registers capped at the
-// unmasked kernel's seven waves per SIMD.)
-template <typename T, int P, int MODE, int BW, bool MASK = false>
+// (FP32 with the row masks, 256-marker items of one tile: registers capped at
+// the unmasked kernel's seven waves per SIMD.)
+template <typename T, int P, int MODE, int BW, bool MASK = false, int TXW = TILE>
 __global__ void __launch_bounds__(BW)
-__attribute__((amdgpu_waves_per_eu(MASK && sizeof(T) == 4 && BW == 256 ? 7 : 1, 8)))
+__attribute__((amdgpu_waves_per_eu(MASK && sizeof(T) == 4 && BW == 256 && TXW == TILE ? 7 : 1, 8)))
 k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                const int32_t* __restrict__ nitems, const T* __restrict__ u0,
                const T* __restrict__ G, const int64_t* __restrict__ nbase, MarkerData<T> s,
@@ -109,14 +112,20 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
 {
     constexpr bool BOX = MODE == 0 || MODE == 3;   // field in the box layout
     constexpr int gh = Halo<P>::g, R = Halo<P>::R;
-    // LDS holds the halo as rows [c][jz][jy] of pitch RP = 12 with halo x
-    // index jx at position jx + XO, so the tile's own 8 cells sit at 2..9
-    // and every row segment lands on an aligned pair boundary.
-    constexpr int RP = 12, XO = 2 - gh, PL = R * R * RP, NROW = 3 * R * R;
+    // The work tile is TXW x 8 x 8 cells: one tile, or two x neighbours
+    // (TXW = 16).  LDS holds its halo as rows [c][jz][jy] of pitch RP with
+    // halo x index jx at position jx + XO, so the tile's own cells sit at
+    // 2 .. TXW + 1 and every row segment lands on an aligned pair boundary.
+    // NBX tiles along x (the TXW / 8 own ones and one on each side), 3 along
+    // y and z, hold the halo.
+    constexpr int RX = TXW + 2 * gh, RP = TXW == TILE ? 12 : 20, XO = 2 - gh;
+    constexpr int PL = R * R * RP, NROW = 3 * R * R;
+    constexpr int NBX = TXW / TILE + 2, NNB = 9 * NBX;
+    static_assert(TXW == TILE || TXW == 2 * TILE, "work tile of one or two tiles along x");
     using T2 = typename Vec2<T>::type;
     __shared__ __align__(16) T fld[3 * PL];
-    __shared__ int64_t nb[27];
-    __shared__ uint64_t nbm[27];        // tile slots: rows of each neighbour's slot not all zero
+    __shared__ int64_t nb[NNB];
+    __shared__ uint64_t nbm[NNB];       // tile slots: rows of each neighbour's slot not all zero
     const int n_items = *nitems;
     const double h3 = g.h * g.h * g.h;
     const int tid = threadIdx.x;
@@ -124,7 +133,6 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     const int sy = BOX ? g.ext : TILE;
     const int sz = BOX ? g.ext * g.ext : TILE * TILE;
     const T* src = BOX ? u0 : G;
-    const bool paired = true;   // tile slots: rows start on multiples of 8 elements
     const Slab sl = xcd_slab(n_items);
     // The neighbour offsets of each item are loaded one item ahead (two with
     // the row masks, whose loads follow them one item ahead), so the staging
@@ -132,39 +140,40 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     auto row_mask = [&](int64_t off) -> uint64_t {
         return off >= 0 ? rmask[off / (3 * TILE_CELLS)] : 0ull;
     };
-    int64_t pnb = sl.begin < sl.end && tid < 27 ? nbase[(int64_t)sl.begin * 27 + tid] : 0;
+    int64_t pnb = sl.begin < sl.end && tid < NNB ? nbase[(int64_t)sl.begin * NNB + tid] : 0;
     uint64_t pm = 0ull;
     int64_t qnb = 0;
     if constexpr (MASK) {
-        if (tid < 27 && sl.begin < sl.end)
+        if (tid < NNB && sl.begin < sl.end)
             pm = row_mask(pnb);
-        if (tid < 27 && sl.begin + sl.stride < sl.end)
-            qnb = nbase[(int64_t)(sl.begin + sl.stride) * 27 + tid];
+        if (tid < NNB && sl.begin + sl.stride < sl.end)
+            qnb = nbase[(int64_t)(sl.begin + sl.stride) * NNB + tid];
     }
     for (int it = sl.begin; it < sl.end; it += sl.stride) {
-        if (tid < 27) {
+        if (tid < NNB) {
             nb[tid] = pnb;
             if constexpr (MASK)
                 nbm[tid] = pm;
         }
         __syncthreads();
         if constexpr (MASK) {
-            if (tid < 27) {
+            if (tid < NNB) {
                 pnb = qnb;
                 pm = it + sl.stride < sl.end ? row_mask(qnb) : 0ull;
                 if (it + 2 * sl.stride < sl.end)
-                    qnb = nbase[(int64_t)(it + 2 * sl.stride) * 27 + tid];
+                    qnb = nbase[(int64_t)(it + 2 * sl.stride) * NNB + tid];
             }
-        } else if (tid < 27 && it + sl.stride < sl.end) {
-            pnb = nbase[(int64_t)(it + sl.stride) * 27 + tid];
+        } else if (tid < NNB && it + sl.stride < sl.end) {
+            pnb = nbase[(int64_t)(it + sl.stride) * NNB + tid];
         }
         const Item item = items[it];
         int lo[3];
         tile_coords(g, item.tile, lo);
         // Marker records are fetched just before the halo so both streams of
-        // loads are in flight together.  Small items spread each marker over `split` consecutive lanes, one
-        // z plane of the stencil per lane (then a shuffle sum), so every wave
-        // of the workgroup takes part in the compute phase.
+        // loads are in flight together.  Small items spread each marker over
+        // `split` consecutive lanes, one z plane of the stencil per lane (then
+        // a shuffle sum), so every wave of the workgroup takes part in the
+        // compute phase.
         const int cnt = item.count;
         const int lg = 4 * cnt <= BW ? 2 : 2 * cnt <= BW ? 1 : 0;
         const int split = 1 << lg;
@@ -210,14 +219,14 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
         if (BOX) {
             // box layout: rows are a box extent apart, so consecutive lanes
             // take consecutive cells of the halo
-            constexpr int R3 = R * R * R, NPT = (R3 + BW - 1) / BW;
+            constexpr int R3 = RX * R * R, NPT = (R3 + BW - 1) / BW;
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 const int q = tid + k * BW;
                 if (q < R3) {
-                    const int jx = q % R, jy = (q / R) % R, jz = q / (R * R);
-                    const int sel = ((jx - gh + TILE) >> 3) + 3 * (((jy - gh + TILE) >> 3) +
-                                                                  3 * ((jz - gh + TILE) >> 3));
+                    const int jx = q % RX, jy = (q / RX) % R, jz = q / (RX * R);
+                    const int sel = ((jx - gh + TILE) >> 3) + NBX * (((jy - gh + TILE) >> 3) +
+                                                                    3 * ((jz - gh + TILE) >> 3));
                     const int64_t b = nb[sel];
                     T v0 = T(0), v1 = T(0), v2 = T(0);
                     if (b >= 0) {
@@ -234,93 +243,73 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                 }
             }
         }
-        // tile slots: stage the halo row by row -- left segment (gh cells of
-        // the -x neighbour), the 8 cells of the middle tile, right segment
+        // tile slots (rows start on multiples of 8 elements, so they move in
+        // pairs): stage the halo row by row -- left segment (gh cells of the
+        // -x neighbour), the 8 cells of each own tile, right segment
         for (int task = tid; !BOX && task < NROW; task += BW) {
             const int c = task / (R * R), rr = task - c * (R * R);
             const int jy = rr % R, jz = rr / R;
             const int ys = (jy - gh + TILE) >> 3, zs = (jz - gh + TILE) >> 3;
             const int64_t roff = (int64_t)sy * ((jy - gh) & 7) + (int64_t)sz * ((jz - gh) & 7) +
                                  c * comp;
-            const int q0 = 3 * (ys + 3 * zs);
-            int64_t bl = nb[q0], bc = nb[q0 + 1], br = nb[q0 + 2];
+            const int q0 = NBX * (ys + 3 * zs);
+            int64_t bn[NBX];
+#pragma unroll
+            for (int x = 0; x < NBX; ++x)
+                bn[x] = nb[q0 + x];
             if constexpr (MASK) {
                 // a neighbour row whose mask bit is clear is all zeros in its slot
                 const int rbit = ((jy - gh) & 7) + TILE * ((jz - gh) & 7);
-                bl = (nbm[q0] >> rbit) & 1 ? bl : -1;
-                bc = (nbm[q0 + 1] >> rbit) & 1 ? bc : -1;
-                br = (nbm[q0 + 2] >> rbit) & 1 ? br : -1;
+#pragma unroll
+                for (int x = 0; x < NBX; ++x)
+                    bn[x] = (nbm[q0 + x] >> rbit) & 1 ? bn[x] : -1;
             }
             T* row = fld + ((c * R + jz) * R + jy) * RP;
-            T m[TILE];
-            T l[gh], r[gh];
-            if (paired) {
+            // every load of the row is issued before its first store
+            const int64_t bl = bn[0], br = bn[NBX - 1];
+            T2 v[TXW / 2];
+#pragma unroll
+            for (int mt = 0; mt < TXW / TILE; ++mt) {
+                const int64_t bc = bn[1 + mt];
                 if (bc >= 0) {
                     const T2* q = reinterpret_cast<const T2*>(src + bc + roff);
 #pragma unroll
-                    for (int k = 0; k < TILE / 2; ++k) {
-                        const T2 v = q[k];
-                        m[2 * k] = v.x;
-                        m[2 * k + 1] = v.y;
-                    }
+                    for (int k = 0; k < TILE / 2; ++k)
+                        v[mt * (TILE / 2) + k] = q[k];
                 } else {
 #pragma unroll
-                    for (int k = 0; k < TILE; ++k)
-                        m[k] = T(0);
-                }
-                if (gh == 2) {
-                    T2 vl, vr;
-                    vl.x = vl.y = vr.x = vr.y = T(0);
-                    if (bl >= 0)
-                        vl = *reinterpret_cast<const T2*>(src + bl + roff + (TILE - 2));
-                    if (br >= 0)
-                        vr = *reinterpret_cast<const T2*>(src + br + roff);
-                    l[0] = vl.x;
-                    l[gh - 1] = vl.y;
-                    r[0] = vr.x;
-                    r[gh - 1] = vr.y;
-                } else {
-                    l[0] = bl >= 0 ? src[bl + roff + TILE - 1] : T(0);
-                    r[0] = br >= 0 ? src[br + roff] : T(0);
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < TILE; ++k)
-                    m[k] = bc >= 0 ? src[bc + roff + k] : T(0);
-#pragma unroll
-                for (int k = 0; k < gh; ++k) {
-                    l[k] = bl >= 0 ? src[bl + roff + TILE - gh + k] : T(0);
-                    r[k] = br >= 0 ? src[br + roff + k] : T(0);
+                    for (int k = 0; k < TILE / 2; ++k)
+                        v[mt * (TILE / 2) + k].x = v[mt * (TILE / 2) + k].y = T(0);
                 }
             }
-#pragma unroll
-            for (int k = 0; k < TILE / 2; ++k) {
-                T2 v;
-                v.x = m[2 * k];
-                v.y = m[2 * k + 1];
-                *reinterpret_cast<T2*>(row + 2 + 2 * k) = v;
-            }
+            T2 vl, vr;
+            vl.x = vl.y = vr.x = vr.y = T(0);
             if (gh == 2) {
-                T2 v;
-                v.x = l[0];
-                v.y = l[gh - 1];
-                *reinterpret_cast<T2*>(row) = v;
-                v.x = r[0];
-                v.y = r[gh - 1];
-                *reinterpret_cast<T2*>(row + 2 + TILE) = v;
+                if (bl >= 0)
+                    vl = *reinterpret_cast<const T2*>(src + bl + roff + (TILE - 2));
+                if (br >= 0)
+                    vr = *reinterpret_cast<const T2*>(src + br + roff);
             } else {
-                row[XO] = l[0];
-                row[2 + TILE] = r[0];
+                vl.x = bl >= 0 ? src[bl + roff + TILE - 1] : T(0);
+                vr.x = br >= 0 ? src[br + roff] : T(0);
+            }
+#pragma unroll
+            for (int k = 0; k < TXW / 2; ++k)
+                *reinterpret_cast<T2*>(row + 2 + 2 * k) = v[k];
+            if (gh == 2) {
+                *reinterpret_cast<T2*>(row) = vl;
+                *reinterpret_cast<T2*>(row + 2 + TXW) = vr;
+            } else {
+                row[XO] = vl.x;
+                row[2 + TXW] = vr.x;
             }
         }
         __syncthreads();
         T acc0 = 0, acc1 = 0, acc2 = 0;
         T gr0 = 0, gr1 = 0, gr2 = 0;      // mode 3: position gradient
         if (mine) {
-            bool ok = true;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                ok &= (lb[a] >= 0 && lb[a] <= R - P);
+            const bool ok = lb[0] >= 0 && lb[0] <= RX - P && lb[1] >= 0 && lb[1] <= R - P &&
+                            lb[2] >= 0 && lb[2] <= R - P;
             // planes sub, sub + split, ...: the trip count is uniform per item
             const int trips = (P + split - 1) >> lg;
             for (int n = 0; n < trips; ++n) {

@@ -73,7 +73,7 @@ _bucket = _sig("ib_bucket", C.c_int, [_PL, _PM, C.c_int, _PB, _p, _sz, _p])
 _interp = _sig("ib_interp", C.c_int, [_PL, _PM, C.c_int, C.c_int, _p, _p, _p])
 _spread = _sig("ib_spread", C.c_int, [_PL, _PM, _PB, C.c_int, C.c_int, _p, _p, _p])
 _plan_create = _sig("ib_plan_create", C.c_int,
-                    [C.POINTER(_p), C.c_int, C.c_int, C.c_int, _i32, _i32, _i32, _i32])
+                    [C.POINTER(_p), C.c_int, C.c_int, C.c_int, _i32, _i32, _i32, _i32, _i32])
 _plan_destroy = _sig("ib_plan_destroy", None, [_p])
 _plan_query = _sig("ib_plan_query", C.c_int, [_p, _p])
 _ws_bytes = _sig("ib_workspace_bytes", _sz, [_p, _PL, _i64, _i32])
@@ -405,21 +405,21 @@ class Plan:
 
     def __init__(self, delta: int, dtype=torch.float32, path: int = IB_PATH_AUTO,
                  bucket_width: int = 0, spread_wgs_per_cu: int = 0, use_graph: bool = False,
-                 row_masks: bool = False):
+                 row_masks: bool = False, interp_tile: int = 0):
         self.delta = int(delta)
         self.dtype = dtype
         h = _p()
         _check(_plan_create(C.byref(h), self.delta, _prec_of(dtype), int(path),
                             int(bucket_width), int(spread_wgs_per_cu), int(bool(use_graph)),
-                            int(bool(row_masks))), "ib_plan_create")
+                            int(bool(row_masks)), int(interp_tile)), "ib_plan_create")
         self._h = h
         self._ws = None
 
     def query(self):
-        out = np.zeros(5, dtype=np.int32)
+        out = np.zeros(6, dtype=np.int32)
         _check(_plan_query(self._h, out.ctypes.data), "ib_plan_query")
         return dict(path=int(out[0]), bucket_width=int(out[1]), spread_wgs_per_cu=int(out[2]),
-                    use_graph=int(out[3]), row_masks=int(out[4]))
+                    use_graph=int(out[3]), row_masks=int(out[4]), interp_tile=int(out[5]))
 
     def profile(self, enable: bool = True):
         _check(_plan_profile(self._h, int(bool(enable))), "ib_plan_profile")
@@ -464,9 +464,10 @@ class Plan:
 
     def autotune(self, level: DeviceLevel, parts: Particles, m: Markers, b: Buckets, ns: int,
                  dt: float, u0: torch.Tensor) -> dict:
-        """Pick bucket width, spreading residency and the use of the slot row
-        masks by timing the loop on these inputs (synchronizes the current
-        stream).  Returns the choice and its loop time in ms."""
+        """Pick the interpolation work tile, bucket width, spreading residency
+        and the use of the slot row masks by timing the loop on these inputs
+        (synchronizes the current stream).  Returns the choice and its loop
+        time in ms."""
         dev = u0.device
         if u0.dtype != self.dtype:
             raise TypeError("u0 dtype differs from the plan precision")

@@ -104,7 +104,8 @@ def test_adjoint_matches_oracle(dev, name, mk, dtype, path):
                          ids=["grad_small-f64", "spheres64_128-f32"])
 def test_adjoint_with_row_masks(dev, name, mk, dtype):
     """The adjoint's spreads through the slot row masks give the same
-    gradients as without them."""
+    gradients as without them (and, in FP32, its interpolation on 16 x 8 x 8
+    work tiles the same to rounding)."""
     import torch
     announce(f"adjoint row masks {name} {dtype}")
     wl = mk()
@@ -116,6 +117,12 @@ def test_adjoint_with_row_masks(dev, name, mk, dtype):
     b = _grads(c, dtype, 2, wts, with_ustar=gus, row_masks=True)
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+    if dtype == "f32":      # and with work tiles of two x neighbours, to rounding
+        t = _grads(c, dtype, 2, wts, with_ustar=gus, row_masks=True, interp_tile=16)
+        for x, y in zip(a, t):
+            x = x.detach().double().cpu().numpy()
+            y = y.detach().double().cpu().numpy()
+            assert np.linalg.norm(y - x) <= 1e-5 * np.linalg.norm(x)
 
 
 def test_adjoint_matches_central_differences_on_gpu(dev):

@@ -289,6 +289,54 @@ def test_row_masks_match_oracle_and_unmasked(dev, name, mk, dtype):
     assert torch.equal(ip[2], a[2])
 
 
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("masks", [False, True], ids=["", "masks"])
+def test_interp_tile_16_matches_oracle_and_8(dev, name, mk, masks):
+    """FP32 loop with interpolation work tiles of two x neighbours (16 x 8 x 8,
+    one shared halo): against the oracle, and against the 8^3 work tiles to
+    rounding (1e-6; an item's marker count decides over how many lanes each
+    marker's stencil is summed), with residuals, force history and in
+    place."""
+    import torch
+
+    import oracle as O
+    announce(f"interp tile 16 {name} masks={masks}")
+    wl = mk()
+    c = Case(wl, dev)
+    ref = O.multidirect(c.g, wl.delta, wl.ns, wl.dt, c.m, wl.xc, wl.up, wl.om, wl.u0,
+                        history=True)
+    a = _run(c, "f32", 2, fhist=True, row_masks=masks)
+    w = _run(c, "f32", 2, fhist=True, row_masks=masks, interp_tile=16)
+    ustar, f, F, r, Fh, _ = w
+    assert rel(F.cpu().numpy(), ref["F"]) <= TOL32
+    assert c.field_rel(f, ref["f"]) <= TOL32
+    assert c.field_rel(ustar, ref["ustar"]) <= TOL32
+    m = np.broadcast_to(c.mask, (3,) + c.mask.shape)
+    for x, y in zip(a[:2], w[:2]):
+        assert rel(c.to_global(y)[m], c.to_global(x)[m]) <= 1e-6
+    for x, y in zip(a[2:5], w[2:5]):
+        assert rel(y.double().cpu().numpy(), x.double().cpu().numpy()) <= 1e-6
+    ip = _run(c, "f32", 2, inplace=True, resid=False, row_masks=masks, interp_tile=16)
+    assert np.array_equal(c.to_global(ip[0])[m], c.to_global(w[0])[m])
+    assert torch.equal(ip[2], w[2])
+    # and reproducible: a second run gives the same bits
+    w2 = _run(c, "f32", 2, fhist=True, row_masks=masks, interp_tile=16)
+    for x, y in zip(w[2:5], w2[2:5]):
+        assert torch.equal(x, y)
+
+
+def test_interp_tile_16_is_fp32_only(dev):
+    import torch
+
+    import paper_2408_14140_amd as ibx
+    announce("interp tile 16 refused in FP64")
+    with pytest.raises(ibx.IbxError) as e:
+        ibx.Plan(4, torch.float64, ibx.IB_PATH_BATCHED, interp_tile=16)
+    assert e.value.status == ibx.IB_EUNSUPPORTED
+    with pytest.raises(ibx.IbxError):
+        ibx.Plan(4, torch.float32, ibx.IB_PATH_BATCHED, interp_tile=12)
+
+
 @pytest.mark.parametrize("ns", [1, 2])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_row_masks_short_loops(dev, ns, dtype):
