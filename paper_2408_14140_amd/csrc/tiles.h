@@ -102,7 +102,8 @@ __global__ void k_item_bases(Grid g, const Item* __restrict__ items,
 // the unmasked kernel's seven waves per SIMD.)
 template <typename T, int P, int MODE, int BW, bool MASK = false, int TXW = TILE>
 __global__ void __launch_bounds__(BW)
-__attribute__((amdgpu_waves_per_eu(MASK && sizeof(T) == 4 && BW == 256 && TXW == TILE ? 7 : 1, 8)))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && BW == 256 && TXW == TILE
+                                        ? (MASK ? 7 : MODE == 0 ? 5 : 1) : 1, 8)))
 k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                const int32_t* __restrict__ nitems, const T* __restrict__ u0,
                const T* __restrict__ G, const int64_t* __restrict__ nbase, MarkerData<T> s,
@@ -122,6 +123,7 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     constexpr int PL = R * R * RP, NROW = 3 * R * R;
     constexpr int NBX = TXW / TILE + 2, NNB = 9 * NBX;
     static_assert(TXW == TILE || TXW == 2 * TILE, "work tile of one or two tiles along x");
+    static_assert(TXW + 4 <= RP, "a row holds the paired window of TXW + 4 cells");
     using T2 = typename Vec2<T>::type;
     __shared__ __align__(16) T fld[3 * PL];
     __shared__ int64_t nb[NNB];
@@ -133,6 +135,9 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
     const int sy = BOX ? g.ext : TILE;
     const int sz = BOX ? g.ext * g.ext : TILE * TILE;
     const T* src = BOX ? u0 : G;
+    // box layout: pair loads need an even ghost width and a field aligned to
+    // two elements (box extents and component strides are then even)
+    const bool pairs = BOX && (g.ngrow & 1) == 0 && !((uintptr_t)src & (2 * sizeof(T) - 1));
     const Slab sl = xcd_slab(n_items);
     // The neighbour offsets of each item are loaded one item ahead (two with
     // the row masks, whose loads follow them one item ahead), so the staging
@@ -216,9 +221,39 @@ k_interp_tiles(Grid g, int64_t nl, double dt, const Item* __restrict__ items,
                     fv = s.f4[i];
             }
         }
-        if (BOX) {
-            // box layout: rows are a box extent apart, so consecutive lanes
-            // take consecutive cells of the halo
+        if (BOX && pairs) {
+            // box layout with an even ghost width: every tile starts on an
+            // even element, so the window lo - 2 .. lo + TXW + 1 of each row
+            // (the halo of either kernel width) moves in aligned x pairs, none
+            // across a tile; consecutive lanes take consecutive pairs
+            constexpr int NPR = TXW / 2 + 2, R2 = NPR * R * R, NPT = (R2 + BW - 1) / BW;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int q = tid + k * BW;
+                if (q < R2) {
+                    const int px = q % NPR, jy = (q / NPR) % R, jz = q / (NPR * R);
+                    const int xo = 2 * px - 2;   // x of the pair's first cell from lo
+                    const int sel = ((xo + TILE) >> 3) + NBX * (((jy - gh + TILE) >> 3) +
+                                                                3 * ((jz - gh + TILE) >> 3));
+                    const int64_t b = nb[sel];
+                    T2 v0, v1, v2;
+                    v0.x = v0.y = v1.x = v1.y = v2.x = v2.y = T(0);
+                    if (b >= 0) {
+                        const T* p = src + b + (xo & 7) + (int64_t)sy * ((jy - gh) & 7) +
+                                     (int64_t)sz * ((jz - gh) & 7);
+                        v0 = *reinterpret_cast<const T2*>(p);
+                        v1 = *reinterpret_cast<const T2*>(p + comp);
+                        v2 = *reinterpret_cast<const T2*>(p + 2 * comp);
+                    }
+                    const int at = (jz * R + jy) * RP + 2 * px;
+                    *reinterpret_cast<T2*>(fld + at) = v0;
+                    *reinterpret_cast<T2*>(fld + PL + at) = v1;
+                    *reinterpret_cast<T2*>(fld + 2 * PL + at) = v2;
+                }
+            }
+        } else if (BOX) {
+            // box layout, odd ghost width: consecutive lanes take consecutive
+            // cells of the halo
             constexpr int R3 = RX * R * R, NPT = (R3 + BW - 1) / BW;
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {

@@ -434,6 +434,32 @@ def test_box_tiling_invariance(dev):
         assert rel(F, outs[0][1]) <= 1e-14
 
 
+@pytest.mark.parametrize("delta", [3, 4])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_odd_ghost_width(dev, dtype, delta):
+    """Ghost widths 1 and 3 (the halo staged cell by cell) against the oracle,
+    and against ghost width 2 (staged in x pairs) bit for bit: the same
+    values reach every kernel, only from other addresses."""
+    import oracle as O
+    announce(f"odd ghost width {dtype} P{delta}")
+    wl = small_workload(32, 16, delta, 3, 6)
+    c0 = Case(wl, dev)
+    ref = O.multidirect(c0.g, wl.delta, wl.ns, wl.dt, c0.m, wl.xc, wl.up, wl.om, wl.u0)
+    tol = TOL64 if dtype == "f64" else TOL32
+    outs = []
+    for ng in (2, 1, 3):
+        lev = W.make_level(wl.level.n, wl.level.h, box=16, ngrow=ng)
+        w2 = W.Workload(wl.name, lev, wl.delta, wl.ns, wl.dt, wl.xc, wl.d, wl.up, wl.om, wl.u0)
+        c = Case(w2, dev)
+        ustar, f, F, _, _, _ = _run(c, dtype, 2, resid=False)
+        outs.append((c.to_global(ustar), c.to_global(f), F.cpu().numpy()))
+        assert rel(outs[-1][2], ref["F"]) <= tol
+        assert rel(outs[-1][0], ref["ustar"]) <= tol
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
 def _big_spheres():
     """Two spheres far larger than the others here (bounding boxes of 64 and
     75 cells per axis, thousands of near-surface cells per workgroup, so the
@@ -540,25 +566,28 @@ def test_batched_rejects_unsupported_levels(dev):
         assert e.value.status == ibx.IB_EUNSUPPORTED
 
 
-def test_batched_misaligned_fields(dev):
-    """Fields that start one element past an 8-byte boundary take the
-    single-cell finalize instead of the pair one: the results are the same
-    bit for bit."""
+@pytest.mark.parametrize("delta", [3, 4])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batched_misaligned_fields(dev, dtype, delta):
+    """Fields that start one element past a two-element boundary take the
+    single-cell halo staging and finalize instead of the pair ones: the
+    results are the same bit for bit."""
     import torch
 
     import paper_2408_14140_amd as ibx
-    announce("batched path, misaligned field pointers")
-    wl = small_workload(32, 16, 4, 3, 2)
+    announce(f"batched path, misaligned field pointers {dtype} P{delta}")
+    wl = small_workload(32, 16, delta, 3, 2)
     c = Case(wl, dev)
     b = ibx.bucket(c.dl, c.dm, wl.delta)
-    plan = ibx.Plan(wl.delta, torch.float32, ibx.IB_PATH_BATCHED)
-    u0 = c.u0_boxes(torch.float32)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    plan = ibx.Plan(wl.delta, tdt, ibx.IB_PATH_BATCHED)
+    u0 = c.u0_boxes(tdt)
 
     def shifted(t):
         base = torch.full((t.numel() + 1,), float("nan"), dtype=t.dtype, device=dev)
         v = base[1:].view(t.shape)
         v.copy_(t)
-        assert v.data_ptr() % 8 == 4
+        assert v.data_ptr() % (2 * t.element_size()) == t.element_size()
         return v
 
     outs = []
