@@ -854,19 +854,32 @@ static void launch_interp(const BatchedCfg& cfg, hipStream_t st, const Grid& g, 
                                         s, e2, Fout, perm, vin, gX, use_dv);
 }
 
+// The tile spreading: one 2 x 2 x 2 block per lane for the 3-point kernel,
+// one row per lane for the 4-point one (the faster layout for each width).
+template <typename T, int P, bool MASK>
+static void spread_kernel(const BatchedCfg& cfg, hipStream_t st, const Grid& g,
+                          const BatchedWs<T>& w, const ib_buckets* b, int use_dv)
+{
+    if constexpr (P == 3) {
+        constexpr auto K = k_spread_blocks<T, P, MASK>;
+        K<<<resident_grid<K, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
+            w.sent, w.nactive, b->src_idx, g, w.s, w.G, w.rmask, w.tmask, use_dv);
+    } else {
+        constexpr auto K = k_spread_tiles<T, P, MASK>;
+        K<<<resident_grid<K, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
+            w.sent, w.nactive, b->src_idx, g, w.s, w.G, w.rmask, w.tmask, use_dv);
+    }
+}
+
 // The tile spreading, with or without the slot row masks.
 template <typename T, int P>
 static void launch_spread(const BatchedCfg& cfg, hipStream_t st, const Grid& g,
                           const BatchedWs<T>& w, const ib_buckets* b, int use_dv)
 {
     if (cfg.masks)
-        k_spread_tiles<T, P, true>
-            <<<resident_grid<k_spread_tiles<T, P, true>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
-                w.sent, w.nactive, b->src_idx, g, w.s, w.G, w.rmask, w.tmask, use_dv);
+        spread_kernel<T, P, true>(cfg, st, g, w, b, use_dv);
     else
-        k_spread_tiles<T, P, false>
-            <<<resident_grid<k_spread_tiles<T, P, false>, 64>(cfg.ncu, cfg.wgs_s), 64, 0, st>>>(
-                w.sent, w.nactive, b->src_idx, g, w.s, w.G, w.rmask, w.tmask, use_dv);
+        spread_kernel<T, P, false>(cfg, st, g, w, b, use_dv);
 }
 
 #define IBX_PROF_BEGIN(k) \

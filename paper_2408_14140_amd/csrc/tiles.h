@@ -749,3 +749,286 @@ k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactiv
         ent = nent;
     }
 }
+
+// The same spreading with one 2 x 2 x 2 block of the tile per lane instead
+// of one row; it takes the entries of `sent` as k_spread_tiles does.
+//
+// Each lane holds one 2 x 2 x 2 block of the tile (lane = bx + 4 by + 16 bz,
+// cells 2 bx .. 2 bx + 1 along x and so on).  Sources are staged 64 at a
+// time as structure-of-arrays in LDS: per axis the P weights with a zero on
+// each side, and F dV/h^3 (F alone when use_dv is 0: the transpose of
+// interpolation in the adjoint).  Twelve ballots give, per block index along
+// each axis, the 64-bit set of staged sources whose stencil overlaps it; a
+// lane's own set is the AND of its three, and the lane visits exactly those
+// sources in list order.  A stencil of P cells overlaps (P - 1)/2 + 1 blocks
+// of 2 per axis on average, so a visit spends fewer of its multiply-adds on
+// zero weights than a whole 8-cell row would, at the price of more work per
+// visit (two dependent LDS reads, ten products besides the 24 multiply-adds)
+// and half-row stores.  It is the faster of the two for the 3-point kernel,
+// whose stencil covers less of an 8-cell row; the rows are faster for the
+// 4-point kernel.  A block cell just outside the stencil reads a zero pad.
+// LDS stays near 6.5 KB so that 24 workgroups fit on a CU.
+// (FP32: registers capped so that 6 waves fit per SIMD, the residency that the
+// latency-bound visit chain wants.)
+template <typename T, int P, bool MASK = false>
+__global__ void __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1, 8)))
+k_spread_blocks(const int4* __restrict__ sent, const int32_t* __restrict__ nactive,
+               const int32_t* __restrict__ src_idx, Grid g, MarkerData<T> s,
+               T* __restrict__ G, uint64_t* __restrict__ rmask, uint64_t* __restrict__ tmask,
+               int use_dv)
+{
+    constexpr int PW = P + 2;                              // weights per axis, zero padded
+    constexpr int NW = 3 * PW + 3;                         // staged values per source
+    constexpr int NBUF = NW * 64;
+    constexpr int MAXP = NBUF / (3 * TILE) < 64 ? NBUF / (3 * TILE) : 64;   // phase-B pieces
+    constexpr int NB = TILE / 2;                           // blocks per axis
+    __shared__ T buf[NBUF];
+    // per source k: o_a = k - 64 (b_a - 1) for the stencil base b_a along
+    // axis a, so tile cell c's weight sits at s_a[64 c + o_a]; x and y in the
+    // 16-bit halves of .x (|o_a| < 2^15), z in .y
+    __shared__ int2 sb[64];
+    T* const sx = buf;                  // [PW][64] zero, the P x weights, zero
+    T* const sy = buf + PW * 64;        // [PW][64] y
+    T* const sz = sy + PW * 64;         // [PW][64] z
+    T* const sf = sz + PW * 64;         // [3][64]  F dV / h^3
+    __shared__ uint64_t rest[64];       // sources of each block left after phase A
+    __shared__ int32_t piece[MAXP];     // phase-B slot -> lane | piece << 8
+    using T2 = typename Vec2<T>::type;
+    // add source k's contribution to the 8 cells of block (cx, cy, cz):
+    // a[z][y][x][c], with F wx and wy wz formed once per visit
+    auto visit = [&](T (&a)[2][2][2][3], int cx, int cy, int cz, int k) {
+        const int2 o = sb[k];
+        const int ox = (int)(int16_t)(o.x & 0xffff), oy = o.x >> 16, oz = o.y;
+        const T* px = sx + 128 * cx + ox;
+        const T* py = sy + 128 * cy + oy;
+        const T* pz = sz + 128 * cz + oz;
+        const T wx[2] = {px[0], px[64]};
+        const T wy0 = py[0], wy1 = py[64], wz0 = pz[0], wz1 = pz[64];
+        const T f[3] = {sf[k], sf[64 + k], sf[128 + k]};
+        const T t[2][2] = {{wy0 * wz0, wy1 * wz0}, {wy0 * wz1, wy1 * wz1}};   // [z][y]
+#pragma unroll
+        for (int xi = 0; xi < 2; ++xi) {
+            const T u[3] = {f[0] * wx[xi], f[1] * wx[xi], f[2] * wx[xi]};
+#pragma unroll
+            for (int z = 0; z < 2; ++z)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        a[z][y][xi][c] += u[c] * t[z][y];
+        }
+    };
+    const int lane = threadIdx.x;
+    const int lbx = lane & 3, lby = (lane >> 2) & 3, lbz = lane >> 4;
+    const int n_act = *nactive;
+    const int per = (n_act + NXCD - 1) / NXCD;
+    const int x = blockIdx.x % NXCD, nwg = gridDim.x / NXCD, wg = blockIdx.x / NXCD;
+    const int s_end = min(n_act, (x + 1) * per);
+    auto entry = [&](int r) { return x * per + r * nwg + ((r & 1) ? nwg - 1 - wg : wg); };
+    // The source indices of each batch are loaded one batch ahead (the next
+    // tile's first batch after a tile's last), so the visits hide that load.
+    int idx = entry(0);
+    int4 ent = idx < s_end ? sent[idx] : make_int4(0, 0, 0, 0);
+    int pf = idx < s_end && ent.z + lane < ent.w ? src_idx[ent.z + lane] : 0;
+    for (int r = 0; idx < s_end; ++r) {
+        // (slot, tile, first source, end of sources) of this and the next tile
+        const int nidx = entry(r + 1);
+        const int4 nent = nidx < s_end ? sent[nidx] : make_int4(0, 0, 0, 0);
+        const int a = ent.x;
+        int lo[3];
+        tile_coords(g, ent.y, lo);
+        T acc[2][2][2][3];
+#pragma unroll
+        for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int xx = 0; xx < 2; ++xx)
+                    acc[z][y][xx][0] = acc[z][y][xx][1] = acc[z][y][xx][2] = T(0);
+        const int s0 = ent.z, s1 = ent.w;
+        for (int sbat = s0; sbat < s1; sbat += 64) {
+            const int sidx = sbat + lane;
+            const int cur = pf;
+            const bool more = sbat + 64 < s1;
+            const int n0 = more ? sbat + 64 : nent.z, n1 = more ? s1 : nent.w;
+            pf = n0 + lane < n1 ? src_idx[n0 + lane] : 0;
+            int b[3] = {64, 64, 64};    // no block for lanes past the list
+            if (sidx < s1) {
+                const int64_t i = cur;
+                const typename Vec4<T>::type gq = s.geo[i];
+                const typename Vec4<T>::type Fv = s.f4[i];
+                int rb[3];
+                unpack_rb(s.rb[i], rb);
+                T gw[3][P];
+                axis_weights_r<T, P>(gq.x, gw[0]);
+                axis_weights_r<T, P>(gq.y, gw[1]);
+                axis_weights_r<T, P>(gq.z, gw[2]);
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    int v = rb[ax] - lo[ax];
+                    if (v < -(P - 1)) v += g.n[ax];
+                    else if (v > TILE - 1) v -= g.n[ax];
+                    b[ax] = v;
+                }
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    T* sa = buf + ax * PW * 64;
+                    sa[lane] = T(0);
+#pragma unroll
+                    for (int o = 0; o < P; ++o)
+                        sa[(o + 1) * 64 + lane] = gw[ax][o];
+                    sa[(P + 1) * 64 + lane] = T(0);
+                }
+                const int ox = lane - 64 * (b[0] - 1), oy = lane - 64 * (b[1] - 1);
+                sb[lane] = make_int2((int)(((unsigned)ox & 0xffffu) | ((unsigned)oy << 16)),
+                                     lane - 64 * (b[2] - 1));
+                const T sc = use_dv ? gq.w : T(1);
+                sf[0 * 64 + lane] = Fv.x * sc;
+                sf[1 * 64 + lane] = Fv.y * sc;
+                sf[2 * 64 + lane] = Fv.z * sc;
+            }
+            // block cb along an axis overlaps the stencil [b, b + P) when
+            // b - 1 <= 2 cb <= b + P - 1
+            uint64_t mx = 0, my = 0, mz = 0;
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) {
+                const uint64_t xk = __ballot((unsigned)(2 * cb - b[0] + 1) < (unsigned)(P + 1));
+                const uint64_t yk = __ballot((unsigned)(2 * cb - b[1] + 1) < (unsigned)(P + 1));
+                const uint64_t zk = __ballot((unsigned)(2 * cb - b[2] + 1) < (unsigned)(P + 1));
+                mx = lbx == cb ? xk : mx;
+                my = lby == cb ? yk : my;
+                mz = lbz == cb ? zk : mz;
+            }
+            __syncthreads();
+            // Phase A: every lane visits up to K sources of its own block.
+            // Phase B: what is left of the heavier blocks is cut into pieces
+            // of K sources dealt out to the lanes; the owners then add the
+            // pieces in order.  K is the smallest cap whose pieces fit.
+            uint64_t M = mx & my & mz;
+            const int n = __popcll(M);
+            const int nmax = wave_max(n);
+            // 64 K + MAXP K >= the batch's visits bounds K from below; the
+            // cap rarely lies more than a few steps above that bound, so it
+            // is searched upwards from there.
+            int K = nmax;
+            if (nmax > 1) {
+                K = max(1, (wave_sum(n) + 63 + MAXP) / (64 + MAXP));
+                while (K < nmax && wave_sum(n > K ? small_div(n - 1, K) : 0) > MAXP)
+                    ++K;
+            }
+            for (int tt = 0; tt < K && M; ++tt) {
+                const int k = __builtin_ctzll(M);
+                M &= M - 1;
+                visit(acc, lbx, lby, lbz, k);
+            }
+            if (nmax > K) {
+                const int np = n > K ? small_div(n - 1, K) : 0;   // pieces of this block
+                const int ps = wave_exclusive_sum(np);
+                rest[lane] = M;
+                for (int q = 0; q < np; ++q)
+                    piece[ps + q] = lane | (q << 8);
+                const int NP = wave_sum(np);
+                __syncthreads();
+                T pacc[2][2][2][3];
+#pragma unroll
+                for (int z = 0; z < 2; ++z)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y)
+#pragma unroll
+                        for (int xx = 0; xx < 2; ++xx)
+                            pacc[z][y][xx][0] = pacc[z][y][xx][1] = pacc[z][y][xx][2] = T(0);
+                if (lane < NP) {
+                    const int pr = piece[lane] & 255, pq = piece[lane] >> 8;
+                    uint64_t m = drop_low_bits(rest[pr], pq * K);
+                    for (int tt = 0; tt < K && m; ++tt) {
+                        const int k = __builtin_ctzll(m);
+                        m &= m - 1;
+                        visit(pacc, pr & 3, (pr >> 2) & 3, pr >> 4, k);
+                    }
+                }
+                __syncthreads();
+                // the staged sources are no longer needed: pieces reuse them
+                if (lane < NP) {
+                    T* pp = buf + lane * 3 * TILE;
+#pragma unroll
+                    for (int z = 0; z < 2; ++z)
+#pragma unroll
+                        for (int y = 0; y < 2; ++y)
+#pragma unroll
+                            for (int xx = 0; xx < 2; ++xx)
+#pragma unroll
+                                for (int c = 0; c < 3; ++c)
+                                    pp[((z * 2 + y) * 2 + xx) * 3 + c] = pacc[z][y][xx][c];
+                }
+                __syncthreads();
+                for (int q = 0; q < np; ++q) {
+                    const T* pp = buf + (ps + q) * 3 * TILE;
+#pragma unroll
+                    for (int z = 0; z < 2; ++z)
+#pragma unroll
+                        for (int y = 0; y < 2; ++y)
+#pragma unroll
+                            for (int xx = 0; xx < 2; ++xx)
+#pragma unroll
+                                for (int c = 0; c < 3; ++c)
+                                    acc[z][y][xx][c] += pp[((z * 2 + y) * 2 + xx) * 3 + c];
+                }
+            }
+            __syncthreads();
+        }
+        // the lane's block is 4 rows of 2 cells per component in the slot
+        // (rows of 8 cells are contiguous there); with MASK, rows of zeros
+        // are not stored and their bit in the slot's row mask (kept by slot
+        // and by tile) is clear: row (y, z) is bit y + 8 z, held by the four
+        // lanes of its blocks along x
+        bool nz[2][2] = {{true, true}, {true, true}};
+        if constexpr (MASK) {
+            uint64_t bl[2][2];
+#pragma unroll
+            for (int z = 0; z < 2; ++z)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    bool v = false;
+#pragma unroll
+                    for (int xx = 0; xx < 2; ++xx)
+                        v = v || acc[z][y][xx][0] != T(0) || acc[z][y][xx][1] != T(0) ||
+                            acc[z][y][xx][2] != T(0);
+                    bl[z][y] = __ballot(v);
+                }
+            // lane j decides row j: y = j & 7, z = j >> 3
+            const int ry = lane & 7, rz = lane >> 3;
+            const uint64_t sel = (rz & 1) ? ((ry & 1) ? bl[1][1] : bl[1][0])
+                                          : ((ry & 1) ? bl[0][1] : bl[0][0]);
+            const bool row_nz = ((sel >> (4 * (ry >> 1) + 16 * (rz >> 1))) & 0xfull) != 0;
+            const uint64_t rm = __ballot(row_nz);
+#pragma unroll
+            for (int z = 0; z < 2; ++z)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    nz[z][y] = (rm >> ((2 * lby + y) + TILE * (2 * lbz + z))) & 1;
+            if (lane == 0) {
+                rmask[a] = rm;
+                tmask[ent.y] = rm;
+            }
+        }
+        T* gs = G + (int64_t)a * 3 * TILE_CELLS + 2 * lbx;
+#pragma unroll
+        for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                if (!nz[z][y])
+                    continue;
+                T* row = gs + TILE * (2 * lby + y) + TILE * TILE * (2 * lbz + z);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    T2 v;
+                    v.x = acc[z][y][0][c];
+                    v.y = acc[z][y][1][c];
+                    *reinterpret_cast<T2*>(row + c * TILE_CELLS) = v;
+                }
+            }
+        idx = nidx;
+        ent = nent;
+    }
+}

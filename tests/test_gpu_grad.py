@@ -78,7 +78,13 @@ def _small():
                            nmodes=8, K=4, cover_all=True)
 
 
-CASES = [("grad_small", _small), ("spheres64_128", lambda: W.config(5, 0))]
+def _small_p3():
+    return W.make_workload("grad_small_P3", 32, 16, 2, 3, 3, np.array([6.9, 8.4]), seed=12,
+                           nmodes=8, K=4, cover_all=True)
+
+
+CASES = [("grad_small", _small), ("grad_small_P3", _small_p3),
+         ("spheres64_128", lambda: W.config(5, 0))]
 
 
 @pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
@@ -100,8 +106,9 @@ def test_adjoint_matches_oracle(dev, name, mk, dtype, path):
 
 
 @pytest.mark.parametrize("name,mk,dtype", [("grad_small", _small, "f64"),
+                                           ("grad_small_P3", _small_p3, "f32"),
                                            ("spheres64_128", lambda: W.config(5, 0), "f32")],
-                         ids=["grad_small-f64", "spheres64_128-f32"])
+                         ids=["grad_small-f64", "grad_small_P3-f32", "spheres64_128-f32"])
 def test_adjoint_with_row_masks(dev, name, mk, dtype):
     """The adjoint's spreads through the slot row masks give the same
     gradients as without them (and, in FP32, its interpolation on 16 x 8 x 8
