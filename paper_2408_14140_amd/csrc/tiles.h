@@ -764,7 +764,7 @@ k_spread_tiles(const int4* __restrict__ sent, const int32_t* __restrict__ nactiv
 // of 2 per axis on average, so a visit spends fewer of its multiply-adds on
 // zero weights than a whole 8-cell row would, at the price of more work per
 // visit (two dependent LDS reads, ten products besides the 24 multiply-adds)
-// and half-row stores.  It is the faster of the two for the 3-point kernel,
+// and a pass through LDS before the rows are stored.  It is the faster of the two for the 3-point kernel,
 // whose stencil covers less of an 8-cell row; the rows are faster for the
 // 4-point kernel.  A block cell just outside the stencil reads a zero pad.
 // LDS stays near 6.5 KB so that 24 workgroups fit on a CU.
@@ -783,7 +783,7 @@ k_spread_blocks(const int4* __restrict__ sent, const int32_t* __restrict__ nacti
     constexpr int NBUF = NW * 64;
     constexpr int MAXP = NBUF / (3 * TILE) < 64 ? NBUF / (3 * TILE) : 64;   // phase-B pieces
     constexpr int NB = TILE / 2;                           // blocks per axis
-    __shared__ T buf[NBUF];
+    __shared__ __align__(16) T buf[NBUF];
     // per source k: o_a = k - 64 (b_a - 1) for the stencil base b_a along
     // axis a, so tile cell c's weight sits at s_a[64 c + o_a]; x and y in the
     // 16-bit halves of .x (|o_a| < 2^15), z in .y
@@ -977,12 +977,13 @@ k_spread_blocks(const int4* __restrict__ sent, const int32_t* __restrict__ nacti
             }
             __syncthreads();
         }
-        // the lane's block is 4 rows of 2 cells per component in the slot
-        // (rows of 8 cells are contiguous there); with MASK, rows of zeros
-        // are not stored and their bit in the slot's row mask (kept by slot
-        // and by tile) is clear: row (y, z) is bit y + 8 z, held by the four
-        // lanes of its blocks along x
-        bool nz[2][2] = {{true, true}, {true, true}};
+        // the block goes to the slot through LDS, one component at a time,
+        // so that each lane stores one whole row (8 cells, contiguous in the
+        // slot) as the row layout does; with MASK, rows of zeros are not
+        // stored and their bit in the slot's row mask (kept by slot and by
+        // tile) is clear: row (y, z) is bit y + 8 z, held by the four lanes
+        // of its blocks along x
+        bool row_nz = true;
         if constexpr (MASK) {
             uint64_t bl[2][2];
 #pragma unroll
@@ -1000,34 +1001,38 @@ k_spread_blocks(const int4* __restrict__ sent, const int32_t* __restrict__ nacti
             const int ry = lane & 7, rz = lane >> 3;
             const uint64_t sel = (rz & 1) ? ((ry & 1) ? bl[1][1] : bl[1][0])
                                           : ((ry & 1) ? bl[0][1] : bl[0][0]);
-            const bool row_nz = ((sel >> (4 * (ry >> 1) + 16 * (rz >> 1))) & 0xfull) != 0;
+            row_nz = ((sel >> (4 * (ry >> 1) + 16 * (rz >> 1))) & 0xfull) != 0;
             const uint64_t rm = __ballot(row_nz);
-#pragma unroll
-            for (int z = 0; z < 2; ++z)
-#pragma unroll
-                for (int y = 0; y < 2; ++y)
-                    nz[z][y] = (rm >> ((2 * lby + y) + TILE * (2 * lbz + z))) & 1;
             if (lane == 0) {
                 rmask[a] = rm;
                 tmask[ent.y] = rm;
             }
         }
-        T* gs = G + (int64_t)a * 3 * TILE_CELLS + 2 * lbx;
+        static_assert(TILE_CELLS <= NBUF, "one component of the tile fits the staging buffer");
+        T* gs = G + (int64_t)a * 3 * TILE_CELLS + TILE * lane;
 #pragma unroll
-        for (int z = 0; z < 2; ++z)
+        for (int c = 0; c < 3; ++c) {
 #pragma unroll
-            for (int y = 0; y < 2; ++y) {
-                if (!nz[z][y])
-                    continue;
-                T* row = gs + TILE * (2 * lby + y) + TILE * TILE * (2 * lbz + z);
+            for (int z = 0; z < 2; ++z)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
+                for (int y = 0; y < 2; ++y) {
                     T2 v;
                     v.x = acc[z][y][0][c];
                     v.y = acc[z][y][1][c];
-                    *reinterpret_cast<T2*>(row + c * TILE_CELLS) = v;
+                    *reinterpret_cast<T2*>(buf + TILE * TILE * (2 * lbz + z) +
+                                           TILE * (2 * lby + y) + 2 * lbx) = v;
                 }
+            __syncthreads();
+            const typename Vec4<T>::type v0 =
+                *reinterpret_cast<const typename Vec4<T>::type*>(buf + TILE * lane);
+            const typename Vec4<T>::type v1 =
+                *reinterpret_cast<const typename Vec4<T>::type*>(buf + TILE * lane + 4);
+            __syncthreads();
+            if (row_nz) {
+                *reinterpret_cast<typename Vec4<T>::type*>(gs + c * TILE_CELLS) = v0;
+                *reinterpret_cast<typename Vec4<T>::type*>(gs + c * TILE_CELLS + 4) = v1;
             }
+        }
         idx = nidx;
         ent = nent;
     }
