@@ -118,6 +118,7 @@ static BatchedCfg cfg_of(const ib_plan* pl)
     c.wgs_s = pl->spread_wgs_per_cu;
     c.masks = pl->row_masks;
     c.txw = pl->interp_tile;
+    c.partial = 0;
     c.prof = pl->prof;
     return c;
 }
@@ -472,6 +473,15 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess)
         e = hipEventCreate(&e1);
+    // Each candidate is timed as the replay of its captured graph, which is
+    // how the plan runs it: eager launches would add host submission gaps
+    // around the short list kernels and favour candidates with fewer of
+    // them.  The capture runs on a stream of the library's own (the caller's
+    // may be the null stream, which cannot be captured); the replays run on
+    // the caller's stream.
+    hipStream_t cs = nullptr;
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     const int32_t keep_bw = plan->bucket_width, keep_wgs = plan->spread_wgs_per_cu,
                   keep_masks = plan->row_masks, keep_tile = plan->interp_tile;
     float best = -1.f;
@@ -487,17 +497,27 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
             plan->spread_wgs_per_cu = wgs[j];
             plan->row_masks = mk;
             plan->interp_tile = tl ? 16 : 8;
-            const BatchedCfg cfg = cfg_of(plan);
-            rc = batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0, ustar, f,
-                                     F, nullptr, nullptr, ws, ws_bytes, st);
+            BatchedCfg cfg = cfg_of(plan);
+            cfg.partial = 1;     // the traffic of an in-place run, u0 left untouched
+            hipGraph_t gr = nullptr;
+            hipGraphExec_t ex = nullptr;
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                rc = batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0, ustar,
+                                         f, F, nullptr, nullptr, ws, ws_bytes, cs);
+                e = hipStreamEndCapture(cs, &gr);
+            }
+            if (e == hipSuccess && rc == IB_OK)
+                e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            if (e == hipSuccess && rc == IB_OK)
+                e = hipGraphLaunch(ex, st);             // warm-up
             // the faster of two samples of REPS runs each (one-off stalls
             // would otherwise decide between configurations a few % apart)
             float ms = -1.f;
             for (int k = 0; k < 2 && e == hipSuccess && rc == IB_OK; ++k) {
                 e = hipEventRecord(e0, st);
-                for (int r = 0; r < REPS && rc == IB_OK; ++r)
-                    rc = batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0,
-                                             ustar, f, F, nullptr, nullptr, ws, ws_bytes, st);
+                for (int r = 0; r < REPS && e == hipSuccess; ++r)
+                    e = hipGraphLaunch(ex, st);
                 if (e == hipSuccess)
                     e = hipEventRecord(e1, st);
                 if (e == hipSuccess)
@@ -508,6 +528,10 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
                 if (ms < 0.f || sample_ms < ms)
                     ms = sample_ms;
             }
+            if (ex)
+                (void)hipGraphExecDestroy(ex);
+            if (gr)
+                (void)hipGraphDestroy(gr);
             // the row masks and the wider work tile must win by more than 1%
             // (the candidates without them come first), so near-ties keep
             // the simpler setting
@@ -521,6 +545,12 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
             }
         }
     plan->prof = prof;
+    if (cs) {
+        const hipError_t es = hipStreamSynchronize(st);
+        if (e == hipSuccess)
+            e = es;
+        (void)hipStreamDestroy(cs);
+    }
     if (e0)
         (void)hipEventDestroy(e0);
     if (e1)
@@ -539,6 +569,12 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
     plan->spread_wgs_per_cu = best_wgs;
     plan->row_masks = best_masks;
     plan->interp_tile = best_tile;
+    // the timed runs left the cells of ustar without force as they were: one
+    // complete run with the chosen tuning writes the whole result
+    rc = batched_multidirect(g, plan->P, plan->prec, cfg_of(plan), p, m, b, ns, dt, u0, ustar, f,
+                             F, nullptr, nullptr, ws, ws_bytes, st);
+    if (rc != IB_OK)
+        return rc;
     if (out_ms)
         *out_ms = best / REPS;
     return IB_OK;

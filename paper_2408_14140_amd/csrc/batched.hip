@@ -515,12 +515,14 @@ int resident_grid(int ncu, int cap)
 // In place (ustar == u0) only the cells whose force is not exactly zero are
 // read and rewritten (u0 + dt 0 = u0): inside the tiles that have a force
 // slot, most cells lie outside every stencil.  With f_acc, f += G^ns instead,
-// on the same cells.  ustar may be null (f only).
+// on the same cells.  ustar may be null (f only).  A separate ustar takes u0
+// on the cells without force when copy is set (always, except in the timing
+// runs of the autotuner, which leave those cells as they were).
 template <typename T, bool F_ACC, bool MASK>
 __global__ void __launch_bounds__(256)
 k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G,
            const uint64_t* __restrict__ tilemask, const T* u0, T* ustar, T* __restrict__ f,
-           double dt, int use_g)
+           double dt, int use_g, int copy)
 {
     __shared__ int tslot[64];                 // G slot of each tile along the row
     __shared__ uint64_t tmask[64];            // and its row mask
@@ -564,7 +566,7 @@ k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G,
                     continue;
                 if (v != T(0))
                     __builtin_nontemporal_store(u0[o] + tdt * v, &ustar[o]);
-                else if (ustar != u0)
+                else if (copy)
                     __builtin_nontemporal_store(u0[o], &ustar[o]);
             }
         }
@@ -590,7 +592,7 @@ template <typename T, bool F_ACC, bool MASK>
 __global__ void __launch_bounds__(256)
 k_finalize_pairs(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G,
                  const uint64_t* __restrict__ tilemask, const T* u0, T* ustar, T* __restrict__ f,
-                 double dt, int use_g)
+                 double dt, int use_g, int copy)
 {
     using V2 = typename Pair<T>::type;
     __shared__ int tslot[64];                 // G slot of each tile along the row
@@ -643,7 +645,7 @@ k_finalize_pairs(Grid g, const int32_t* __restrict__ slot, const T* __restrict__
                 } else if (force) {
                     const V2 a = *reinterpret_cast<const V2*>(u0 + o);
                     __builtin_nontemporal_store(a + tdt * v, reinterpret_cast<V2*>(ustar + o));
-                } else if (ustar != u0) {
+                } else if (copy) {
                     const V2 a = *reinterpret_cast<const V2*>(u0 + o);
                     __builtin_nontemporal_store(a, reinterpret_cast<V2*>(ustar + o));
                 }
@@ -656,21 +658,22 @@ k_finalize_pairs(Grid g, const int32_t* __restrict__ slot, const T* __restrict__
 template <typename T, bool F_ACC, bool MASK>
 static void finalize_kernel(bool pairs, unsigned grid, unsigned gp, hipStream_t st, const Grid& g,
                             const int32_t* slot, const T* G, const uint64_t* tilemask,
-                            const T* u0, T* ustar, T* f, double dt, int use_g)
+                            const T* u0, T* ustar, T* f, double dt, int use_g, int copy)
 {
     if (pairs)
         k_finalize_pairs<T, F_ACC, MASK>
-            <<<gp, 256, 0, st>>>(g, slot, G, tilemask, u0, ustar, f, dt, use_g);
+            <<<gp, 256, 0, st>>>(g, slot, G, tilemask, u0, ustar, f, dt, use_g, copy);
     else
         k_finalize<T, F_ACC, MASK>
-            <<<grid, 256, 0, st>>>(g, slot, G, tilemask, u0, ustar, f, dt, use_g);
+            <<<grid, 256, 0, st>>>(g, slot, G, tilemask, u0, ustar, f, dt, use_g, copy);
 }
 
 template <typename T>
 static void launch_finalize(unsigned grid, hipStream_t st, const Grid& g, const int32_t* slot,
                             const T* G, const uint64_t* tilemask, const T* u0, T* ustar, T* f,
-                            double dt, int use_g, int f_acc, int masks)
+                            double dt, int use_g, int f_acc, int masks, int partial = 0)
 {
+    const int copy = ustar && ustar != u0 && !partial;
     // pairs of cells: rows start on even elements when ngrow is even, and the
     // pair loads and stores need the fields aligned to two elements
     const uintptr_t am = 2 * sizeof(T) - 1;
@@ -680,16 +683,16 @@ static void launch_finalize(unsigned grid, hipStream_t st, const Grid& g, const 
     const unsigned gp = (unsigned)(items < 65535 ? (items > 0 ? items : 1) : 65535);
     if (f_acc && masks)
         finalize_kernel<T, true, true>(pairs, grid, gp, st, g, slot, G, tilemask, u0, ustar, f,
-                                       dt, use_g);
+                                       dt, use_g, copy);
     else if (f_acc)
         finalize_kernel<T, true, false>(pairs, grid, gp, st, g, slot, G, tilemask, u0, ustar, f,
-                                        dt, use_g);
+                                        dt, use_g, copy);
     else if (masks)
         finalize_kernel<T, false, true>(pairs, grid, gp, st, g, slot, G, tilemask, u0, ustar, f,
-                                        dt, use_g);
+                                        dt, use_g, copy);
     else
         finalize_kernel<T, false, false>(pairs, grid, gp, st, g, slot, G, tilemask, u0, ustar, f,
-                                         dt, use_g);
+                                         dt, use_g, copy);
 }
 
 template <typename T>
@@ -1022,7 +1025,8 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     launch_spread<T, P>(cfg, st, g, w, b, 1);
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_FILL);
-    launch_finalize<T>(gfin, st, g, w.slot, w.G, w.tmask, u0, ustar, f, dt, 1, f_acc, cfg.masks);
+    launch_finalize<T>(gfin, st, g, w.slot, w.G, w.tmask, u0, ustar, f, dt, 1, f_acc, cfg.masks,
+                       cfg.partial);
     IBX_PROF_END();
     if (resid) {
         IBX_PROF_BEGIN(PK_RESID);
