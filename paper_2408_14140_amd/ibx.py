@@ -463,17 +463,26 @@ class Plan:
         return ustar, f, F
 
     def autotune(self, level: DeviceLevel, parts: Particles, m: Markers, b: Buckets, ns: int,
-                 dt: float, u0: torch.Tensor) -> dict:
+                 dt: float, u0: torch.Tensor, outputs=None) -> dict:
         """Pick the interpolation work tile, bucket width, spreading residency
         and the use of the slot row masks by timing the loop on these inputs
         (synchronizes the current stream).  Returns the choice and its loop
-        time in ms."""
+        time in ms.  ``outputs`` (ustar, f, F), if given, receive the loop's
+        result at the chosen tuning (ustar must not be u0)."""
         dev = u0.device
         if u0.dtype != self.dtype:
             raise TypeError("u0 dtype differs from the plan precision")
-        ustar = torch.empty_like(u0)
-        f = torch.empty_like(u0)
-        F = torch.empty((m.nl, 3), dtype=u0.dtype, device=dev)
+        if outputs is None:
+            ustar = torch.empty_like(u0)
+            f = torch.empty_like(u0)
+            F = torch.empty((m.nl, 3), dtype=u0.dtype, device=dev)
+        else:
+            ustar, f, F = outputs
+            if ustar.data_ptr() == u0.data_ptr():
+                raise ValueError("autotune cannot run in place")
+            for t, shape in ((ustar, u0.shape), (f, u0.shape), (F, (m.nl, 3))):
+                if tuple(t.shape) != tuple(shape) or t.dtype != u0.dtype or not t.is_contiguous():
+                    raise ValueError("autotune outputs must match u0 and [nl][3] in shape and type")
         ws = self.workspace(level, m.nl, ns, dev)
         ms = C.c_double(0.0)
         lc, pc, mc, bc = level.c, parts.c, m.c, b.c

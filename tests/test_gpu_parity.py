@@ -460,6 +460,44 @@ def test_odd_ghost_width(dev, dtype, delta):
             assert np.array_equal(a, b)
 
 
+def _dense_clump(delta):
+    """40 spheres of 6-10 cells packed around one point of a 64^3 grid (each
+    centre within 2 cells of it): a few tiles receive thousands of sources,
+    so every spreading batch cuts the heavier rows or blocks into pieces."""
+    rng = np.random.default_rng(31 + delta)
+    n = 64
+    xc = 0.5 + rng.normal(0.0, 1.0 / n, size=(40, 3))
+    return W.make_workload(f"dense_clump_P{delta}", n, 16, 2, delta, 3,
+                           rng.uniform(6.0, 10.0, 40), centres=xc, nmodes=8, K=4,
+                           cover_all=True)
+
+
+@pytest.mark.parametrize("delta", [3, 4])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_dense_clump_matches_oracle(dev, dtype, delta):
+    """Heavy tiles (the pieces of the spreading's second phase) with and
+    without the slot row masks, against the oracle; the masks change no bit."""
+    import torch
+
+    import oracle as O
+    announce(f"dense clump {dtype} P{delta}")
+    wl = _dense_clump(delta)
+    c = Case(wl, dev)
+    ref = O.multidirect(c.g, wl.delta, wl.ns, wl.dt, c.m, wl.xc, wl.up, wl.om, wl.u0)
+    counts = np.diff(O.bucket(c.lev, wl.delta, c.m)["src_offs"])
+    assert counts.max() > 2000                    # heavy tiles, as intended
+    tol = TOL64 if dtype == "f64" else TOL32
+    outs = []
+    for masks in (False, True):
+        ustar, f, F, _, _, _ = _run(c, dtype, 2, resid=False, row_masks=masks)
+        assert rel(F.cpu().numpy(), ref["F"]) <= tol
+        assert c.field_rel(f, ref["f"]) <= tol
+        assert c.field_rel(ustar, ref["ustar"]) <= tol
+        outs.append((c.to_global(ustar), c.to_global(f), F.cpu().numpy()))
+    for x, y in zip(*outs):                       # valid cells only
+        assert np.array_equal(x, y)
+
+
 def _big_spheres():
     """Two spheres far larger than the others here (bounding boxes of 64 and
     75 cells per axis, thousands of near-surface cells per workgroup, so the
@@ -523,13 +561,22 @@ def test_autotune_keeps_parity(dev, dtype):
     b = ibx.bucket(c.dl, c.dm, wl.delta)
     plan = ibx.Plan(wl.delta, tdt, ibx.IB_PATH_BATCHED)
     u0 = c.u0_boxes(tdt)
-    choice = plan.autotune(c.dl, c.parts, c.dm, b, wl.ns, wl.dt, u0)
+    u0_before = u0.clone()
+    outs = (torch.full_like(u0, float("nan")), torch.full_like(u0, float("nan")),
+            torch.full((c.m.nl, 3), float("nan"), dtype=tdt, device=dev))
+    choice = plan.autotune(c.dl, c.parts, c.dm, b, wl.ns, wl.dt, u0, outputs=outs)
+    # the timing runs leave u0 as it was, and the outputs hold one whole run
+    # at the chosen tuning (the timed runs write ustar only where G != 0)
+    assert torch.allclose(u0, u0_before, rtol=0.0, atol=0.0, equal_nan=True)   # NaN ghosts
     assert choice["bucket_width"] in (64, 128, 256)
     assert choice["spread_wgs_per_cu"] in (4, 8, 16, 32)
     assert choice["loop_ms"] > 0.0
     assert plan.query() == {k: v for k, v in choice.items() if k != "loop_ms"}
     ustar, f, F = plan.multidirect_force(c.dl, c.parts, c.dm, b, wl.ns, wl.dt, u0)
     torch.cuda.synchronize()
+    for x, y in zip(outs[:2], (ustar, f)):       # valid cells (NaN where uncovered)
+        assert np.array_equal(c.to_global(x), c.to_global(y), equal_nan=True)
+    assert torch.equal(outs[2], F)
     tol = TOL64 if dtype == "f64" else TOL32
     assert rel(F.cpu().numpy(), ref["F"]) <= tol
     assert c.field_rel(f, ref["f"]) <= tol
