@@ -103,20 +103,26 @@ def sources_sha():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(kernel, fname=TRAFFIC_FILE):
+def committed_traffic(kernel, fname=TRAFFIC_FILE, plan=None):
     """HBM bytes per launch of `kernel` from a committed counter summary
     (FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration), or None if
-    the summary is absent or the kernel sources changed since it was taken."""
+    the summary is absent, the kernel sources changed since it was taken, or
+    `plan` (a plan's query) runs other kernel variants (row masks, work tile)
+    than the counted run."""
     path = os.path.join(ROOT, fname)
     if not os.path.exists(path):
         return None
-    sha, val = None, None
+    sha, val, tuning = None, None, {}
     for ln in open(path):
         f = ln.split()
         if len(f) == 2 and f[0] == "sources_sha256_16:":
             sha = f[1]
         if len(f) == 3 and f[0] == "traffic_bytes_per_launch:" and f[1] == kernel:
             val = float(f[2])
+        if len(f) == 3 and f[0] == "counted_tuning:":
+            tuning[f[1]] = int(f[2])
+    if plan is not None and any(int(plan.get(k, -1)) != v for k, v in tuning.items()):
+        return None
     return val if sha == sources_sha() else None
 
 
@@ -230,7 +236,7 @@ def big_workload_leg(args, dev, timed, timed_median):
            "dominant_kernel": dom, "kernels": kern,
            "dominant_frac": (ITERATIONS_PER_LAUNCH.get(dom, 0) * bit /
                              (kern[dom]["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS),
-           "dominant_traffic": committed_traffic(dom, TRAFFIC_FILE_CFG4),
+           "dominant_traffic": committed_traffic(dom, TRAFFIC_FILE_CFG4, tuned),
            "dominant_model_bytes": ITERATIONS_PER_LAUNCH.get(dom, 0) * bit}
     log(f"spheres20000_512: {N} markers, C {C}, loop {ms:.3f} ms, frac {res['loop_frac']:.3f}")
     # the collision force of Eq. (DKT_model) on the clumped spheres (bin search)
@@ -455,7 +461,7 @@ def run():
     bmodel = loop_bytes(4, N, C, ns)
     roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                "traffic": committed_traffic(dom), "bytes_per_launch": nb,
+                "traffic": committed_traffic(dom, plan=plan.query()), "bytes_per_launch": nb,
                 "iterations_per_launch": ITERATIONS_PER_LAUNCH.get(dom),
                 "avg_launch_us": kern[dom]["avg_us"],
                 "impl_bytes_per_launch": kern[dom].get("impl_bytes"),

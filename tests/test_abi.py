@@ -110,3 +110,27 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_bench_reports_counted_traffic_only_for_the_counted_variants(tmp_path):
+    """bench.py takes the dominant kernel's HBM traffic from a committed
+    counter summary only while the kernel sources hash as when it was taken
+    and the plan runs the kernel variants that were counted."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    summary = tmp_path / path
+    summary.write_text("traffic_bytes_per_launch: spread 1000\n"
+                       f"counted_tuning: row_masks 1\ncounted_tuning: interp_tile 8\n"
+                       f"sources_sha256_16: {bench.sources_sha()}\n")
+    path = str(summary)                  # absolute: joined to nothing
+    assert bench.committed_traffic("spread", path) == 1000.0
+    assert bench.committed_traffic("spread", path, {"row_masks": 1, "interp_tile": 8}) \
+        == 1000.0
+    assert bench.committed_traffic("spread", path, {"row_masks": 0, "interp_tile": 8}) \
+        is None
+    assert bench.committed_traffic("spread", path, {"row_masks": 1, "interp_tile": 16}) \
+        is None
+    assert bench.committed_traffic("interp_g", path) is None
+    summary.write_text("traffic_bytes_per_launch: spread 1000\nsources_sha256_16: 0123456789abcdef\n")
+    assert bench.committed_traffic("spread", path) is None
