@@ -119,7 +119,7 @@ def test_bench_reports_counted_traffic_only_for_the_counted_variants(tmp_path):
     import sys
     sys.path.insert(0, ROOT)
     import bench
-    summary = tmp_path / path
+    summary = tmp_path / "summary.txt"
     summary.write_text("traffic_bytes_per_launch: spread 1000\n"
                        f"counted_tuning: row_masks 1\ncounted_tuning: interp_tile 8\n"
                        f"sources_sha256_16: {bench.sources_sha()}\n")
