@@ -105,24 +105,26 @@ def sources_sha():
 
 def committed_traffic(kernel, fname=TRAFFIC_FILE, plan=None):
     """HBM bytes per launch of `kernel` from a committed counter summary
-    (FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration), or None if
-    the summary is absent, the kernel sources changed since it was taken, or
-    `plan` (a plan's query) runs other kernel variants (row masks, work tile)
-    than the counted run."""
+    (FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration), taken for
+    each tuning variant (row masks, work tile): the line of the variant that
+    `plan` (a plan's query) runs, else the first line of the kernel.  None if
+    the summary is absent, holds no such line, or the kernel sources changed
+    since it was taken."""
     path = os.path.join(ROOT, fname)
     if not os.path.exists(path):
         return None
-    sha, val, tuning = None, None, {}
+    sha, val = None, None
     for ln in open(path):
         f = ln.split()
         if len(f) == 2 and f[0] == "sources_sha256_16:":
             sha = f[1]
-        if len(f) == 3 and f[0] == "traffic_bytes_per_launch:" and f[1] == kernel:
-            val = float(f[2])
-        if len(f) == 3 and f[0] == "counted_tuning:":
-            tuning[f[1]] = int(f[2])
-    if plan is not None and any(int(plan.get(k, -1)) != v for k, v in tuning.items()):
-        return None
+        if len(f) >= 3 and f[0] == "traffic_bytes_per_launch:" and f[1] == kernel:
+            tuning = dict(kv.split("=") for kv in f[3:])
+            if plan is not None and any(int(plan.get(k, -1)) != int(v)
+                                        for k, v in tuning.items()):
+                continue
+            if val is None:
+                val = float(f[2])
     return val if sha == sources_sha() else None
 
 

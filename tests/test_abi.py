@@ -114,23 +114,22 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_bench_reports_counted_traffic_only_for_the_counted_variants(tmp_path):
     """bench.py takes the dominant kernel's HBM traffic from a committed
-    counter summary only while the kernel sources hash as when it was taken
-    and the plan runs the kernel variants that were counted."""
+    counter summary (one line per counted tuning variant) only while the
+    kernel sources hash as when it was taken, and only the line of the
+    variant its plan runs."""
     import sys
     sys.path.insert(0, ROOT)
     import bench
     summary = tmp_path / "summary.txt"
-    summary.write_text("traffic_bytes_per_launch: spread 1000\n"
-                       f"counted_tuning: row_masks 1\ncounted_tuning: interp_tile 8\n"
-                       f"sources_sha256_16: {bench.sources_sha()}\n")
     path = str(summary)                  # absolute: joined to nothing
+    summary.write_text("traffic_bytes_per_launch: spread 1000 row_masks=0 interp_tile=8\n"
+                       "traffic_bytes_per_launch: spread 900 row_masks=1 interp_tile=8\n"
+                       "traffic_bytes_per_launch: spread 1100 row_masks=0 interp_tile=16\n"
+                       f"sources_sha256_16: {bench.sources_sha()}\n")
     assert bench.committed_traffic("spread", path) == 1000.0
-    assert bench.committed_traffic("spread", path, {"row_masks": 1, "interp_tile": 8}) \
-        == 1000.0
-    assert bench.committed_traffic("spread", path, {"row_masks": 0, "interp_tile": 8}) \
-        is None
-    assert bench.committed_traffic("spread", path, {"row_masks": 1, "interp_tile": 16}) \
-        is None
+    assert bench.committed_traffic("spread", path, {"row_masks": 1, "interp_tile": 8}) == 900.0
+    assert bench.committed_traffic("spread", path, {"row_masks": 0, "interp_tile": 16}) == 1100.0
+    assert bench.committed_traffic("spread", path, {"row_masks": 1, "interp_tile": 16}) is None
     assert bench.committed_traffic("interp_g", path) is None
     summary.write_text("traffic_bytes_per_launch: spread 1000\nsources_sha256_16: 0123456789abcdef\n")
     assert bench.committed_traffic("spread", path) is None
