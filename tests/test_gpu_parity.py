@@ -255,6 +255,24 @@ def test_multidirect_matches_oracle(dev, name, mk, dtype, path):
     assert np.all(np.abs(r.cpu().numpy() - ref["resid"]) <= bound)
 
 
+@pytest.mark.parametrize("name,mk", _bucket_extra()[:2], ids=[c[0] for c in _bucket_extra()[:2]])
+@pytest.mark.parametrize("dtype,path", PATHS, ids=[f"{d}-{'plain' if p == 1 else 'batched'}" for d, p in PATHS])
+def test_bounded_axes_match_oracle(dev, name, mk, dtype, path):
+    """Walls on x and z (y periodic), particles a few cells from them: tiles
+    beyond a wall have no neighbour (their halo reads zero) in every kernel."""
+    import oracle as O
+    announce(f"bounded axes {name} {dtype} path={path}")
+    wl = mk()
+    c = Case(wl, dev)
+    ref = O.multidirect(c.g, wl.delta, wl.ns, wl.dt, c.m, wl.xc, wl.up, wl.om, wl.u0)
+    ustar, f, F, _, _, b = _run(c, dtype, path, resid=False)
+    assert int(b.flag[0].item()) == 0
+    tol = TOL64 if dtype == "f64" else TOL32
+    assert rel(F.cpu().numpy(), ref["F"]) <= tol
+    assert c.field_rel(f, ref["f"]) <= tol
+    assert c.field_rel(ustar, ref["ustar"]) <= tol
+
+
 @pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_row_masks_match_oracle_and_unmasked(dev, name, mk, dtype):
