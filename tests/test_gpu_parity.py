@@ -34,6 +34,18 @@ def _cases():
 CASES = _cases()
 
 
+def _odd_tiles():
+    """A 40^3 grid of 8^3 boxes: five tiles per axis, so with 16-wide
+    interpolation work tiles the last tile of every row is an item on its
+    own; one sphere reaches into those tiles across the periodic seam."""
+    h = 1.0 / 40
+    return [("odd_tiles40_P4",
+             lambda: W.make_workload("odd40", 40, 8, 2, 4, 3, np.array([9.0, 7.5]),
+                                     centres=[[37.3 * h, 20.4 * h, 11.8 * h],
+                                              [14.6 * h, 9.9 * h, 30.2 * h]],
+                                     nmodes=8, K=4, cover_all=True))]
+
+
 @pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
 def test_build_markers(dev, name, mk):
     import torch
@@ -307,7 +319,7 @@ def test_row_masks_match_oracle_and_unmasked(dev, name, mk, dtype):
     assert torch.equal(ip[2], a[2])
 
 
-@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("name,mk", CASES + _odd_tiles(), ids=[c[0] for c in CASES + _odd_tiles()])
 @pytest.mark.parametrize("masks", [False, True], ids=["", "masks"])
 def test_interp_tile_16_matches_oracle_and_8(dev, name, mk, masks):
     """FP32 loop with interpolation work tiles of two x neighbours (16 x 8 x 8,
