@@ -251,8 +251,9 @@ int ib_multidirect_force(ib_plan* plan, const ib_level* lv, const ib_particles* 
  * chosen on the real inputs).  Times the loop of ib_multidirect_force for
  * every bucket_width in {64, 128, 256}, spread_wgs_per_cu in {4, 8, 16, 32},
  * row_masks in {0, 1} and (FP32) interp_tile in {8, 16}, each as replays of
- * its captured graph (one warm-up, then the faster of two samples of 3
- * replays; the capture runs on a stream the call creates and destroys) and
+ * its captured graph, in place on ustar after a copy of u0 (one warm-up, then
+ * the faster of two samples of 3 replays; the capture runs on a stream the
+ * call creates and destroys) and
  * keeps the fastest in the plan (see ib_plan_query); the row masks and the
  * 16-wide work tile are kept only when they win by more than 1%.  The
  * tile stays 8^3: one 64-wide wavefront holds the 64 rows of a tile.

@@ -118,7 +118,6 @@ static BatchedCfg cfg_of(const ib_plan* pl)
     c.wgs_s = pl->spread_wgs_per_cu;
     c.masks = pl->row_masks;
     c.txw = pl->interp_tile;
-    c.partial = 0;
     c.prof = pl->prof;
     return c;
 }
@@ -478,10 +477,18 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
     // around the short list kernels and favour candidates with fewer of
     // them.  The capture runs on a stream of the library's own (the caller's
     // may be the null stream, which cannot be captured); the replays run on
-    // the caller's stream.
+    // the caller's stream.  The timed loops run in place on ustar, which
+    // first receives a copy of u0: u0 stays intact, and the finalize moves
+    // the bytes of an in-place run (each replay drifts ustar by dt G, which
+    // leaves the cells with force, and so the traffic, unchanged).
     hipStream_t cs = nullptr;
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ustar, u0,
+                           (size_t)g.nbox * (size_t)g.bstride *
+                               (plan->prec == IB_F32 ? sizeof(float) : sizeof(double)),
+                           hipMemcpyDeviceToDevice, st);
     const int32_t keep_bw = plan->bucket_width, keep_wgs = plan->spread_wgs_per_cu,
                   keep_masks = plan->row_masks, keep_tile = plan->interp_tile;
     float best = -1.f;
@@ -497,14 +504,13 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
             plan->spread_wgs_per_cu = wgs[j];
             plan->row_masks = mk;
             plan->interp_tile = tl ? 16 : 8;
-            BatchedCfg cfg = cfg_of(plan);
-            cfg.partial = 1;     // the traffic of an in-place run, u0 left untouched
+            const BatchedCfg cfg = cfg_of(plan);
             hipGraph_t gr = nullptr;
             hipGraphExec_t ex = nullptr;
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                rc = batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, u0, ustar,
-                                         f, F, nullptr, nullptr, ws, ws_bytes, cs);
+                rc = batched_multidirect(g, plan->P, plan->prec, cfg, p, m, b, ns, dt, ustar,
+                                         ustar, f, F, nullptr, nullptr, ws, ws_bytes, cs);
                 e = hipStreamEndCapture(cs, &gr);
             }
             if (e == hipSuccess && rc == IB_OK)
@@ -569,8 +575,8 @@ extern "C" int ib_plan_autotune(ib_plan* plan, const ib_level* lv, const ib_part
     plan->spread_wgs_per_cu = best_wgs;
     plan->row_masks = best_masks;
     plan->interp_tile = best_tile;
-    // the timed runs left the cells of ustar without force as they were: one
-    // complete run with the chosen tuning writes the whole result
+    // the timed runs drifted ustar: one run from u0 with the chosen tuning
+    // writes the result
     rc = batched_multidirect(g, plan->P, plan->prec, cfg_of(plan), p, m, b, ns, dt, u0, ustar, f,
                              F, nullptr, nullptr, ws, ws_bytes, st);
     if (rc != IB_OK)

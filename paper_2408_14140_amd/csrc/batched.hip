@@ -516,8 +516,7 @@ int resident_grid(int ncu, int cap)
 // read and rewritten (u0 + dt 0 = u0): inside the tiles that have a force
 // slot, most cells lie outside every stencil.  With f_acc, f += G^ns instead,
 // on the same cells.  ustar may be null (f only).  A separate ustar takes u0
-// on the cells without force when copy is set (always, except in the timing
-// runs of the autotuner, which leave those cells as they were).
+// on the cells without force (copy).
 template <typename T, bool F_ACC, bool MASK>
 __global__ void __launch_bounds__(256)
 k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G,
@@ -671,9 +670,9 @@ static void finalize_kernel(bool pairs, unsigned grid, unsigned gp, hipStream_t 
 template <typename T>
 static void launch_finalize(unsigned grid, hipStream_t st, const Grid& g, const int32_t* slot,
                             const T* G, const uint64_t* tilemask, const T* u0, T* ustar, T* f,
-                            double dt, int use_g, int f_acc, int masks, int partial = 0)
+                            double dt, int use_g, int f_acc, int masks)
 {
-    const int copy = ustar && ustar != u0 && !partial;
+    const int copy = ustar && ustar != u0;
     // pairs of cells: rows start on even elements when ngrow is even, and the
     // pair loads and stores need the fields aligned to two elements
     const uintptr_t am = 2 * sizeof(T) - 1;
@@ -1025,8 +1024,7 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     launch_spread<T, P>(cfg, st, g, w, b, 1);
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_FILL);
-    launch_finalize<T>(gfin, st, g, w.slot, w.G, w.tmask, u0, ustar, f, dt, 1, f_acc, cfg.masks,
-                       cfg.partial);
+    launch_finalize<T>(gfin, st, g, w.slot, w.G, w.tmask, u0, ustar, f, dt, 1, f_acc, cfg.masks);
     IBX_PROF_END();
     if (resid) {
         IBX_PROF_BEGIN(PK_RESID);

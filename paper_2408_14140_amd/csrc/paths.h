@@ -30,8 +30,6 @@ struct BatchedCfg {
     int wgs_s;     // cap on resident spreading workgroups per CU (0 = as many as fit)
     int masks;     // G slot row masks: zero rows neither stored nor loaded
     int txw;       // x extent of an interpolation work tile: 8 (one tile) or 16 (FP32)
-    int partial;   // timing runs only: a separate ustar receives u0 + dt G only where G is
-                   // not zero, as an in-place run writes it; its other cells keep what they held
     Profiler* prof;  // nullable: per-kernel event timing
 };
 
