@@ -969,14 +969,12 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
                        size_t ws_bytes, hipStream_t st, int f_acc)
 {
     const int64_t nl = m->nl;
-    const int64_t T_ = g.ntiles;
     size_t need = 0;
     carve_batched<T>(g, nl, cfg.bw, nullptr, 0, &need);
     if (!ws || ws_bytes < need)
         return IB_EWORKSPACE;
     BatchedWs<T> w = carve_batched<T>(g, nl, cfg.bw, ws, ws_bytes, &need);
     const unsigned gm = (unsigned)((nl + 255) / 256 > 0 ? (nl + 255) / 256 : 1);
-    const unsigned gt = (unsigned)((T_ + 255) / 256);
     const int64_t nfin = (int64_t)g.nbox * (g.box / TILE) * g.box;
     const unsigned gfin = (unsigned)(nfin < 65535 ? (nfin > 0 ? nfin : 1) : 65535);
     if (nl == 0) {

@@ -139,7 +139,7 @@ k_volume_partials(Grid g, const double* __restrict__ xc, const double* __restric
     // the product's error (a few units in 2^-52 relative) stays far below the
     // bias, and the bias below the 1/b gap to the next integer
     auto qdiv = [](int a, double rb) { return (int)((double)a * rb + 1e-6); };
-    const double r_ne0 = 1.0 / ne[0], r_ne1 = 1.0 / ne[1], r_box = 1.0 / g.box;
+    const double r_ne0 = 1.0 / ne[0], r_box = 1.0 / g.box;
     // this slab's cells: planes kk = slab + RD_SLABS * m
     const int nplanes = ne[2] > slab ? (ne[2] - slab + RD_SLABS - 1) / RD_SLABS : 0;
     const int plane = ne[0] * ne[1];
