@@ -545,8 +545,14 @@ __global__ void k_bucket_keys(Grid g, int64_t nl, const double* __restrict__ x,
         // two tiles, those of these two cells
         int q0, q1;
         if (g.periodic[a]) {
-            c[a] = wrapi(fl, g.n[a]);
-            q0 = wrapi(b[a], g.n[a]);
+            // markers sit at most a period outside: one add or subtract, else
+            // the modulo
+            c[a] = fl < 0 ? fl + g.n[a] : fl >= g.n[a] ? fl - g.n[a] : fl;
+            if ((unsigned)c[a] >= (unsigned)g.n[a])
+                c[a] = wrapi(fl, g.n[a]);
+            q0 = b[a] < 0 ? b[a] + g.n[a] : b[a] >= g.n[a] ? b[a] - g.n[a] : b[a];
+            if ((unsigned)q0 >= (unsigned)g.n[a])
+                q0 = wrapi(b[a], g.n[a]);
             q1 = q0 + P - 1;
             if (q1 >= g.n[a])
                 q1 -= g.n[a];
