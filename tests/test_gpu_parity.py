@@ -267,13 +267,26 @@ def test_multidirect_matches_oracle(dev, name, mk, dtype, path):
     assert np.all(np.abs(r.cpu().numpy() - ref["resid"]) <= bound)
 
 
-@pytest.mark.parametrize("name,mk", _bucket_extra()[:2], ids=[c[0] for c in _bucket_extra()[:2]])
+def _two_tiles_p3():
+    h16 = 1.0 / 16
+    return W.make_workload("two16_P3", 16, 16, 2, 3, 2, np.full(2, 5.0),
+                           centres=[[3.6 * h16, 12.2 * h16, 7.7 * h16],
+                                    [12.1 * h16, 4.4 * h16, 15.2 * h16]],
+                           nmodes=8, K=4, cover_all=True)
+
+
+_SMALL_GRIDS = _bucket_extra() + [("two_tiles16_P3", _two_tiles_p3)]
+
+
+@pytest.mark.parametrize("name,mk", _SMALL_GRIDS, ids=[c[0] for c in _SMALL_GRIDS])
 @pytest.mark.parametrize("dtype,path", PATHS, ids=[f"{d}-{'plain' if p == 1 else 'batched'}" for d, p in PATHS])
-def test_bounded_axes_match_oracle(dev, name, mk, dtype, path):
+def test_bounded_and_small_grids_match_oracle(dev, name, mk, dtype, path):
     """Walls on x and z (y periodic), particles a few cells from them: tiles
-    beyond a wall have no neighbour (their halo reads zero) in every kernel."""
+    beyond a wall have no neighbour (their halo reads zero) in every kernel;
+    and a 16^3 grid of two tiles per axis (source lists built by sorting,
+    both neighbours of a tile the same tile across the periodic seam)."""
     import oracle as O
-    announce(f"bounded axes {name} {dtype} path={path}")
+    announce(f"bounded or small grid {name} {dtype} path={path}")
     wl = mk()
     c = Case(wl, dev)
     ref = O.multidirect(c.g, wl.delta, wl.ns, wl.dt, c.m, wl.xc, wl.up, wl.om, wl.u0)
