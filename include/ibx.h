@@ -195,15 +195,16 @@ int ib_spread(const ib_level* lv, const ib_markers* m, const ib_buckets* b, ib_d
 /* already being captured the launches go into the caller's graph instead.  */
 /* row_masks (batched path): the spreading records which rows of each tile's */
 /* G slot are not all zeros and stores only those, and the interpolation    */
-/* and the finalize step load only those; it pays when the slots do not fit */
-/* in the caches (on the 20000-sphere 512^3 workload, not on 1000 spheres   */
-/* at 256^3).  Results are the same either way (a row of zeros reads back  */
-/* as +0).  interp_tile (batched path): x extent of the interpolation work  */
-/* tiles, 8 (one 8^3 tile; 0 = 8) or 16 (two x neighbours, whose markers    */
-/* share one staged halo: 20 x 12 x 12 cells instead of two 12^3; FP32      */
-/* plans only, else IB_EUNSUPPORTED).  Spreading, bucketing and the G slots */
-/* stay on 8^3 tiles; results agree to rounding (an item's marker count    */
-/* decides over how many lanes each marker's stencil sum is split).         */
+/* and the finalize step load only those: less traffic (about a fifth on   */
+/* 1000 spheres at 256^3) for a mask test per row, which may or may not pay */
+/* (ib_plan_autotune measures it).  Results are the same either way (a row */
+/* of zeros reads back as +0).  interp_tile (batched path): x extent of the */
+/* interpolation work tiles, 8 (one 8^3 tile; 0 = 8) or 16 (two x          */
+/* neighbours, whose markers share one staged halo: 20 x 12 x 12 cells     */
+/* instead of two 12^3; FP32 plans only, else IB_EUNSUPPORTED).  Spreading, */
+/* bucketing and the G slots stay on 8^3 tiles; results agree to rounding  */
+/* (an item's marker count decides over how many lanes each marker's       */
+/* stencil sum is split).                                                   */
 /* ib_plan_autotune, ib_plan_profile_read, ib_particle_levels and           */
 /* ib_multidirect_sequential synchronize and must not be captured; every    */
 /* other call only enqueues work on its stream and may be.                  */
