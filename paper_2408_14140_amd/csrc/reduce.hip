@@ -118,13 +118,17 @@ k_volume_partials(Grid g, const double* __restrict__ xc, const double* __restric
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double R = 0.5 * d[p];
     const double h = g.h, h3 = h * h * h;
+    // Only a cell with a node inside the sphere has alpha != 0, and such a
+    // node n satisfies |n - s| < e along every axis (s = centre, e = R, in
+    // cells), so the cells floor(s - e) .. floor(s + e) hold all of them; the
+    // 1e-6 cell margin is far above the rounding of s, e and phi.
     int i0[3], ne[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double s = __ddiv_rn(__dsub_rn(c[a], g.lo[a]), h);
         const double e = R / h;
-        i0[a] = (int)floor(s - e) - 1;
-        ne[a] = ((int)floor(s + e) + 1) - i0[a] + 1;
+        i0[a] = (int)floor(s - e - 1e-6);
+        ne[a] = (int)floor(s + e + 1e-6) - i0[a] + 1;
     }
     const double invR = 1.0 / R;
     // A cell whose centre lies farther than half its diagonal (plus a margin
