@@ -552,8 +552,22 @@ def _big_spheres():
                            centres=xc, nmodes=8, K=4, cover_all=True)
 
 
-@pytest.mark.parametrize("name,mk", CASES + [("big_spheres96", _big_spheres)],
-                         ids=[c[0] for c in CASES] + ["big_spheres96"])
+def _exact_edges():
+    """Spheres whose extents end exactly on nodes: centred on a node (one at a
+    box corner, one on node 0, wrapping x and z) with R = 8 h, and centred in a
+    cell with R = 7.5 h, so s - e and s + e are integers and the surface passes
+    through nodes (phi = 0 there), the edge of the cells the volume sums visit."""
+    h = 1.0 / 64
+    xc = np.array([[32 * h, 32 * h, 32 * h], [0.0, 16 * h, 63 * h],
+                   [20.5 * h, 50.5 * h, 10.5 * h]])
+    return W.make_workload("exact_edges64", 64, 32, 2, 4, 2, np.array([16.0, 16.0, 15.0]),
+                           centres=xc, nmodes=8, K=4, cover_all=True)
+
+
+RED_CASES = CASES + [("big_spheres96", _big_spheres), ("exact_edges64", _exact_edges)]
+
+
+@pytest.mark.parametrize("name,mk", RED_CASES, ids=[c[0] for c in RED_CASES])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_particle_reductions(dev, name, mk, dtype):
     import torch
