@@ -133,15 +133,15 @@ int ib_desired_velocity(const ib_particles* p, const ib_markers* m, ib_prec prec
                         void* stream);
 
 /* ---------------------------------------------------------------------- */
-/* a2  Bucketing.  Owning cell c = floor(s) per axis, tile = c / 8;        */
-/* stable counting sort of markers by tile (histogram, scan, scatter); for */
-/* every tile the ascending list of sorted positions whose stencil cells   */
-/* touch it.  Not in the paper, which treats one particle at a time        */
-/* (Sec. 3.1); integer outputs are deterministic.  flag[0] counts markers   */
-/* whose stencil leaves the covered boxes or a bounded axis, flag[1] is set */
-/* when src_idx overflows src_cap; ib_spread, ib_multidirect_force,        */
-/* ib_plan_autotune and ib_multidirect_backward called with such a set      */
-/* write NaN into every output.                                            */
+/* a2  Bucketing.  Owning cell c = floor(s) per axis, tile = c / 8; stable */
+/* LSD radix sort of markers by tile (per 8-bit digit: histogram, scan,    */
+/* scatter); for every tile the ascending list of sorted positions whose   */
+/* stencil cells touch it.  Not in the paper, which treats one particle at */
+/* a time (Sec. 3.1); integer outputs are deterministic.  flag[0] counts   */
+/* markers whose stencil leaves the covered boxes or a bounded axis,       */
+/* flag[1] is set when src_idx overflows src_cap; ib_spread,               */
+/* ib_multidirect_force, ib_plan_autotune and ib_multidirect_backward      */
+/* called with such a set write NaN into every output.                     */
 /* ---------------------------------------------------------------------- */
 
 /* Device workspace of ib_bucket in bytes: grows with nl and with the level's
