@@ -181,15 +181,15 @@ __device__ inline int64_t tile_base(const Grid& g, const int* lo)
 
 // ------------------------------------------------------------------ prep
 
+// Record and U^d of the marker at sorted position i.
 template <typename T, int P>
-__global__ void __launch_bounds__(256)
-k_prep(Grid g, int64_t nl, const double* __restrict__ x, const double* __restrict__ y,
-       const double* __restrict__ z, const int32_t* __restrict__ pid,
-       const double* __restrict__ dv, const int32_t* __restrict__ perm,
-       const double* __restrict__ xc, const double* __restrict__ up,
-       const double* __restrict__ om, MarkerData<T> s)
+__device__ inline void prep_marker(int64_t i, const Grid& g, int64_t nl,
+                                   const double* __restrict__ x, const double* __restrict__ y,
+                                   const double* __restrict__ z, const int32_t* __restrict__ pid,
+                                   const double* __restrict__ dv, const int32_t* __restrict__ perm,
+                                   const double* __restrict__ xc, const double* __restrict__ up,
+                                   const double* __restrict__ om, const MarkerData<T>& s)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nl)
         return;
     const int64_t l = perm[i];
@@ -267,17 +267,18 @@ __device__ inline int item_markers(const int32_t* __restrict__ tile_offs, int64_
     return (tx + 1 < nt0 ? tile_offs[t + 2] : tile_offs[t + 1]) - s;
 }
 
-// (block 0 also clears the cost histogram that k_cost_hist fills next)
+// Block blk of 256 threads (block 0 also clears the cost histogram that
+// k_cost_hist fills next).
 template <bool PAIR>
-__global__ void k_tile_counts(int64_t T, int bw, int nt0,
-                              const int32_t* __restrict__ tile_offs,
-                              const int32_t* __restrict__ src_offs, int32_t* item_cnt,
-                              int32_t* act, int32_t* __restrict__ hist)
+__device__ inline void tile_counts_block(unsigned blk, int64_t T, int bw, int nt0,
+                                         const int32_t* __restrict__ tile_offs,
+                                         const int32_t* __restrict__ src_offs, int32_t* item_cnt,
+                                         int32_t* act, int32_t* __restrict__ hist)
 {
-    if (blockIdx.x == 0)
-        for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
+    if (blk == 0)
+        for (int b = threadIdx.x; b < NXCD * COST_BINS; b += 256)
             hist[b] = 0;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blk * 256 + threadIdx.x;
     if (t >= T)
         return;
     int start;
@@ -309,24 +310,25 @@ k_cost_hist(int64_t T, const int32_t* __restrict__ src_offs, const int32_t* __re
 }
 
 // The two work-list scans for grids of at most SCAN_FUSE / 2 scan tiles, in
-// two launches.  Pass 1: workgroup b < nb scans the interpolation item counts
-// ceil(markers / bw) of scan tile b, workgroup nb + b the flags "source list
-// not empty" (the inputs are formed from the offsets on the fly); workgroup 0
-// also clears the cost histogram.
+// two passes.  Pass 1 (blocks of SCAN_THREADS threads): block id = b < nb
+// scans the interpolation item counts ceil(markers / bw) of scan tile b,
+// block nb + b the flags "source list not empty" (the inputs are formed from
+// the offsets on the fly); block 0 also clears the cost histogram.
 template <bool PAIR>
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_list_scan(int64_t T, int bw, int nt0, const int32_t* __restrict__ tile_offs,
-            const int32_t* __restrict__ src_offs, int32_t* __restrict__ item_offs,
-            int32_t* __restrict__ act_offs, int32_t* __restrict__ sums,
-            int32_t* __restrict__ hist)
+__device__ inline void list_scan_block(unsigned id, int64_t T, int bw, int nt0,
+                                       const int32_t* __restrict__ tile_offs,
+                                       const int32_t* __restrict__ src_offs,
+                                       int32_t* __restrict__ item_offs,
+                                       int32_t* __restrict__ act_offs, int32_t* __restrict__ sums,
+                                       int32_t* __restrict__ hist)
 {
     __shared__ int32_t ts[SCAN_THREADS];
-    if (blockIdx.x == 0)
-        for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
+    if (id == 0)
+        for (int b = threadIdx.x; b < NXCD * COST_BINS; b += SCAN_THREADS)
             hist[b] = 0;
     const int64_t nb = (T + SCAN_TILE - 1) / SCAN_TILE;
-    const bool second = blockIdx.x >= nb;
-    const int64_t blk = second ? blockIdx.x - nb : blockIdx.x;
+    const bool second = id >= nb;
+    const int64_t blk = second ? id - nb : id;
     int32_t* out = second ? act_offs : item_offs;
     const int t = threadIdx.x;
     const int64_t base = blk * SCAN_TILE + (int64_t)t * SCAN_ITEMS;
@@ -359,7 +361,7 @@ k_list_scan(int64_t T, int bw, int nt0, const int32_t* __restrict__ tile_offs,
         run += v[k];
     }
     if (t == SCAN_THREADS - 1)
-        sums[blockIdx.x] = ts[t];
+        sums[id] = ts[t];
 }
 
 // Pass 2: each workgroup adds the totals of the scan tiles before its own
@@ -411,6 +413,35 @@ k_list_add(int64_t T, const int32_t* __restrict__ src_offs, int32_t* __restrict_
     for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
         if (lh[b])
             atomicAdd(&hist[b], lh[b]);
+}
+
+// The marker records and the first work-list pass, which are independent,
+// in one launch of 256-thread blocks: blocks below nlist run the list pass
+// (SCAN: the fused list scan over 2 nb blocks; else the tile counts), the
+// others form the records, one thread per marker in bucket order.
+template <typename T, int P, bool PAIR, bool SCAN>
+__global__ void __launch_bounds__(256)
+k_prep_lists(unsigned nlist, Grid g, int64_t nl, const double* __restrict__ x,
+             const double* __restrict__ y, const double* __restrict__ z,
+             const int32_t* __restrict__ pid, const double* __restrict__ dv,
+             const int32_t* __restrict__ perm, const double* __restrict__ xc,
+             const double* __restrict__ up, const double* __restrict__ om, MarkerData<T> s,
+             int bw, const int32_t* __restrict__ tile_offs, const int32_t* __restrict__ src_offs,
+             int32_t* __restrict__ out_items, int32_t* __restrict__ out_act,
+             int32_t* __restrict__ sums, int32_t* __restrict__ hist)
+{
+    static_assert(SCAN_THREADS == 256, "one block size for both parts");
+    if (blockIdx.x >= nlist) {
+        prep_marker<T, P>((int64_t)(blockIdx.x - nlist) * 256 + threadIdx.x, g, nl, x, y, z,
+                          pid, dv, perm, xc, up, om, s);
+        return;
+    }
+    if constexpr (SCAN)
+        list_scan_block<PAIR>(blockIdx.x, g.ntiles, bw, g.nt[0], tile_offs, src_offs, out_items,
+                              out_act, sums, hist);
+    else
+        tile_counts_block<PAIR>(blockIdx.x, g.ntiles, bw, g.nt[0], tile_offs, src_offs,
+                                out_items, out_act, hist);
 }
 
 // cur[x][b] = first position of slab x plus its tiles in bins above b.
@@ -892,6 +923,14 @@ static void launch_spread(const BatchedCfg& cfg, hipStream_t st, const Grid& g,
 // Work lists of the interpolation items (work tiles of one tile, or with
 // PAIR of two x neighbours) and of the active tiles, and each item's
 // neighbour offsets.
+// The list pass that k_prep_lists runs beside the records: the fused list
+// scan for grids of at most SCAN_FUSE / 2 scan tiles, else the tile counts.
+static bool fused_list_scan(const Grid& g)
+{
+    return 2 * ((g.ntiles + SCAN_TILE - 1) / SCAN_TILE) <= SCAN_FUSE;
+}
+
+// The rest of the work lists, after k_prep_lists.
 template <typename T, bool PAIR>
 static void build_lists(const Grid& g, const BatchedCfg& cfg, const ib_buckets* b,
                         BatchedWs<T>& w, hipStream_t st)
@@ -899,16 +938,11 @@ static void build_lists(const Grid& g, const BatchedCfg& cfg, const ib_buckets* 
     const int64_t T_ = g.ntiles;
     const unsigned gt = (unsigned)((T_ + 255) / 256);
     const int64_t nbl = (T_ + SCAN_TILE - 1) / SCAN_TILE;
-    if (2 * nbl <= SCAN_FUSE) {
+    if (fused_list_scan(g)) {
         int32_t* sums = (int32_t*)w.scan;
-        k_list_scan<PAIR><<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
-            T_, cfg.bw, g.nt[0], b->tile_offs, b->src_offs, w.item_offs, w.act_offs, sums,
-            w.hist);
         k_list_add<<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
             T_, b->src_offs, w.item_offs, w.act_offs, sums, w.nitems, w.nactive, w.hist);
     } else {
-        k_tile_counts<PAIR><<<gt, 256, 0, st>>>(T_, cfg.bw, g.nt[0], b->tile_offs, b->src_offs,
-                                                w.item_cnt, w.act, w.hist);
         scan_exclusive2(w.item_cnt, w.item_offs, w.act, w.act_offs, T_, w.nitems, w.nactive,
                         w.scan, st);
         k_cost_hist<<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.hist);
@@ -931,13 +965,30 @@ static void records_and_lists(const Grid& g, const BatchedCfg& cfg, const ib_par
                               hipStream_t st)
 {
     const int64_t nl = m->nl;
-    const unsigned gm = (unsigned)((nl + 255) / 256 > 0 ? (nl + 255) / 256 : 1);
+    const unsigned gm = (unsigned)((nl + 255) / 256);
+    const bool scan = fused_list_scan(g);
+    const unsigned nlist = (unsigned)(scan ? 2 * ((g.ntiles + SCAN_TILE - 1) / SCAN_TILE)
+                                           : (g.ntiles + 255) / 256);
+    int32_t* out_items = scan ? w.item_offs : w.item_cnt;
+    int32_t* out_act = scan ? w.act_offs : w.act;
+    const bool pair = pair_items<T>(cfg);
     IBX_PROF_BEGIN(PK_PREP);
-    k_prep<T, P><<<gm, 256, 0, st>>>(g, nl, m->x, m->y, m->z, m->pid, m->dv, b->perm, p->xc,
-                                     p->up, p->om, w.s);
+#define IBX_PREP_LISTS(PAIR, SCAN)                                                               \
+    k_prep_lists<T, P, PAIR, SCAN><<<nlist + gm, 256, 0, st>>>(                                  \
+        nlist, g, nl, m->x, m->y, m->z, m->pid, m->dv, b->perm, p->xc, p->up, p->om, w.s, cfg.bw, \
+        b->tile_offs, b->src_offs, out_items, out_act, (int32_t*)w.scan, w.hist)
+    if (pair && scan)
+        IBX_PREP_LISTS(true, true);
+    else if (pair)
+        IBX_PREP_LISTS(true, false);
+    else if (scan)
+        IBX_PREP_LISTS(false, true);
+    else
+        IBX_PREP_LISTS(false, false);
+#undef IBX_PREP_LISTS
     IBX_PROF_END();
     IBX_PROF_BEGIN(PK_LISTS);
-    if (pair_items<T>(cfg))
+    if (pair)
         build_lists<T, true>(g, cfg, b, w, st);
     else
         build_lists<T, false>(g, cfg, b, w, st);
