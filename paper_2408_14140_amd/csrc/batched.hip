@@ -537,6 +537,33 @@ int resident_grid(int ncu, int cap)
 
 // ------------------------------------------------------------------ fill
 
+// NaN in ustar and f (either nullable) on every valid cell of the covered
+// boxes and in Fp[0 .. nF): the finalize's outputs when the bucket set is
+// flagged (an error path, so a plain grid-stride loop).
+template <typename T>
+__device__ void finalize_poison(const Grid& g, T* ustar, T* f, T* Fp, int64_t nF)
+{
+    const T nan = (T)__builtin_nan("");
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_box = (int64_t)g.box * g.box * g.box;
+    for (int64_t q = t0; (ustar || f) && q < per_box * g.nbox; q += stride) {
+        const int64_t bid = q / per_box, r = q - bid * per_box;
+        const int lx = (int)(r % g.box) + g.ngrow;
+        const int ly = (int)((r / g.box) % g.box) + g.ngrow;
+        const int lz = (int)(r / ((int64_t)g.box * g.box)) + g.ngrow;
+        const int64_t off = bid * g.bstride + ((int64_t)lz * g.ext + ly) * g.ext + lx;
+        for (int c = 0; c < 3; ++c) {
+            if (ustar)
+                ustar[off + c * g.cstride] = nan;
+            if (f)
+                f[off + c * g.cstride] = nan;
+        }
+    }
+    for (int64_t i = t0; Fp && i < nF; i += stride)
+        Fp[i] = nan;
+}
+
 // Last step of Algorithm 1 on every valid cell of the covered boxes:
 // f = G^ns and ustar = u0 + dt G^ns, with G = 0 on tiles no marker reaches
 // (and everywhere when use_g is 0) and on the slot rows whose bit in the
@@ -547,13 +574,20 @@ int resident_grid(int ncu, int cap)
 // read and rewritten (u0 + dt 0 = u0): inside the tiles that have a force
 // slot, most cells lie outside every stencil.  With f_acc, f += G^ns instead,
 // on the same cells.  ustar may be null (f only).  A separate ustar takes u0
-// on the cells without force (copy).
+// on the cells without force (copy).  With flag (nullable) raised (a flagged
+// bucket set), f and ustar are NaN on every such cell instead, and so is
+// Fp[0 .. nF) (the marker forces, written before this kernel).
 template <typename T, bool F_ACC, bool MASK>
 __global__ void __launch_bounds__(256)
 k_finalize(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G,
            const uint64_t* __restrict__ tilemask, const T* u0, T* ustar, T* __restrict__ f,
-           double dt, int use_g, int copy)
+           double dt, int use_g, int copy, const int32_t* __restrict__ flag, T* __restrict__ Fp,
+           int64_t nF)
 {
+    if (flag && (flag[0] | flag[1]) != 0) {
+        finalize_poison(g, ustar, f, Fp, nF);
+        return;
+    }
     __shared__ int tslot[64];                 // G slot of each tile along the row
     __shared__ uint64_t tmask[64];            // and its row mask
     const int B = g.box;
@@ -622,9 +656,14 @@ template <typename T, bool F_ACC, bool MASK>
 __global__ void __launch_bounds__(256)
 k_finalize_pairs(Grid g, const int32_t* __restrict__ slot, const T* __restrict__ G,
                  const uint64_t* __restrict__ tilemask, const T* u0, T* ustar, T* __restrict__ f,
-                 double dt, int use_g, int copy)
+                 double dt, int use_g, int copy, const int32_t* __restrict__ flag,
+                 T* __restrict__ Fp, int64_t nF)
 {
     using V2 = typename Pair<T>::type;
+    if (flag && (flag[0] | flag[1]) != 0) {
+        finalize_poison(g, ustar, f, Fp, nF);
+        return;
+    }
     __shared__ int tslot[64];                 // G slot of each tile along the row
     __shared__ uint64_t tmask[64];            // and its row mask
     const int B = g.box;
@@ -688,20 +727,24 @@ k_finalize_pairs(Grid g, const int32_t* __restrict__ slot, const T* __restrict__
 template <typename T, bool F_ACC, bool MASK>
 static void finalize_kernel(bool pairs, unsigned grid, unsigned gp, hipStream_t st, const Grid& g,
                             const int32_t* slot, const T* G, const uint64_t* tilemask,
-                            const T* u0, T* ustar, T* f, double dt, int use_g, int copy)
+                            const T* u0, T* ustar, T* f, double dt, int use_g, int copy,
+                            const int32_t* flag, T* Fp, int64_t nF)
 {
     if (pairs)
-        k_finalize_pairs<T, F_ACC, MASK>
-            <<<gp, 256, 0, st>>>(g, slot, G, tilemask, u0, ustar, f, dt, use_g, copy);
+        k_finalize_pairs<T, F_ACC, MASK><<<gp, 256, 0, st>>>(g, slot, G, tilemask, u0, ustar, f,
+                                                             dt, use_g, copy, flag, Fp, nF);
     else
-        k_finalize<T, F_ACC, MASK>
-            <<<grid, 256, 0, st>>>(g, slot, G, tilemask, u0, ustar, f, dt, use_g, copy);
+        k_finalize<T, F_ACC, MASK><<<grid, 256, 0, st>>>(g, slot, G, tilemask, u0, ustar, f, dt,
+                                                         use_g, copy, flag, Fp, nF);
 }
 
+// With flag, the kernel also stands in for the flag check of the outputs
+// (ustar, f and Fp[0 .. nF)).
 template <typename T>
 static void launch_finalize(unsigned grid, hipStream_t st, const Grid& g, const int32_t* slot,
                             const T* G, const uint64_t* tilemask, const T* u0, T* ustar, T* f,
-                            double dt, int use_g, int f_acc, int masks)
+                            double dt, int use_g, int f_acc, int masks,
+                            const int32_t* flag = nullptr, T* Fp = nullptr, int64_t nF = 0)
 {
     const int copy = ustar && ustar != u0;
     // pairs of cells: rows start on even elements when ngrow is even, and the
@@ -713,16 +756,16 @@ static void launch_finalize(unsigned grid, hipStream_t st, const Grid& g, const 
     const unsigned gp = (unsigned)(items < 65535 ? (items > 0 ? items : 1) : 65535);
     if (f_acc && masks)
         finalize_kernel<T, true, true>(pairs, grid, gp, st, g, slot, G, tilemask, u0, ustar, f,
-                                       dt, use_g, copy);
+                                       dt, use_g, copy, flag, Fp, nF);
     else if (f_acc)
         finalize_kernel<T, true, false>(pairs, grid, gp, st, g, slot, G, tilemask, u0, ustar, f,
-                                        dt, use_g, copy);
+                                        dt, use_g, copy, flag, Fp, nF);
     else if (masks)
         finalize_kernel<T, false, true>(pairs, grid, gp, st, g, slot, G, tilemask, u0, ustar, f,
-                                        dt, use_g, copy);
+                                        dt, use_g, copy, flag, Fp, nF);
     else
         finalize_kernel<T, false, false>(pairs, grid, gp, st, g, slot, G, tilemask, u0, ustar, f,
-                                         dt, use_g, copy);
+                                         dt, use_g, copy, flag, Fp, nF);
 }
 
 template <typename T>
@@ -1072,8 +1115,12 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
     IBX_PROF_BEGIN(PK_SPREAD_FINAL);
     launch_spread<T, P>(cfg, st, g, w, b, 1);
     IBX_PROF_END();
+    // without residuals or force history, the finalize writes the last
+    // outputs (F is written before it) and checks the flags itself
+    const bool fold = !resid && !Fhist;
     IBX_PROF_BEGIN(PK_FILL);
-    launch_finalize<T>(gfin, st, g, w.slot, w.G, w.tmask, u0, ustar, f, dt, 1, f_acc, cfg.masks);
+    launch_finalize<T>(gfin, st, g, w.slot, w.G, w.tmask, u0, ustar, f, dt, 1, f_acc, cfg.masks,
+                       fold ? b->flag : nullptr, F, 3 * nl);
     IBX_PROF_END();
     if (resid) {
         IBX_PROF_BEGIN(PK_RESID);
@@ -1082,7 +1129,8 @@ static int run_batched(const Grid& g, const BatchedCfg& cfg, const ib_particles*
         IBX_PROF_END();
         sum_to(w.e2, nl, w.part, resid + ns, true, st);
     }
-    poison_outputs(g, b, ustar, f, F, resid, Fhist, nl, ns, st);
+    if (!fold)
+        poison_outputs(g, b, ustar, f, F, resid, Fhist, nl, ns, st);
     return launch_status();
 }
 
