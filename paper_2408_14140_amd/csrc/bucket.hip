@@ -520,14 +520,24 @@ __device__ inline uint32_t dir_set(int code)
 // direction code: per axis the owning tile's layer alone, with the layer
 // below, or with the layer above -- the owning cell is always in the stencil,
 // and with 3 or more tiles on the axis the P cells reach one neighbour layer
-// at most).
+// at most).  Without dmask a marker whose stencil leaves the coverage adds 1
+// to flag[0]; with it, such a marker sets bit 31 of its dmask entry (for
+// k_dir_counts to count), and this kernel clears the two flags and
+// ztot[0 .. nz) first (nothing raises them before k_dir_counts).
 template <int P>
 __global__ void k_bucket_keys(Grid g, int64_t nl, const double* __restrict__ x,
                               const double* __restrict__ y, const double* __restrict__ z,
                               int32_t* cell, int32_t* tileid, int32_t* base, int32_t* keys,
-                              int32_t* vals, int32_t* flag, int kb, uint32_t* dmask)
+                              int32_t* vals, int32_t* flag, int kb, uint32_t* dmask, int64_t nz,
+                              int32_t* __restrict__ ztot)
 {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (dmask) {
+        if (l < 2)
+            flag[l] = 0;
+        for (int64_t i = l; i < nz; i += (int64_t)gridDim.x * blockDim.x)
+            ztot[i] = 0;
+    }
     if (l >= nl)
         return;
     const double X[3] = {x[l], y[l], z[l]};
@@ -595,13 +605,13 @@ __global__ void k_bucket_keys(Grid g, int64_t nl, const double* __restrict__ x,
     if (kb > 0)
         key |= tcount << kb;
     if (dmask)
-        dmask[l] = dir_set(code);
+        dmask[l] = dir_set(code) | (bad ? 1u << 31 : 0u);
     keys[l] = key;
     vals[l] = (int32_t)l;
     base[3 * l + 0] = b[0];
     base[3 * l + 1] = b[1];
     base[3 * l + 2] = b[2];
-    if (bad)
+    if (bad && !dmask)
         atomicAdd(&flag[0], 1);
 }
 
@@ -651,13 +661,15 @@ __global__ void k_src_emit(Grid g, int64_t nl, const int32_t* perm, const int32_
 }
 
 // cnt[t'][d]: markers owned by tile t' whose stencil touches tile t' + d;
-// tot[t' + d] += that count.  One wavefront per owning tile.
+// tot[t' + d] += that count.  One wavefront per owning tile.  flag[0] counts
+// the markers whose dmask entry has bit 31 (stencil leaving the coverage).
 __global__ void __launch_bounds__(64)
 k_dir_counts(Grid g, int64_t T, const int32_t* __restrict__ tile_offs,
              const int32_t* __restrict__ perm, const uint32_t* __restrict__ dmask,
-             int32_t* __restrict__ cnt, int32_t* __restrict__ tot)
+             int32_t* __restrict__ cnt, int32_t* __restrict__ tot, int32_t* __restrict__ flag)
 {
     const int lane = threadIdx.x;
+    int nbad = 0;
     for (int64_t t = blockIdx.x; t < T; t += gridDim.x) {
         const int s0 = tile_offs[t], s1 = tile_offs[t + 1];
         int mine = 0;                  // lane d < 27: count of direction d
@@ -669,6 +681,7 @@ k_dir_counts(Grid g, int64_t T, const int32_t* __restrict__ tile_offs,
                 if (lane == d)
                     mine += c;
             }
+            nbad += __popcll(__ballot(m >> 31));
         }
         if (lane < NDIR) {
             cnt[t * NDIR + lane] = mine;
@@ -679,6 +692,8 @@ k_dir_counts(Grid g, int64_t T, const int32_t* __restrict__ tile_offs,
             }
         }
     }
+    if (lane == 0 && nbad)
+        atomicAdd(&flag[0], nbad);
 }
 
 // In place: cnt[t'][d] becomes the first position of that run in src_idx
@@ -853,8 +868,10 @@ extern "C" int ib_bucket(const ib_level* lv, const ib_markers* m, ib_delta delta
         return IB_EWORKSPACE;
     w = carve_bucket_ws(ws, ws_bytes, nl, cap, dir ? T : 0, &need);
 
-    const int64_t nz = dir && nl > 0 ? T : 0;                // the list totals, when used
-    k_init_flags<<<(unsigned)(nz > 0 ? (nz + 255) / 256 : 1), 256, 0, st>>>(b->flag, nz, w.dtot);
+    // the flags (and, for lists by direction, their totals) start cleared:
+    // here, or with lists by direction in the key kernel
+    if (nl == 0 || !dir)
+        k_init_flags<<<1, 256, 0, st>>>(b->flag, 0, w.dtot);
     if (nl == 0) {
         lower_bounds(w.keys, 0, nullptr, b->tile_offs, T, st);
         lower_bounds(w.keys, 0, nullptr, b->src_offs, T, st);
@@ -864,20 +881,22 @@ extern "C" int ib_bucket(const ib_level* lv, const ib_markers* m, ib_delta delta
     const int bits = key_bits(T);
     const int passes = (bits + 7) / 8;
     const int kb = 8 * passes + 4 <= 31 ? 8 * passes : 0;   // 4 count bits above the digits
+    const int64_t nz = dir ? T : 0;      // the list totals, when used
     if (delta == IB_DELTA3)
         k_bucket_keys<3><<<gb, 256, 0, st>>>(g, nl, m->x, m->y, m->z, b->cell, b->tileid,
                                              b->base, w.keys, b->perm, b->flag, kb,
-                                             dir ? w.dmask : nullptr);
+                                             dir ? w.dmask : nullptr, nz, w.dtot);
     else
         k_bucket_keys<4><<<gb, 256, 0, st>>>(g, nl, m->x, m->y, m->z, b->cell, b->tileid,
                                              b->base, w.keys, b->perm, b->flag, kb,
-                                             dir ? w.dmask : nullptr);
+                                             dir ? w.dmask : nullptr, nz, w.dtot);
     radix_sort_pairs(w.keys, b->perm, w.tk, w.tv, nl, nullptr, bits, w.rs, st);
     lower_bounds(w.keys, nl, nullptr, b->tile_offs, T, st, kb > 0 ? (1 << kb) - 1 : -1);
 
     if (dir) {
         const unsigned gw = (unsigned)(T < 16384 ? T : 16384);
-        k_dir_counts<<<gw, 64, 0, st>>>(g, T, b->tile_offs, b->perm, w.dmask, w.dcnt, w.dtot);
+        k_dir_counts<<<gw, 64, 0, st>>>(g, T, b->tile_offs, b->perm, w.dmask, w.dcnt, w.dtot,
+                                        b->flag);
         scan_exclusive(w.dtot, b->src_offs, T, b->src_offs + T, w.dscan, st);
         k_dir_offsets<<<(unsigned)((T + 4) / 4), 256, 0, st>>>(g, T, w.dcnt, b->src_offs,
                                                               w.dtot, cap, b->flag);
