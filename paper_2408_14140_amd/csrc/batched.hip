@@ -267,6 +267,23 @@ __device__ inline int item_markers(const int32_t* __restrict__ tile_offs, int64_
     return (tx + 1 < nt0 ? tile_offs[t + 2] : tile_offs[t + 1]) - s;
 }
 
+// The interpolation items of work tile t, from its first item io on.
+template <bool PAIR>
+__device__ inline void write_items(int64_t t, int io, int bw, int nt0,
+                                   const int32_t* __restrict__ tile_offs, Item* items)
+{
+    int start;
+    const int cnt = item_markers<PAIR>(tile_offs, t, nt0, &start);
+    for (int k = 0; k * bw < cnt; ++k) {
+        Item it;
+        it.tile = (int32_t)t;
+        it.start = start + k * bw;
+        it.count = min(bw, cnt - k * bw);
+        it.pad = 0;
+        items[io + k] = it;
+    }
+}
+
 // Block blk of 256 threads (block 0 also clears the cost histogram that
 // k_cost_hist fills next).
 template <bool PAIR>
@@ -287,10 +304,14 @@ __device__ inline void tile_counts_block(unsigned blk, int64_t T, int bw, int nt
     act[t] = src_offs[t + 1] > src_offs[t] ? 1 : 0;
 }
 
-// hist[x][b]: active tiles of slab x in cost bin b (zeroed beforehand).
+// hist[x][b]: active tiles of slab x in cost bin b (zeroed beforehand); and
+// the interpolation items of every work tile.
+template <bool PAIR>
 __global__ void __launch_bounds__(256)
 k_cost_hist(int64_t T, const int32_t* __restrict__ src_offs, const int32_t* __restrict__ act_offs,
-            const int32_t* __restrict__ nactive, int32_t* __restrict__ hist)
+            const int32_t* __restrict__ nactive, int32_t* __restrict__ hist, int bw, int nt0,
+            const int32_t* __restrict__ tile_offs, const int32_t* __restrict__ item_offs,
+            Item* items)
 {
     __shared__ int32_t lh[NXCD * COST_BINS];
     for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
@@ -302,6 +323,7 @@ k_cost_hist(int64_t T, const int32_t* __restrict__ src_offs, const int32_t* __re
         const int c = src_offs[t + 1] - src_offs[t];
         if (c > 0)
             atomicAdd(&lh[slab_of(act_offs[t], n_act) * COST_BINS + min(c, COST_BINS - 1)], 1);
+        write_items<PAIR>(t, item_offs[t], bw, nt0, tile_offs, items);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
@@ -367,12 +389,15 @@ __device__ inline void list_scan_block(unsigned id, int64_t T, int bw, int nt0,
 // Pass 2: each workgroup adds the totals of the scan tiles before its own
 // (for the flags, less the item total), the last one of each array writes its
 // total (nitems, nactive), and the flag workgroups count their spreading
-// tiles into the cost histogram (as k_cost_hist does).
+// tiles into the cost histogram (as k_cost_hist does); the item workgroups
+// also write the interpolation items of their work tiles.
+template <bool PAIR>
 __global__ void __launch_bounds__(SCAN_THREADS)
 k_list_add(int64_t T, const int32_t* __restrict__ src_offs, int32_t* __restrict__ item_offs,
            int32_t* __restrict__ act_offs, const int32_t* __restrict__ sums,
            int32_t* __restrict__ nitems, int32_t* __restrict__ nactive,
-           int32_t* __restrict__ hist)
+           int32_t* __restrict__ hist, int bw, int nt0, const int32_t* __restrict__ tile_offs,
+           Item* items)
 {
     __shared__ int32_t lh[NXCD * COST_BINS];
     const int64_t nb = (T + SCAN_TILE - 1) / SCAN_TILE;
@@ -392,8 +417,11 @@ k_list_add(int64_t T, const int32_t* __restrict__ src_offs, int32_t* __restrict_
     }
     if (!second) {
         for (int k = threadIdx.x; k < SCAN_TILE; k += blockDim.x)
-            if (base + k < T)
-                out[base + k] += add;
+            if (base + k < T) {
+                const int io = out[base + k] + add;
+                out[base + k] = io;
+                write_items<PAIR>(base + k, io, bw, nt0, tile_offs, items);
+            }
         return;
     }
     for (int b = threadIdx.x; b < NXCD * COST_BINS; b += blockDim.x)
@@ -444,13 +472,14 @@ k_prep_lists(unsigned nlist, Grid g, int64_t nl, const double* __restrict__ x,
                                 out_items, out_act, hist);
 }
 
-// cur[x][b] = first position of slab x plus its tiles in bins above b.
-__global__ void __launch_bounds__(COST_BINS)
-k_bin_scan(const int32_t* __restrict__ hist, const int32_t* __restrict__ nactive,
-           int32_t* __restrict__ cur)
+// cur[x][b] = first position of slab x plus its tiles in bins above b (slab
+// x = blk, thread b of COST_BINS).
+__device__ inline void bin_scan_block(unsigned blk, const int32_t* __restrict__ hist,
+                                      const int32_t* __restrict__ nactive,
+                                      int32_t* __restrict__ cur)
 {
     __shared__ int32_t v[COST_BINS];
-    const int b = threadIdx.x, x = blockIdx.x;
+    const int b = threadIdx.x, x = (int)blk;
     const int per = (*nactive + NXCD - 1) / NXCD;
     const int32_t* h = hist + x * COST_BINS;
     v[b] = h[COST_BINS - 1 - b];
@@ -465,17 +494,41 @@ k_bin_scan(const int32_t* __restrict__ hist, const int32_t* __restrict__ nactive
     cur[x * COST_BINS + COST_BINS - 1 - b] = x * per + v[b] - h[COST_BINS - 1 - b];
 }
 
-// Work lists: interpolation items in tile order, the G slot of every tile
-// (-1 when its source list is empty), and the spreading entries (slot, tile,
-// source range) in spreading order (cur[x][b] holds the first free position
-// of bin b of slab x).
+// The cost-bin scan and the items' neighbour offsets, which do not depend on
+// each other, in one launch of COST_BINS-thread blocks: blocks below NXCD
+// scan the bins of one slab each, the others take one (item, neighbour)
+// each ([it][9 NBX] into nb_u and nb_g; the items are written by then).
 template <bool PAIR>
+__global__ void __launch_bounds__(COST_BINS)
+k_bins_bases(const int32_t* __restrict__ hist, const int32_t* __restrict__ nactive,
+             int32_t* __restrict__ cur, Grid g, const Item* __restrict__ items,
+             const int32_t* __restrict__ nitems, const int32_t* __restrict__ src_offs,
+             const int32_t* __restrict__ act_offs, int64_t* __restrict__ nb_u,
+             int64_t* __restrict__ nb_g)
+{
+    static_assert(COST_BINS == 256, "one block size for both parts");
+    if (blockIdx.x < NXCD) {
+        bin_scan_block(blockIdx.x, hist, nactive, cur);
+        return;
+    }
+    constexpr int NBX = PAIR ? 4 : 3, NNB = 9 * NBX;
+    const int64_t q = (int64_t)(blockIdx.x - NXCD) * COST_BINS + threadIdx.x;
+    const int64_t it = q / NNB;
+    if (it >= *nitems)
+        return;
+    int64_t bu, bg;
+    item_base<NBX>(g, items[it].tile, (int)(q - it * NNB), src_offs, act_offs, &bu, &bg);
+    nb_u[q] = bu;
+    nb_g[q] = bg;
+}
+
+// Work lists: the G slot of every tile (-1 when its source list is empty),
+// and the spreading entries (slot, tile, source range) in spreading order
+// (cur[x][b] holds the first free position of bin b of slab x).
 __global__ void __launch_bounds__(256)
-k_fill_lists(int64_t T, int bw, int nt0, const int32_t* __restrict__ tile_offs,
-             const int32_t* __restrict__ src_offs, const int32_t* __restrict__ item_offs,
+k_fill_lists(int64_t T, const int32_t* __restrict__ src_offs,
              const int32_t* __restrict__ act_offs, const int32_t* __restrict__ nactive,
-             Item* items, int32_t* slot, int32_t* __restrict__ cur,
-             int4* __restrict__ sent)
+             int32_t* slot, int32_t* __restrict__ cur, int4* __restrict__ sent)
 {
     __shared__ int32_t lc[NXCD * COST_BINS];
     __shared__ int32_t base[NXCD * COST_BINS];
@@ -486,17 +539,6 @@ k_fill_lists(int64_t T, int bw, int nt0, const int32_t* __restrict__ tile_offs,
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int bin = -1, rank = 0, s0 = 0, s1 = 0;
     if (t < T) {
-        int start;
-        const int cnt = item_markers<PAIR>(tile_offs, t, nt0, &start);
-        const int io = item_offs[t];
-        for (int k = 0; k * bw < cnt; ++k) {
-            Item it;
-            it.tile = (int32_t)t;
-            it.start = start + k * bw;
-            it.count = min(bw, cnt - k * bw);
-            it.pad = 0;
-            items[io + k] = it;
-        }
         s0 = src_offs[t];
         s1 = src_offs[t + 1];
         const int c = s1 - s0;
@@ -983,21 +1025,22 @@ static void build_lists(const Grid& g, const BatchedCfg& cfg, const ib_buckets* 
     const int64_t nbl = (T_ + SCAN_TILE - 1) / SCAN_TILE;
     if (fused_list_scan(g)) {
         int32_t* sums = (int32_t*)w.scan;
-        k_list_add<<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
-            T_, b->src_offs, w.item_offs, w.act_offs, sums, w.nitems, w.nactive, w.hist);
+        k_list_add<PAIR><<<(unsigned)(2 * nbl), SCAN_THREADS, 0, st>>>(
+            T_, b->src_offs, w.item_offs, w.act_offs, sums, w.nitems, w.nactive, w.hist, cfg.bw,
+            g.nt[0], b->tile_offs, w.items);
     } else {
         scan_exclusive2(w.item_cnt, w.item_offs, w.act, w.act_offs, T_, w.nitems, w.nactive,
                         w.scan, st);
-        k_cost_hist<<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.hist);
+        k_cost_hist<PAIR><<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.hist,
+                                              cfg.bw, g.nt[0], b->tile_offs, w.item_offs,
+                                              w.items);
     }
-    k_bin_scan<<<NXCD, COST_BINS, 0, st>>>(w.hist, w.nactive, w.cur);
-    k_fill_lists<PAIR><<<gt, 256, 0, st>>>(T_, cfg.bw, g.nt[0], b->tile_offs, b->src_offs,
-                                           w.item_offs, w.act_offs, w.nactive, w.items, w.slot,
-                                           w.cur, w.sent);
     constexpr int NBX = PAIR ? 4 : 3;
     const int64_t nth = 9 * NBX * w.max_items;
-    k_item_bases<NBX><<<(unsigned)((nth + 255) / 256), 256, 0, st>>>(g, w.items, w.nitems,
-                                                                     w.slot, w.nb_u, w.nb_g);
+    k_bins_bases<PAIR><<<(unsigned)(NXCD + (nth + COST_BINS - 1) / COST_BINS), COST_BINS, 0, st>>>(
+        w.hist, w.nactive, w.cur, g, w.items, w.nitems, b->src_offs, w.act_offs, w.nb_u, w.nb_g);
+    k_fill_lists<<<gt, 256, 0, st>>>(T_, b->src_offs, w.act_offs, w.nactive, w.slot, w.cur,
+                                     w.sent);
 }
 
 // Marker records in bucket order and the work lists of the tile kernels

@@ -5,7 +5,7 @@
 // Interpolation (one work item = up to BW markers of one 8^3 tile, BW
 // threads): the tile plus a ceil(P/2)-cell halo of the field is staged into
 // three LDS planes.  For every item the element offsets of the 27 tiles
-// around it are precomputed once per loop (k_item_bases), so a halo cell's
+// around it are precomputed once per loop (item_base), so a halo cell's
 // address is base[(j-g+8)>>3 per axis] + its position in that tile.  Items
 // with few markers spread each marker over 2 or 4 lanes (one z plane of the
 // stencil each), so all waves of the workgroup share the compute phase.
@@ -47,24 +47,17 @@ __device__ inline Slab xcd_slab(int n)
     return r;
 }
 
-// Element offsets of the 9 NBX tiles around every interpolation item (NBX
+// Element offsets of the 9 NBX tiles around an interpolation item (NBX
 // along x: the work tile's own TXW / 8 tiles and one on each side; 3 along y
-// and z): [it][9 NBX] for the velocity field (box layout) and for the
-// per-tile force buffer.  -1 where the tile lies outside a bounded axis, in
-// an uncovered box, or has no force slot.
+// and z), for an item of work tile t and neighbour k < 9 NBX: *bu in the
+// velocity field (box layout), *bg in the per-tile force buffer.  -1 where
+// the tile lies outside a bounded axis, in an uncovered box, or has no force
+// slot (a tile has one when its source list is not empty: slot act_offs[tile]).
 template <int NBX>
-__global__ void k_item_bases(Grid g, const Item* __restrict__ items,
-                             const int32_t* __restrict__ nitems, const int32_t* __restrict__ slot,
-                             int64_t* __restrict__ nb_u, int64_t* __restrict__ nb_g)
+__device__ inline void item_base(const Grid& g, int t, int k, const int32_t* __restrict__ src_offs,
+                                 const int32_t* __restrict__ act_offs, int64_t* bu, int64_t* bg)
 {
-    constexpr int NNB = 9 * NBX;
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t it = q / NNB;
-    if (it >= *nitems)
-        return;
-    const int k = (int)(q - it * NNB);
     int lo[3];
-    const int t = items[it].tile;
     lo[0] = (t % g.nt[0]) * TILE;
     lo[1] = ((t / g.nt[0]) % g.nt[1]) * TILE;
     lo[2] = (t / (g.nt[0] * g.nt[1])) * TILE;
@@ -80,14 +73,13 @@ __global__ void k_item_bases(Grid g, const Item* __restrict__ items,
         }
         c[a] = v;
     }
-    int64_t bu = -1, bg = -1;
+    *bu = *bg = -1;
     if (ok) {
-        bu = cell_offset(g, c[0], c[1], c[2]);
-        const int sl = slot[(c[0] >> 3) + g.nt[0] * ((c[1] >> 3) + g.nt[1] * (c[2] >> 3))];
-        bg = sl >= 0 ? (int64_t)sl * 3 * TILE_CELLS : -1;
+        *bu = cell_offset(g, c[0], c[1], c[2]);
+        const int tn = (c[0] >> 3) + g.nt[0] * ((c[1] >> 3) + g.nt[1] * (c[2] >> 3));
+        if (src_offs[tn + 1] > src_offs[tn])
+            *bg = (int64_t)act_offs[tn] * 3 * TILE_CELLS;
     }
-    nb_u[q] = bu;
-    nb_g[q] = bg;
 }
 
 // mode 0: field = u0 (box layout): D = (U^d - J u0)/dt, F = D.
